@@ -1,0 +1,177 @@
+"""Benchmark of the RTW far-field hot path on one MI355X.
+
+Workload (the ellipsoid workload of the benchmark configuration): ellipsoid
+with semi-axes 60/50/40 um, Z-Y-Z Euler angles (30, 20, 10) deg, m = 1.333,
+lambda = 0.6328 um, orders p = 0..3, a 2048 x 2048 incident ray grid, far field
+on 1801 x 720 (theta, phi) nodes (0.1 x 0.5 deg), x and y polarisations.
+
+One step = one rtw_farfield call (trace every ray, rasterise every order,
+ordered per-node sum) with all inputs resident in HBM.  The metric is active
+incident rays per second of the mixed-precision path; the plain FP64 path is
+timed on the same workload beside it.  Per-kernel durations are measured live
+with HIP events on the library's stream (rtw_profile_*).  The CPU baseline is
+the FP64 oracle on the full workload, timed on the host cores.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point work (adds, multiplies, divides, square roots and
+# elementary functions counted once each, an FMA as two), per unit:
+#   trace: per active ray, p = 0..3 (4 interactions, 3 propagations, 4 emissions)
+#   raster: per valid triangle set-up, per candidate node test, per node hit (2 polarisations)
+#   node sum: per hit accumulated (8 components)
+FLOP_TRACE_PER_RAY = 4 * 183 + 3 * 130 + 4 * 250 + 40
+FLOP_RASTER_PER_TRIANGLE = 110
+FLOP_RASTER_PER_CANDIDATE = 55
+FLOP_RASTER_PER_HIT = 320
+PEAK_VALU_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published, packed-math figure)
+PEAK_VALU_FP64_TFLOPS = 78.6   # MI355X vector FP64
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def active_rays(rtw, w, grid_n):
+    """Incident rays that meet the particle (rays that emit order 0)."""
+    import torch
+    part = rtw.make_particle(w.semi_axes, w.euler_deg, w.m)
+    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1), rtw.make_opts(0, 0, grid_n, rtw.FP64))
+    n = int((rec["flags"][0] & 1).sum().item())
+    del rec
+    torch.cuda.empty_cache()
+    return n
+
+
+def time_path(rtw, w, grid_n, precision, steps, warmup):
+    import torch
+    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m), rtw.make_incident(w.wavelength, w.n_pol),
+                      rtw.make_opts(w.p_min, w.p_max, grid_n, precision), w.theta_deg, w.phi_deg)
+    ff()  # sizes the workspace (grows it if the hit pool overflowed)
+    for _ in range(warmup):
+        ff.launch(with_counts=False)
+    torch.cuda.synchronize()
+    rtw.profile_read()  # drop anything recorded before the timed region
+    rtw.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ff.launch(with_counts=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rtw.profile_enable(False)
+    prof = rtw.profile_read()
+    rc, _ = ff.status()
+    if rc != rtw.RTW_OK:
+        raise RuntimeError("hit pool overflowed during the timed steps")
+    hits, fp64_rays = ff.stats()
+    ms = (t1 - t0) * 1e3 / steps
+    del ff
+    torch.cuda.empty_cache()
+    return ms, prof, hits, fp64_rays
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--grid-n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run would shard the ray grid "
+              f"by rows and reduce the node field once, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_13856_amd import inputs, rtw
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    rtw.load()
+    w = inputs.ellipsoid_mixed(args.grid_n)
+    n_active = active_rays(rtw, w, args.grid_n)
+    log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "
+        f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}")
+
+    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup)
+    log(f"[bench] mixed: {ms_mixed:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
+    for k, (t, n) in sorted(prof_mixed.items(), key=lambda kv: -kv[1][0]):
+        log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
+    fp64 = None
+    if not args.no_fp64:
+        ms64, prof64, hits64, _ = time_path(rtw, w, args.grid_n, rtw.FP64, max(2, args.steps // 2),
+                                            max(1, args.warmup // 2))
+        log(f"[bench] fp64: {ms64:.3f} ms/step")
+        for k, (t, n) in sorted(prof64.items(), key=lambda kv: -kv[1][0]):
+            log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
+        fp64 = dict(ms_per_step=round(ms64, 4), rays_per_s=n_active / (ms64 * 1e-3),
+                    kernels_ms={k: round(t / n, 5) for k, (t, n) in prof64.items()})
+
+    value = n_active / (ms_mixed * 1e-3)
+    # roofline of the dominant kernel (ALU-bound: plain VALU arithmetic)
+    dom, (tot, cnt) = max(prof_mixed.items(), key=lambda kv: kv[1][0])
+    avg_s = tot / cnt * 1e-3
+    n_ord = w.p_max - w.p_min + 1
+    if dom.startswith("k_trace"):
+        flops = FLOP_TRACE_PER_RAY * n_active
+    elif dom.startswith("k_raster"):
+        flops = (FLOP_RASTER_PER_TRIANGLE * 2 * n_active * n_ord + FLOP_RASTER_PER_HIT * hits)
+    else:
+        flops = 8 * hits
+    achieved = flops / avg_s / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 4), traffic=None, kernel=dom,
+                    kernel_ms=round(avg_s * 1e3, 4))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.farfield(oracle.particle(w.semi_axes, w.euler_deg, w.m),
+                        oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n), w.theta_deg, w.phi_deg)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
+                   sample=f"full workload ({args.grid_n}^2 rays, all {w.n_nodes} nodes), one run, {dt:.1f} s")
+        log(f"[bench] cpu oracle: {dt:.1f} s on {oracle.get_threads()} threads")
+
+    out = {
+        "metric": "rays/s (p<=3) mixed vs FP64 at 1e-4 rel",
+        "value": round(value, 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_mixed, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"ellipsoid 60/50/40 um, Euler (30,20,10) deg, m=1.333, lambda=0.6328 um, "
+                               f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed",
+                   "active_rays": n_active, "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
+                   "far_field_points_per_s": round(w.n_nodes * w.n_pol / (ms_mixed * 1e-3), 1),
+                   "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},
+        "fp64_path": fp64,
+        "speedup_mixed_over_fp64": round(fp64["ms_per_step"] / ms_mixed, 3) if fp64 else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

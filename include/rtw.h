@@ -1,0 +1,162 @@
+/*
+ * rtw.h -- C ABI of the MI355X-native Ray Theory of Waves library (librtw.so).
+ *
+ * Method: Ren et al., "Ray Theory of Waves" (arXiv 2403.13856).  A plane wave
+ * travelling along lab +z meets one smooth ellipsoid.  A cell-centred square
+ * grid of incident rays is traced; every ray carries a 2x2 wavefront-curvature
+ * (WFC) matrix updated at each reflection and refraction by the wavefront
+ * equation (Eq. 3), its direction by vector Snell (Eq. 4) and its
+ * polarisation by the Fresnel coefficients (Eq. 8) re-evaluated in each
+ * incidence plane.  Each order p leaves the particle with the amplitude of
+ * Eqs. 5-7 (divergence factor from the WFC) and the phase of Eqs. 9-10 (path,
+ * Fresnel and focal-line phases).  The far field on a (theta, phi) grid is the
+ * coherent sum of all orders, obtained by interpolating the per-ray fields as
+ * functions of the incident ray (section "Strategy of Ray Theory of Waves").
+ *
+ * Conventions
+ *   - lengths in micrometres; angles in degrees at this interface;
+ *   - lab frame: incident wave along +z, incident polarisation x (pol 0) and
+ *     y (pol 1); theta is measured from +z, phi from +x towards +y;
+ *   - body frame: x_lab = R x_body, R = Rz(alpha) Ry(beta) Rz(gamma);
+ *   - time dependence exp(-i w t); the far field F(theta, phi) is
+ *     lim r exp(-ikr) E(r) / E0, in micrometres, projected on (e_theta, e_phi);
+ *     |F|^2 is the differential cross-section (um^2/sr) of the summed orders;
+ *   - ray grid: N x N cell-centred over [-L, L]^2, L = max(sqrt(S_xx),
+ *     sqrt(S_yy)), S = R diag(a^2, b^2, c^2) R^T; ray index iy*N + ix;
+ *   - every device pointer is caller-owned; the library never allocates or
+ *     frees caller memory.  All calls are asynchronous on the given HIP stream
+ *     (NULL = default stream); argument errors are returned immediately.
+ *
+ * Return codes: 0 = RTW_OK, negative = error; rtw_last_error() returns the
+ * calling thread's message for the last failing call.
+ */
+#ifndef RTW_H
+#define RTW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTW_OK 0
+#define RTW_ERR_INVALID_ARG (-1)
+#define RTW_ERR_UNSUPPORTED (-2)
+#define RTW_ERR_WORKSPACE (-3)
+#define RTW_ERR_DEVICE (-4)
+
+#define RTW_FP64 0  /* every step in double precision */
+#define RTW_MIXED 1 /* FP32 geometry, Fresnel and WFC; FP64 positions, path length,
+                       phase reduction, divergence factor and caustic Jacobian */
+
+#define RTW_MAX_ORDER 15
+
+/* One ellipsoid r^T diag(a^-2, b^-2, c^-2) r = 1 in its body frame. */
+typedef struct {
+  double semi_axes[3]; /* a, b, c > 0 (um) */
+  double euler_deg[3]; /* Z-Y-Z Euler angles (deg), body -> lab */
+  double m;            /* real relative refractive index, m > 0, m != 1 */
+} rtw_particle;
+
+/* Incident plane wave along lab +z (the paper's problem statement: wavelength
+ * and polarisation of the incident wave). */
+typedef struct {
+  double wavelength; /* in the surrounding medium (um) */
+  int n_pol;         /* 1: x polarisation only; 2: x and y */
+} rtw_incident;
+
+typedef struct {
+  int p_min, p_max; /* orders emitted, 0 <= p_min <= p_max <= RTW_MAX_ORDER */
+  int grid_n;       /* incident rays per side, >= 2 */
+  int precision;    /* RTW_FP64 or RTW_MIXED */
+} rtw_trace_opts;
+
+/* Observation grid: sorted node angles, DEVICE pointers (caller-owned),
+ * theta in [0, 180], phi in [0, 360), both strictly increasing. */
+typedef struct {
+  int n_theta;
+  const double* theta_deg;
+  int n_phi;
+  const double* phi_deg;
+} rtw_grid;
+
+/* Mixed path (RTW_MIXED): a ray whose divergence factor is ill-conditioned in
+ * FP32 -- a focal line within a few per cent of an interface, or an exit
+ * wavefront near flat (a far-field caustic) -- is traced again in FP64 inside
+ * the same kernel; its records then carry FP64-accurate values.
+ *
+ * Per-ray records written by rtw_trace, all DEVICE pointers, FP64 whatever
+ * the precision path (the mixed path converts on store).  o = p - p_min is the
+ * order slot, NN = N*N the ray count.  Any pointer may be NULL (not written).
+ *   flags [n_ord][NN]            bit0 order emitted, bits 1..7 focal lines N_f,
+ *                                bit 8 det Q' < 0 at the exit
+ *   dir   [n_ord][3][NN]         lab exit direction
+ *   rexit [n_ord][3][NN]         lab exit point (um)
+ *   phase [n_ord][NN]            path + focal-line phase, unreduced (rad):
+ *                                OPL - k dir.rexit - N_f pi/2
+ *   amp   [n_ord][NN]            amplitude sqrt(D/|det Q'|) (um)
+ *   field [n_ord][n_pol][3][2][NN]  lab field vector amp e^{i phase}
+ *                                (J_perp e_perp + J_par e_par), (re, im) */
+typedef struct {
+  int32_t* flags;
+  double* dir;
+  double* rexit;
+  double* phase;
+  double* amp;
+  double* field;
+} rtw_ray_records;
+
+/* Trace the incident grid and store every emitted order (Eqs. 3-10).
+ * Errors: RTW_ERR_INVALID_ARG (bad sizes, NULL structs), RTW_ERR_UNSUPPORTED
+ * (m == 1, p_max > 15), RTW_ERR_DEVICE (launch failure). */
+int rtw_trace(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
+              const rtw_ray_records* out, void* hip_stream);
+
+/* Bytes of device workspace rtw_farfield needs for these arguments, with room
+ * for hits_per_node contributions per node on average (0 = library default). */
+int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
+                                const rtw_grid* grid, double hits_per_node, size_t* bytes);
+
+/* Far field of the summed orders p_min..p_max on the node grid (interpolation
+ * of the RTW strategy section, coherent sum over orders and branches).
+ *   out_field  DEVICE, [n_pol][2 (theta, phi)][n_theta][n_phi] complex,
+ *              interleaved (re, im): double for RTW_FP64, float for RTW_MIXED.
+ *   ncontrib   DEVICE int32 [n_theta*n_phi] or NULL: triangle contributions per node.
+ *   workspace  DEVICE, >= rtw_farfield_workspace_size bytes, 256-byte aligned.
+ * The per-node sum is taken in a fixed order (deterministic).  If the hit pool
+ * in the workspace overflows, the result is incomplete and
+ * rtw_farfield_status() reports RTW_ERR_WORKSPACE with the size needed. */
+int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
+                 const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* workspace,
+                 size_t workspace_bytes, void* hip_stream);
+
+/* Synchronises hip_stream and reports whether the last rtw_farfield that used
+ * this workspace fitted: RTW_OK, or RTW_ERR_WORKSPACE with *bytes_needed set to
+ * a workspace size that fits.  bytes_needed may be NULL. */
+int rtw_farfield_status(const void* workspace, void* hip_stream, size_t* bytes_needed);
+
+/* Synchronises hip_stream and reads counters of the last rtw_farfield that used
+ * this workspace: the number of node contributions (triangle hits) and, for
+ * RTW_MIXED, the number of rays traced again in FP64 because their divergence
+ * factor was ill-conditioned in FP32.  Either pointer may be NULL. */
+int rtw_farfield_stats(const void* workspace, void* hip_stream, uint64_t* hits, uint64_t* fp64_rays);
+
+/* Per-kernel timing for benchmarks: while enabled, every kernel the library
+ * launches is bracketed by HIP events on the caller's stream.
+ * rtw_profile_read waits for the recorded events and returns, per kernel name,
+ * the summed duration (ms) and launch count: names is a caller buffer of
+ * max_kernels rows of 64 chars; *n_kernels receives the number of distinct
+ * kernels (may exceed max_kernels).  The recorded events are then released. */
+int rtw_profile_enable(int on);
+int rtw_profile_read(int max_kernels, char* names, double* total_ms, int* launches, int* n_kernels);
+
+const char* rtw_last_error(void);
+
+/* Library version string. */
+const char* rtw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

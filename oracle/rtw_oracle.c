@@ -684,11 +684,12 @@ static void unit_centroid(const double* a, const double* b, const double* c, dou
   double s[3] = {a[0] + b[0] + c[0], a[1] + b[1] + c[1], a[2] + b[2] + c[2]};
   scale3(1.0 / norm3(s), s, o);
 }
+/* Angle between two unit vectors from their chord (accurate for tiny angles). */
 static double ang(const double* a, const double* b) {
-  double d = dot3(a, b);
-  if (d > 1.0) d = 1.0;
-  if (d < -1.0) d = -1.0;
-  return acos(d);
+  double df[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+  double h = 0.5 * norm3(df);
+  if (h > 1.0) h = 1.0;
+  return 2.0 * asin(h);
 }
 
 int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_theta, const double* theta_deg,
@@ -804,7 +805,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
           J.nflags = fl_buf;
           J.ncontrib = nc_buf;
           J.n_nodes = n_nodes;
-          for_nodes_in_cap(&nd, cen, rho + 1e-9, tri_node, &J);
+          for_nodes_in_cap(&nd, cen, rho * (1.0 + 1e-9) + 1e-12, tri_node, &J);
         }
       }
   }
