@@ -97,7 +97,12 @@ typedef struct {
  *                                OPL - k dir.rexit - N_f pi/2
  *   amp   [n_ord][NN]            amplitude sqrt(D/|det Q'|) (um)
  *   field [n_ord][n_pol][3][2][NN]  lab field vector amp e^{i phase}
- *                                (J_perp e_perp + J_par e_par), (re, im) */
+ *                                (J_perp e_perp + J_par e_par), (re, im)
+ *   cond  [n_ord][2][NN]         conditioning of the emission: [0] relative-error
+ *                                amplification of the divergence factor (the
+ *                                mixed path re-traces in FP64 above its limit),
+ *                                [1] growth of a direction perturbation along the
+ *                                ray (product of the largest |eig(I + L Q)|) */
 typedef struct {
   int32_t* flags;
   double* dir;
@@ -105,6 +110,7 @@ typedef struct {
   double* phase;
   double* amp;
   double* field;
+  double* cond;
 } rtw_ray_records;
 
 /* Trace the incident grid and store every emitted order (Eqs. 3-10).

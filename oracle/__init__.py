@@ -62,7 +62,7 @@ def lib():
         _lib.rtwo_trace_rays.argtypes = [P(Particle), P(Setup), ctypes.c_int, dp, P(Ray)]
         _lib.rtwo_trace_grid.argtypes = [P(Particle), P(Setup), ip, dp, dp, dp, dp, dp]
         _lib.rtwo_farfield.argtypes = [P(Particle), P(Setup), ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_double,
-                                       dp, dp, ip, ip]
+                                       dp, dp, ip, ip, dp]
         _lib.rtwo_grid_halfwidth.argtypes = [P(Particle)]
         _lib.rtwo_grid_halfwidth.restype = ctypes.c_double
         _lib.rtwo_fresnel.argtypes = [ctypes.c_double, ctypes.c_double, dp]
@@ -155,13 +155,14 @@ def farfield(part, st, theta_deg, phi_deg, band_deg=0.1):
     incoh = np.zeros(nt * nphi)
     nflags = np.zeros(nt * nphi, np.int32)
     ncon = np.zeros(nt * nphi, np.int32)
+    unc = np.zeros(nt * nphi)
     rc = lib().rtwo_farfield(ctypes.byref(part), ctypes.byref(st), nt, _dp(th), nphi, _dp(ph), float(band_deg),
-                             _dp(field), _dp(incoh), _ip(nflags), _ip(ncon))
+                             _dp(field), _dp(incoh), _ip(nflags), _ip(ncon), _dp(unc))
     if rc != 0:
         raise ValueError("rtwo_farfield rejected its arguments")
     F = field[..., 0] + 1j * field[..., 1]
     return dict(field=F, incoh=incoh.reshape(nt, nphi), flags=nflags.reshape(nt, nphi),
-                ncontrib=ncon.reshape(nt, nphi))
+                ncontrib=ncon.reshape(nt, nphi), uncancelled=unc.reshape(nt, nphi))
 
 
 def ray_emit(ray, p):

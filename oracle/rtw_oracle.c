@@ -620,6 +620,7 @@ typedef struct {
   double* incoh;
   int* nflags;
   int* ncontrib;
+  double* uncancelled;
   long n_nodes;
 } tri_job;
 
@@ -659,6 +660,7 @@ static void tri_node(int node, void* user) {
   const double* ep = &J->nd->ephi[3 * (long)node];
   for (int p = 0; p < J->n_pol; p++) {
     cplx ft = 0, fp = 0;
+    double ut = 0, up = 0; /* magnitudes of the summed terms (before cancellation) */
     for (int k = 0; k < 3; k++) {
       const cray* v = J->v[k];
       double dn[3] = {n[0] - v->dir[0], n[1] - v->dir[1], n[2] - v->dir[2]};
@@ -667,7 +669,10 @@ static void tri_node(int node, void* user) {
       for (int x = 0; x < 3; x++) { vt += v->f[p][x] * et[x]; vp += v->f[p][x] * ep[x]; }
       ft += lam[k] * carry * vt;
       fp += lam[k] * carry * vp;
+      ut += fabs(lam[k]) * cabs(vt);
+      up += fabs(lam[k]) * cabs(vp);
     }
+    if (J->uncancelled) J->uncancelled[node] += ut * ut + up * up;
     long base_t = ((long)(p * 2 + 0) * J->n_nodes + node) * 2;
     long base_p = ((long)(p * 2 + 1) * J->n_nodes + node) * 2;
     J->field[base_t] += creal(ft); J->field[base_t + 1] += cimag(ft);
@@ -694,7 +699,7 @@ static double ang(const double* a, const double* b) {
 
 int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_theta, const double* theta_deg,
                   int n_phi, const double* phi_deg, double band_deg, double* field, double* incoh, int* nflags,
-                  int* ncontrib) {
+                  int* ncontrib, double* uncancelled) {
   ctx_t c;
   if (setup_ctx(part, setup, &c) != 0 || setup->grid_n < 2 || n_theta < 1 || n_phi < 1 || !theta_deg ||
       !phi_deg || !field)
@@ -734,6 +739,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
   memset(inc_buf, 0, sizeof(double) * n_nodes);
   memset(fl_buf, 0, sizeof(int) * n_nodes);
   memset(nc_buf, 0, sizeof(int) * n_nodes);
+  if (uncancelled) memset(uncancelled, 0, sizeof(double) * n_nodes);
 
   /* per-ray records of every order */
   cray* rec = malloc(sizeof(cray) * (size_t)n_ord * NN);
@@ -804,6 +810,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
           J.incoh = inc_buf;
           J.nflags = fl_buf;
           J.ncontrib = nc_buf;
+          J.uncancelled = uncancelled;
           J.n_nodes = n_nodes;
           for_nodes_in_cap(&nd, cen, rho * (1.0 + 1e-9) + 1e-12, tri_node, &J);
         }

@@ -97,10 +97,14 @@ int rtwo_trace_grid(const rtwo_particle* part, const rtwo_setup* setup,
  *                           bit1 within band_deg of a dropped fold triangle,
  *                           bit2 within band_deg of theta = 0 or 180
  *   ncontrib[n_theta*n_phi] number of triangle contributions
- * incoh, nflags and ncontrib may be NULL. */
+ *   uncancelled[n_theta*n_phi] sum over contributions of (sum over the three
+ *                           rays of |lambda_v| |F_v|)^2 (pols, comps): the size of
+ *                           the interpolated terms before they cancel
+ * incoh, nflags, ncontrib and uncancelled may be NULL. */
 int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup,
                   int n_theta, const double* theta_deg, int n_phi, const double* phi_deg,
-                  double band_deg, double* field, double* incoh, int* nflags, int* ncontrib);
+                  double band_deg, double* field, double* incoh, int* nflags, int* ncontrib,
+                  double* uncancelled);
 
 /* Fresnel coefficients of the paper's Eq. 8 for a real relative index m_rel =
  * n_other/n_current and the incidence cosine ci (0 < ci <= 1).  Outputs

@@ -8,15 +8,14 @@
 // as (e_perp, n x e_perp) both projection matrices of Eq. 3 are diagonal,
 // diag(1, n.k_hat), so the equation reduces to a handful of multiply-adds.
 //
-// Precision policy (template parameter G = geometry type):
+// Precision policy (template parameter G = type of the wave quantities):
 //   G = double : every step in FP64.
-//   G = float  : directions, bases, Fresnel, Jones and WFC in FP32; the ray
-//                position, chord length, optical path, divergence product and
-//                the propagation Jacobian I + L Q (which vanishes at caustics)
-//                stay in FP64.  The optical path of the FP32-direction polyline
-//                is exact in FP64, and the far-field phase is stationary with
-//                respect to the vertices, so direction rounding enters the phase
-//                only at second order.
+//   G = float  : Fresnel coefficients, Jones matrix, wavefront-curvature
+//                recursion and the emitted fields in FP32; the polyline
+//                (positions, directions, normals, Snell), chord lengths, optical
+//                path, phase reduction, divergence product and the propagation
+//                Jacobian I + L Q (which vanishes at caustics) stay in FP64.
+//                Records and the far-field assembly are FP32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -129,67 +128,71 @@ struct Emission {
   double phase;        // OPL - k dir.rexit - nf pi/2, unreduced
   double amp;          // sqrt(D / |det Q'|)
   double amplif;       // error amplification of the divergence factor along this ray (>= 1)
+  double drift;        // growth of a direction perturbation along the ray: prod of the largest |eig(I + L Q)|
   cx<G> f[2][3];       // lab field vectors amp e^{i phase} (J_perp e_perp + J_par e_par)
 };
 
 // ---------------------------------------------------------------------------
 // the per-ray trace: Eqs. 3, 4, 6, 8, 9, 10
+//
+// The polyline (positions, directions, normals, incidence-plane bases, Snell)
+// is FP64 in both paths; the wave quantities carried along it (Fresnel
+// coefficients, Jones matrix, wavefront-curvature recursion, emitted fields)
+// are in G.  FP32 directions drift: each curved reflection multiplies a
+// direction error by ~3-5, which after three bounces moves the far-field
+// interpolation by ~1e-4; FP64 multiply-adds cost the same as FP32 ones on
+// this chip, so the polyline stays FP64.
 // ---------------------------------------------------------------------------
 template <typename G, typename Sink>
 __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
+  typedef v3<double> V;
   const double* R = P.R;
   const double x = -P.L + (ix + 0.5) * P.h;
   const double y = -P.L + (iy + 0.5) * P.h;
   // lab ray x*ex + y*ey + t ez in body coordinates
-  v3<double> o = mk3(R[0] * x + R[3] * y, R[1] * x + R[4] * y, R[2] * x + R[5] * y);
-  v3<double> d0 = mk3(R[6], R[7], R[8]);
-  const v3<double> Ad0 = mk3(P.A[0] * d0.x, P.A[1] * d0.y, P.A[2] * d0.z);
-  const v3<double> Ao = mk3(P.A[0] * o.x, P.A[1] * o.y, P.A[2] * o.z);
-  double qa = dot(d0, Ad0), qb = 2.0 * dot(d0, Ao), qc = dot(o, Ao) - 1.0;
+  V o = mk3(R[0] * x + R[3] * y, R[1] * x + R[4] * y, R[2] * x + R[5] * y);
+  V d = mk3(R[6], R[7], R[8]);
+  const V Ad0 = mk3(P.A[0] * d.x, P.A[1] * d.y, P.A[2] * d.z);
+  const V Ao = mk3(P.A[0] * o.x, P.A[1] * o.y, P.A[2] * o.z);
+  double qa = dot(d, Ad0), qb = 2.0 * dot(d, Ao), qc = dot(o, Ao) - 1.0;
   double disc = qb * qb - 4.0 * qa * qc;
   if (!(disc > 0.0)) return;
   double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
   if (qq == 0.0) return;
   double t = fmin(qq / qa, qc / qq);
 
-  v3<double> r = axpy(t, d0, o);
-  v3<G> d = cvt<G>(d0);
-  v3<G> u1 = mk3<G>((G)R[0], (G)R[1], (G)R[2]);  // body image of lab x
-  v3<G> u2 = mk3<G>((G)R[3], (G)R[4], (G)R[5]);  // body image of lab y = d x u1
-  G q11 = 0, q12 = 0, q22 = 0;                    // plane wave
-  cx<G> J[2][2];                                  // J[component along u_a][incident pol]
+  V r = axpy(t, d, o);
+  V u1 = mk3(R[0], R[1], R[2]);  // body image of lab x
+  V u2 = mk3(R[3], R[4], R[5]);  // body image of lab y = d x u1
+  G q11 = 0, q12 = 0, q22 = 0;   // plane wave
+  cx<G> J[2][2];                 // J[component along u_a][incident pol]
   J[0][0].re = 1; J[0][0].im = 0; J[0][1].re = 0; J[0][1].im = 0;
   J[1][0].re = 0; J[1][0].im = 0; J[1][1].re = 1; J[1][1].im = 0;
   double D = 1.0;
   int nf = 0;
-  double opl = P.k * dot(d0, r);  // incident phase, referenced to the particle centre
+  double opl = P.k * dot(d, r);  // incident phase, referenced to the particle centre
   // Largest relative-error amplification met so far by the divergence factor:
-  // |L lambda| / |1 + L lambda| per propagation eigenvalue (a focal line close
-  // to an interface).  Each emission adds the cancellation of its own exit
-  // wavefront equation (a flat exit wavefront: a far-field caustic).
+  // the cancellation in det(I + L Q) per propagation (a focal line close to an
+  // interface).  Each emission adds the cancellation of its own exit wavefront
+  // equation (a flat exit wavefront: a far-field caustic).
   double amplif = 1.0;
-  G n_cur = 1, n_oth = (G)P.m;
-  double n_cur_d = 1.0;  // index of the current medium in FP64 for the optical path
+  double drift = 1.0;
+  double n_cur = 1.0, n_oth = P.m;
   const G kk = (G)P.k;
 
   for (int q = 1; q <= P.p_max + 1; ++q) {
-    // outward normal and incidence-plane basis
-    v3<double> Ar_d = mk3(P.A[0] * r.x, P.A[1] * r.y, P.A[2] * r.z);
-    v3<G> Ar = cvt<G>(Ar_d);
-    G inA = rsq(dot(Ar, Ar));
-    v3<G> nh = scl(inA, Ar);
-    G dn = dot(d, nh);                      // n . k_hat (signed)
-    G sgn = dn > 0 ? (G)1 : (G)-1;
-    G ci = sgn * dn;                         // cos(theta_i)
-    amplif = fmax(amplif, 1.0 / fmax((double)ci, 1e-300));  // grazing incidence: relative error of cos(theta_i)
-    v3<G> c = scl(sgn, cross(d, nh));        // d x nu
-    G c2 = dot(c, c);
-    v3<G> ep;
-    G tie = sizeof(G) == 8 ? (G)1e-24 : (G)1e-14;
-    if (c2 < tie) ep = u1;
-    else ep = scl(rsq(c2), c);
+    // outward normal and incidence-plane basis (FP64)
+    V Ar = mk3(P.A[0] * r.x, P.A[1] * r.y, P.A[2] * r.z);
+    const double inA = 1.0 / sqrt(dot(Ar, Ar));
+    V nh = scl(inA, Ar);
+    const double dn = dot(d, nh);  // n . k_hat (signed)
+    const double sgn = dn > 0 ? 1.0 : -1.0;
+    const double ci = sgn * dn;    // cos(theta_i)
+    V c = scl(sgn, cross(d, nh));  // d x nu
+    const double c2 = dot(c, c);
+    V ep = c2 < 1e-24 ? u1 : scl(1.0 / sqrt(c2), c);
     // rotate the carried state into (e_perp, e_par): e_perp = cs u1 + sn u2
-    G cs = dot(ep, u1), sn = dot(ep, u2);
+    const G cs = (G)dot(ep, u1), sn = (G)dot(ep, u2);
     cx<G> Jl[2][2];
     for (int k = 0; k < 2; ++k) {
       Jl[0][k].re = cs * J[0][k].re + sn * J[1][k].re;
@@ -202,49 +205,55 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     G t22 = sn * sn * q11 - 2 * cs * sn * q12 + cs * cs * q22;
 
     // surface curvature in (s1, s2) = (e_perp, n x e_perp), shape operator of r^T A r = 1
-    v3<G> s2 = cross(nh, ep);
-    v3<G> Aep = mk3<G>((G)P.A[0] * ep.x, (G)P.A[1] * ep.y, (G)P.A[2] * ep.z);
-    v3<G> As2 = mk3<G>((G)P.A[0] * s2.x, (G)P.A[1] * s2.y, (G)P.A[2] * s2.z);
-    G C11 = dot(ep, Aep) * inA, C12 = dot(ep, As2) * inA, C22 = dot(s2, As2) * inA;
+    V s2 = cross(nh, ep);
+    const G C11 = (G)((P.A[0] * ep.x * ep.x + P.A[1] * ep.y * ep.y + P.A[2] * ep.z * ep.z) * inA);
+    const G C12 = (G)((P.A[0] * ep.x * s2.x + P.A[1] * ep.y * s2.y + P.A[2] * ep.z * s2.z) * inA);
+    const G C22 = (G)((P.A[0] * s2.x * s2.x + P.A[1] * s2.y * s2.y + P.A[2] * s2.z * s2.z) * inA);
 
-    // Snell (Eq. 4) and Fresnel (Eq. 8) in units of n_cur k
-    G mrel = n_oth / n_cur;
-    G st2 = 1 - ci * ci;
-    G ct2 = 1 - st2 / (mrel * mrel);
-    bool tir = ct2 < 0;
-    v3<G> dr = axpy(-2 * dn, nh, d);
-    G gr = -dn;                              // n . k_hat of the reflected wave
-    cx<G> rp, rl, tp, tl;
-    G m2 = mrel * mrel;
-    G ct = 0, gt = 0;
-    v3<G> dt = d;
+    // Snell (Eq. 4), FP64
+    const double mrel = n_oth / n_cur;
+    const double st2 = 1.0 - ci * ci;
+    const double ct2 = 1.0 - st2 / (mrel * mrel);
+    const bool tir = ct2 < 0.0;
+    V dr = axpy(-2.0 * dn, nh, d);
+    const double gr = -dn;  // n . k_hat of the reflected wave
+    double ct = 0.0, gt = 0.0;
+    V dt = d;
     if (!tir) {
-      ct = sqr_t(ct2);
-      G b = mrel * ct;                       // k_rn / (n_cur k)
-      G inv1 = 1 / (ci + b), inv2 = 1 / (m2 * ci + b);
-      rp.re = (ci - b) * inv1;  rp.im = 0;
-      rl.re = (m2 * ci - b) * inv2;  rl.im = 0;
-      tp.re = 2 * ci * inv1;  tp.im = 0;
-      tl.re = 2 * mrel * ci * inv2;  tl.im = 0;
-      G sct = sgn * ct;
-      dt = mk3<G>((d.x - dn * nh.x) / mrel + sct * nh.x, (d.y - dn * nh.y) / mrel + sct * nh.y,
-                  (d.z - dn * nh.z) / mrel + sct * nh.z);
+      ct = sqrt(ct2);
+      const double sct = sgn * ct, im = 1.0 / mrel;
+      dt = mk3((d.x - dn * nh.x) * im + sct * nh.x, (d.y - dn * nh.y) * im + sct * nh.y,
+               (d.z - dn * nh.z) * im + sct * nh.z);
       gt = dot(dt, nh);
-    } else {
-      // evanescent transmitted wave, k_rn = +i n_cur k sqrt(sin^2 - m_rel^2)
-      G beta = sqr_t(st2 - m2);
-      cx<G> a1, b1, a2, b2;
-      a1.re = ci; a1.im = -beta; b1.re = ci; b1.im = beta;
-      a2.re = m2 * ci; a2.im = -beta; b2.re = m2 * ci; b2.im = beta;
-      rp = cdiv(a1, b1);
-      rl = cdiv(a2, b2);
-      tp.re = tp.im = tl.re = tl.im = 0;
+    }
+    // Fresnel (Eq. 8) in units of n_cur k, in G
+    cx<G> rp, rl, tp, tl;
+    {
+      const G cig = (G)ci, mg = (G)mrel, m2 = mg * mg;
+      if (!tir) {
+        const G b = (G)(mrel * ct);  // k_rn / (n_cur k)
+        const G inv1 = 1 / (cig + b), inv2 = 1 / (m2 * cig + b);
+        rp.re = (cig - b) * inv1;  rp.im = 0;
+        rl.re = (m2 * cig - b) * inv2;  rl.im = 0;
+        tp.re = 2 * cig * inv1;  tp.im = 0;
+        tl.re = 2 * mg * cig * inv2;  tl.im = 0;
+      } else {
+        // evanescent transmitted wave, k_rn = +i n_cur k sqrt(sin^2 - m_rel^2)
+        const G beta = (G)sqrt(st2 - mrel * mrel);
+        cx<G> a1, b1, a2, b2;
+        a1.re = cig; a1.im = -beta; b1.re = cig; b1.im = beta;
+        a2.re = m2 * cig; a2.im = -beta; b2.re = m2 * cig; b2.im = beta;
+        rp = cdiv(a1, b1);
+        rl = cdiv(a2, b2);
+        tp.re = tp.im = tl.re = tl.im = 0;
+      }
     }
 
     // wavefront equation (Eq. 3) with diagonal projections P = diag(1, n.k_hat):
     //   k' P' Q' P' = k_i P_i Q~ P_i + C n.(k' - k_i)
-    const G ki = n_cur * kk;
-    G M11i = ki * t11, M12i = ki * dn * t12, M22i = ki * dn * dn * t22;
+    const G ki = (G)n_cur * kk;
+    const G dng = (G)dn;
+    const G M11i = ki * t11, M12i = ki * dng * t12, M22i = ki * dng * dng * t22;
 
     // ---- emission of an order, if this interaction emits one ----
     int p_emit = -1;
@@ -252,36 +261,37 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     if (q == 1) p_emit = 0;  // external reflection
     else if (!tir) { p_emit = q - 1; emit_t = true; }
     if (p_emit >= P.p_min && p_emit <= P.p_max) {
-      G ko = emit_t ? n_oth * kk : ki;
-      G go = emit_t ? gt : gr;
-      G w = emit_t ? (ko * gt - ki * dn) : (ki * (gr - dn));
-      v3<G> dout = emit_t ? dt : dr;
-      G inko = 1 / ko, igo = 1 / go;
-      double Q11 = (double)((M11i + w * C11) * inko);
-      double Q12 = (double)((M12i + w * C12) * inko * igo);
-      double Q22 = (double)((M22i + w * C22) * inko * igo * igo);
+      const double kod = emit_t ? n_oth * P.k : n_cur * P.k;
+      const double god = emit_t ? gt : gr;
+      const G ko = (G)kod;
+      const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
+      const V dout = emit_t ? dt : dr;
+      const G inko = 1 / ko, igo = (G)(1.0 / god);
+      const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
+      double Q11 = (double)(a11 * inko);
+      double Q12 = (double)(a12 * inko * igo);
+      double Q22 = (double)(a22 * inko * igo * igo);
       double detQ = Q11 * Q22 - Q12 * Q12;
       int nft = nf + neg_eigs(Q11, Q12, Q22);
-      // near-critical transmission: cos^2(theta_t) = 1 - sin^2(theta_i)/m^2 cancels
-      double e_amplif = emit_t ? fmax(amplif, 1.0 / fmax((double)ct2, 1e-300)) : amplif;
+      double e_amplif = amplif;
       {
-        // cancellation in det of the Eq. 3 sum M = k_i P Q~ P + w C: a flat
-        // exit wavefront (far-field caustic) makes det M small against its terms
-        double a11 = (double)(M11i + w * C11), a12 = (double)(M12i + w * C12), a22 = (double)(M22i + w * C22);
-        double t11 = fabs((double)M11i) + fabs((double)(w * C11)), t12 = fabs((double)M12i) + fabs((double)(w * C12));
-        double t22 = fabs((double)M22i) + fabs((double)(w * C22));
-        // first-order bound of the relative error of det M for entry-wise relative errors
-        e_amplif = fmax(e_amplif, (t11 * fabs(a22) + fabs(a11) * t22 + 2.0 * t12 * fabs(a12)) /
-                                      fmax(fabs(a11 * a22 - a12 * a12), 1e-300));
+        // cancellation in det of the Eq. 3 sum M = k_i P Q~ P + w C: a flat exit
+        // wavefront (far-field caustic) makes det M small against its terms;
+        // first-order bound of the relative error of det M for entry-wise errors
+        double t11a = fabs((double)M11i) + fabs((double)(w * C11)), t12a = fabs((double)M12i) + fabs((double)(w * C12));
+        double t22a = fabs((double)M22i) + fabs((double)(w * C22));
+        double b11 = a11, b12 = a12, b22 = a22;
+        e_amplif = fmax(e_amplif, (t11a * fabs(b22) + fabs(b11) * t22a + 2.0 * t12a * fabs(b12)) /
+                                      fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
       }
       double amp = sqrt(D / fabs(detQ));
-      v3<G> epo = cross(dout, ep);           // e_par' of the outgoing wave
-      // lab vectors: direction rounded once; the phase uses exactly that vector
-      v3<double> db = cvt<double>(dout);
-      v3<G> dl = mk3<G>((G)(R[0] * db.x + R[1] * db.y + R[2] * db.z), (G)(R[3] * db.x + R[4] * db.y + R[5] * db.z),
-                        (G)(R[6] * db.x + R[7] * db.y + R[8] * db.z));
-      v3<double> rl_lab = mk3(R[0] * r.x + R[1] * r.y + R[2] * r.z, R[3] * r.x + R[4] * r.y + R[5] * r.z,
-                              R[6] * r.x + R[7] * r.y + R[8] * r.z);
+      V epo = cross(dout, ep);  // e_par' of the outgoing wave
+      // lab vectors: direction rounded once to G; the phase uses exactly that vector
+      v3<G> dl = mk3<G>((G)(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z),
+                        (G)(R[3] * dout.x + R[4] * dout.y + R[5] * dout.z),
+                        (G)(R[6] * dout.x + R[7] * dout.y + R[8] * dout.z));
+      V rl_lab = mk3(R[0] * r.x + R[1] * r.y + R[2] * r.z, R[3] * r.x + R[4] * r.y + R[5] * r.z,
+                     R[6] * r.x + R[7] * r.y + R[8] * r.z);
       double phase = opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
       G sph, cph;
       if (sizeof(G) == 8) sincos_t((G)phase, &sph, &cph);
@@ -289,11 +299,11 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       G ga = (G)amp;
       cx<G> pa;
       pa.re = ga * cph; pa.im = ga * sph;
-      v3<G> epl = mk3<G>((G)R[0] * ep.x + (G)R[1] * ep.y + (G)R[2] * ep.z, (G)R[3] * ep.x + (G)R[4] * ep.y + (G)R[5] * ep.z,
-                         (G)R[6] * ep.x + (G)R[7] * ep.y + (G)R[8] * ep.z);
-      v3<G> eql = mk3<G>((G)R[0] * epo.x + (G)R[1] * epo.y + (G)R[2] * epo.z,
-                         (G)R[3] * epo.x + (G)R[4] * epo.y + (G)R[5] * epo.z,
-                         (G)R[6] * epo.x + (G)R[7] * epo.y + (G)R[8] * epo.z);
+      v3<G> epl = mk3<G>((G)(R[0] * ep.x + R[1] * ep.y + R[2] * ep.z), (G)(R[3] * ep.x + R[4] * ep.y + R[5] * ep.z),
+                         (G)(R[6] * ep.x + R[7] * ep.y + R[8] * ep.z));
+      v3<G> eql = mk3<G>((G)(R[0] * epo.x + R[1] * epo.y + R[2] * epo.z),
+                         (G)(R[3] * epo.x + R[4] * epo.y + R[5] * epo.z),
+                         (G)(R[6] * epo.x + R[7] * epo.y + R[8] * epo.z));
       cx<G> c0 = emit_t ? tp : rp, c1 = emit_t ? tl : rl;
       Emission<G> e;
       e.slot = p_emit - P.p_min;
@@ -304,6 +314,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       e.phase = phase;
       e.amp = amp;
       e.amplif = e_amplif;
+      e.drift = drift;
       for (int k = 0; k < 2; ++k) {
         cx<G> jp = cmul(pa, cmul(c0, Jl[0][k]));
         cx<G> jq = cmul(pa, cmul(c1, Jl[1][k]));
@@ -316,40 +327,38 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     if (q == P.p_max + 1) break;
 
     // ---- continuing branch: transmitted at q = 1, reflected afterwards ----
-    bool cont_t = (q == 1);
+    const bool cont_t = (q == 1);
     if (cont_t && tir) break;
-    if (cont_t) amplif = fmax(amplif, 1.0 / fmax((double)ct2, 1e-300));
-    G ko = cont_t ? n_oth * kk : ki;
-    G go = cont_t ? gt : gr;
-    G w = cont_t ? (ko * gt - ki * dn) : (ki * (gr - dn));
-    G inko = 1 / ko, igo = 1 / go;
-    G Q11 = (M11i + w * C11) * inko;
-    G Q12 = (M12i + w * C12) * inko * igo;
-    G Q22 = (M22i + w * C22) * inko * igo * igo;
+    const double kod = cont_t ? n_oth * P.k : n_cur * P.k;
+    const double god = cont_t ? gt : gr;
+    const G ko = (G)kod;
+    const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
+    const G inko = 1 / ko, igo = (G)(1.0 / god);
+    const G Q11 = (M11i + w * C11) * inko;
+    const G Q12 = (M12i + w * C12) * inko * igo;
+    const G Q22 = (M22i + w * C22) * inko * igo * igo;
     cx<G> c0 = cont_t ? tp : rp, c1 = cont_t ? tl : rl;
     for (int k = 0; k < 2; ++k) {
       J[0][k] = cmul(c0, Jl[0][k]);
       J[1][k] = cmul(c1, Jl[1][k]);
     }
     d = cont_t ? dt : dr;
-    if (sizeof(G) == 4) d = scl(rsq(dot(d, d)), d);  // keep FP32 directions unit
     u1 = ep;
     u2 = cross(d, ep);
-    if (cont_t) { n_cur = n_oth; n_oth = 1; n_cur_d = P.m; }
+    if (cont_t) { n_cur = n_oth; n_oth = 1.0; }
 
     // free propagation along the chord (FP64): G = I + L Q, Q <- Q G^-1
-    v3<double> dd = cvt<double>(d);
-    double tpar = -2.0 * (P.A[0] * dd.x * r.x + P.A[1] * dd.y * r.y + P.A[2] * dd.z * r.z) /
-                  (P.A[0] * dd.x * dd.x + P.A[1] * dd.y * dd.y + P.A[2] * dd.z * dd.z);
-    const double L = tpar * sqrt(dot(dd, dd));  // length of the FP64 segment r -> r + tpar d
+    const double L = -2.0 * (P.A[0] * d.x * r.x + P.A[1] * d.y * r.y + P.A[2] * d.z * r.z) /
+                     (P.A[0] * d.x * d.x + P.A[1] * d.y * d.y + P.A[2] * d.z * d.z);
     double g11 = 1.0 + L * (double)Q11, g12 = L * (double)Q12, g22 = 1.0 + L * (double)Q22;
     double detG = g11 * g22 - g12 * g12;
     {
-      // cancellation in det(I + L Q): a focal line close to the next interface
-      // (relative errors enter through L Q only)
-      amplif = fmax(amplif, (fabs(L * (double)Q11) * fabs(g22) + fabs(g11) * fabs(L * (double)Q22) + 2.0 * g12 * g12) /
-                                fmax(fabs(detG), 1e-300));
+      double mid = 0.5 * (g11 + g22), rad = sqrt(0.25 * (g11 - g22) * (g11 - g22) + g12 * g12);
+      drift *= fmax(1.0, fmax(fabs(mid + rad), fabs(mid - rad)));
     }
+    // cancellation in det(I + L Q) (relative errors enter through L Q only)
+    amplif = fmax(amplif, (fabs(L * (double)Q11) * fabs(g22) + fabs(g11) * fabs(L * (double)Q22) + 2.0 * g12 * g12) /
+                              fmax(fabs(detG), 1e-300));
     D /= fabs(detG);
     nf += neg_eigs(g11, g12, g22);
     double idg = 1.0 / detG;
@@ -358,8 +367,8 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     double n12 = ((double)Q12 * g11 - (double)Q11 * g12) * idg;
     double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
     q11 = (G)n11; q12 = (G)n12; q22 = (G)n22;
-    opl += n_cur_d * P.k * L;
-    r = axpy(tpar, dd, r);
+    opl += n_cur * P.k * L;
+    r = axpy(L, d, r);
   }
 }
 

@@ -197,6 +197,10 @@ struct DiagSink {
     }
     if (out.phase) out.phase[o * NN + id] = e.phase;
     if (out.amp) out.amp[o * NN + id] = e.amp;
+    if (out.cond) {
+      out.cond[(o * 2 + 0) * NN + id] = e.amplif;
+      out.cond[(o * 2 + 1) * NN + id] = e.drift;
+    }
     if (out.field)
       for (int p = 0; p < n_pol; ++p)
         for (int x = 0; x < 3; ++x) {
@@ -216,6 +220,7 @@ __global__ void __launch_bounds__(256) k_trace_diag(const ParticleConst P, const
     if (out.flags) out.flags[o * NN + id] = 0;
     if (out.phase) out.phase[o * NN + id] = 0.0;
     if (out.amp) out.amp[o * NN + id] = 0.0;
+    if (out.cond) out.cond[(o * 2 + 0) * NN + id] = out.cond[(o * 2 + 1) * NN + id] = 0.0;
     for (int x = 0; x < 3; ++x) {
       if (out.dir) out.dir[(o * 3 + x) * NN + id] = 0.0;
       if (out.rexit) out.rexit[(o * 3 + x) * NN + id] = 0.0;

@@ -41,7 +41,8 @@ class Grid(ctypes.Structure):
 
 class RayRecords(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_void_p), ("dir", ctypes.c_void_p), ("rexit", ctypes.c_void_p),
-                ("phase", ctypes.c_void_p), ("amp", ctypes.c_void_p), ("field", ctypes.c_void_p)]
+                ("phase", ctypes.c_void_p), ("amp", ctypes.c_void_p), ("field", ctypes.c_void_p),
+                ("cond", ctypes.c_void_p)]
 
 
 EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_status",
@@ -152,8 +153,9 @@ def trace(part, inc, opts, device="cuda", stream=None):
                rexit=torch.empty((n_ord, 3, NN), dtype=torch.float64, device=device),
                phase=torch.empty((n_ord, NN), dtype=torch.float64, device=device),
                amp=torch.empty((n_ord, NN), dtype=torch.float64, device=device),
-               field=torch.empty((n_ord, inc.n_pol, 3, 2, NN), dtype=torch.float64, device=device))
-    rec = RayRecords(*[_ptr(out[k]) for k in ("flags", "dir", "rexit", "phase", "amp", "field")])
+               field=torch.empty((n_ord, inc.n_pol, 3, 2, NN), dtype=torch.float64, device=device),
+               cond=torch.empty((n_ord, 2, NN), dtype=torch.float64, device=device))
+    rec = RayRecords(*[_ptr(out[k]) for k in ("flags", "dir", "rexit", "phase", "amp", "field", "cond")])
     _check(load().rtw_trace(ctypes.byref(part), ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(rec),
                             _stream_ptr(stream)))
     return out
