@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--grid-n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run would shard the ray grid "
@@ -101,6 +103,13 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     rtw.load()
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.ellipsoid_mixed(args.grid_n)
     n_active = active_rays(rtw, w, args.grid_n)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "

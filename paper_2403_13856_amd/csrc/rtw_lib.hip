@@ -261,11 +261,55 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
   if (i == 0) *hdr = hv;
 }
 
-constexpr int ROWS_CAP = 1 << 22;  // (triangle, row) items of large triangles
+constexpr int ROWS_CAP = 1 << 24;  // (triangle, row) items of large triangles
+
+// Split each node-angle list into uniformly spaced runs (block 0: theta,
+// block 1: phi).  A "break" is an index where the spacing changes; more than
+// MAXSEG - 1 breaks leaves the list to binary search.
+__global__ void __launch_bounds__(256) k_axis_segments(const double* th, int n_t, const double* ph, int n_p,
+                                                       AxisSeg* seg_t, AxisSeg* seg_p) {
+  const double* v = blockIdx.x == 0 ? th : ph;
+  const int n = blockIdx.x == 0 ? n_t : n_p;
+  AxisSeg* out = blockIdx.x == 0 ? seg_t : seg_p;
+  __shared__ int nbreak;
+  __shared__ int brk[MAXSEG];
+  if (threadIdx.x == 0) nbreak = 0;
+  __syncthreads();
+  for (int i = 1 + (int)threadIdx.x; i < n - 1; i += blockDim.x) {
+    const double d0 = v[i] - v[i - 1], d1 = v[i + 1] - v[i];
+    if (fabs(d1 - d0) > 1e-7 * fmax(fabs(d0), fabs(d1))) {
+      const int k = atomicAdd(&nbreak, 1);
+      if (k < MAXSEG) brk[k] = i;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int nb = nbreak;
+  if (n < 2 || nb > MAXSEG - 1) {
+    out->nseg = 0;
+    return;
+  }
+  for (int a = 1; a < nb; ++a) {  // sort the few break indices
+    int x = brk[a], b = a;
+    while (b > 0 && brk[b - 1] > x) { brk[b] = brk[b - 1]; --b; }
+    brk[b] = x;
+  }
+  int lo = 0;
+  for (int k = 0; k <= nb; ++k) {
+    const int hi = k < nb ? brk[k] : n - 1;
+    out->start[k] = lo;
+    out->end[k] = hi;
+    out->v0[k] = v[lo];
+    out->vend[k] = v[hi];
+    out->step[k] = (v[hi] - v[lo]) / (double)(hi - lo);
+    lo = hi;
+  }
+  out->nseg = nb + 1;
+}
 
 // Workspace layout of rtw_farfield.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, flags, dir, kr, field, head, redo, rows, link, contrib, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, flags, rr, head, redo, rows, link, contrib, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -283,10 +327,9 @@ Layout layout(const ParticleConst& P, int precision, int n_theta, int n_phi, lon
   L.th = take(8 * n_theta); L.ph = take(8 * n_phi);
   L.sth = take(8 * n_theta); L.cth = take(8 * n_theta);
   L.sph = take(8 * n_phi); L.cph = take(8 * n_phi);
+  L.seg = take(2 * sizeof(AxisSeg));
   L.flags = take(4 * (size_t)n_ord * NN);
-  L.dir = take(gs * 3 * (size_t)n_ord * NN);
-  L.kr = take(gs * 3 * (size_t)n_ord * NN);
-  L.field = take(gs * 6 * (size_t)P.n_pol * n_ord * NN);
+  L.rr = take((precision == RTW_FP64 ? sizeof(RayRec<double>) : sizeof(RayRec<float>)) * (size_t)n_ord * NN);
   L.head = take(4 * (size_t)n_nodes);
   L.redo = take(precision == RTW_FP64 ? 4 : 4 * (size_t)NN);
   L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
@@ -341,11 +384,11 @@ int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid,
   ng.th = (double*)(ws + L.th); ng.ph = (double*)(ws + L.ph);
   ng.sth = (double*)(ws + L.sth); ng.cth = (double*)(ws + L.cth);
   ng.sph = (double*)(ws + L.sph); ng.cph = (double*)(ws + L.cph);
+  ng.seg_t = (const AxisSeg*)(ws + L.seg);
+  ng.seg_p = (const AxisSeg*)(ws + L.seg) + 1;
   Records<G> rec;
   rec.flags = (int32_t*)(ws + L.flags);
-  rec.dir = (G*)(ws + L.dir);
-  rec.kr = (G*)(ws + L.kr);
-  rec.field = (G*)(ws + L.field);
+  rec.rr = (RayRec<G>*)(ws + L.rr);
   rec.NN = NN;
   rec.n_pol = P.n_pol;
   rec.n_fp64 = (unsigned*)(ws + L.counter) + NPART;
@@ -365,7 +408,9 @@ int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid,
   hipLaunchKernelGGL(k_setup, dim3((unsigned)((setup_n + 255) / 256)), dim3(256), 0, st, grid->n_theta,
                      grid->theta_deg, grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth,
                      (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, pool.head, n_nodes, pool.counter,
-                     (WsHeader*)(ws + L.hdr), hv); }
+                     (WsHeader*)(ws + L.hdr), hv);
+  hipLaunchKernelGGL(k_axis_segments, dim3(2), dim3(256), 0, st, ng.th, ng.n_theta, ng.ph, ng.n_phi,
+                     (AxisSeg*)(ws + L.seg), (AxisSeg*)(ws + L.seg) + 1); }
   { ProfScope ps(precision == RTW_FP64 ? "k_trace_fp64" : "k_trace_mixed", st);
   hipLaunchKernelGGL(k_trace<G>, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, P, rec); }
   if (precision == RTW_MIXED) {
@@ -376,10 +421,9 @@ int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid,
   const long nquad = (long)(P.N - 1) * (P.N - 1);
   { ProfScope ps(precision == RTW_FP64 ? "k_raster_fp64" : "k_raster_mixed", st);
   hipLaunchKernelGGL(k_raster<G>, dim3((unsigned)((nquad + 255) / 256), n_ord), dim3(256), 0, st, P, rec, ng, pool,
-                     precision == RTW_FP64 ? 1e-9 : 2e-5); }
+                     BOX_MARGIN); }
   { ProfScope ps(precision == RTW_FP64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
-  hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, P, rec, ng, pool,
-                     precision == RTW_FP64 ? 1e-9 : 1e-6); }
+  hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, P, rec, ng, pool, BOX_MARGIN); }
   { ProfScope ps(precision == RTW_FP64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
   hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, st, pool, n_nodes,
                      P.n_pol, (G*)out, ncontrib); }

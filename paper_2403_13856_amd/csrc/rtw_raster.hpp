@@ -28,6 +28,16 @@ namespace rtw {
 constexpr int NPART = 1024;        // hit-pool partitions (spreads the append atomics)
 constexpr int NODE_SORT_MAX = 16;  // hits per node sorted in registers; more use a selection pass
 
+// An angle list split into uniformly spaced runs (detected on the device), so
+// that "first node >= x" is arithmetic rather than a binary search.  nseg == 0
+// means the list is not piecewise uniform in at most MAXSEG runs.
+constexpr int MAXSEG = 8;
+struct AxisSeg {
+  int nseg;
+  int start[MAXSEG], end[MAXSEG];  // index range [start, end] of each run (ends shared)
+  double v0[MAXSEG], step[MAXSEG], vend[MAXSEG];
+};
+
 struct NodeGrid {
   int n_theta, n_phi;
   const double* th;   // radians, ascending
@@ -36,14 +46,23 @@ struct NodeGrid {
   const double* cth;
   const double* sph;
   const double* cph;
+  const AxisSeg* seg_t;
+  const AxisSeg* seg_p;
+};
+
+// One ray's emission record for one order, contiguous so that a triangle's
+// vertices are a few cache lines each (the rasteriser gathers them at random).
+template <typename G>
+struct alignas(16) RayRec {
+  G dir[3];   // lab exit direction
+  G kr[3];    // k r_exit (lab)
+  G f[12];    // [pol][xyz][re|im] lab field amp e^{i phase} (J_perp e_perp + J_par e_par)
 };
 
 template <typename G>
 struct Records {
   int32_t* flags;  // [n_ord][NN]  bit0 valid, bits 1..7 nf, bit 8 det_neg
-  G* dir;          // [n_ord][3][NN]
-  G* kr;           // [n_ord][3][NN] (k r_exit, lab)
-  G* field;        // [n_ord][n_pol][3][2][NN]
+  RayRec<G>* rr;   // [n_ord][NN]
   long NN;
   int n_pol;
   unsigned* n_fp64;  // rays re-traced in FP64 (mixed path)
@@ -62,7 +81,10 @@ struct HitPool {
   int rows_cap;
 };
 
-constexpr int CAND_INLINE = 256;  // triangles with more box candidates go to the row list
+constexpr int CAND_INLINE = 32;  // triangles with more box candidates go to the row list
+// Angular margin (rad) of the FP32 bounding box: well above its rounding error,
+// so the box never excludes a node that the exact membership test accepts.
+constexpr double BOX_MARGIN = 4e-6;
 
 // Sink writing the compact emission records used by the rasteriser.  In the
 // mixed path an emission whose divergence factor is ill-conditioned for FP32
@@ -79,16 +101,15 @@ struct RecordSink {
     if (sizeof(E) == 4 && e.amplif > amplif_limit) need64 = true;
     const long NN = rec.NN;
     rec.flags[e.slot * NN + id] = 1 | (e.nf << 1) | (e.det_neg << 8);
-    G* dp = rec.dir + (long)e.slot * 3 * NN + id;
-    dp[0] = e.dir.x; dp[NN] = e.dir.y; dp[2 * NN] = e.dir.z;
-    G* kp = rec.kr + (long)e.slot * 3 * NN + id;
-    kp[0] = (G)(k * e.rexit.x); kp[NN] = (G)(k * e.rexit.y); kp[2 * NN] = (G)(k * e.rexit.z);
-    G* fp = rec.field + (long)e.slot * rec.n_pol * 6 * NN + id;
-    for (int p = 0; p < rec.n_pol; ++p)
+    RayRec<G> r;
+    r.dir[0] = (G)e.dir.x; r.dir[1] = (G)e.dir.y; r.dir[2] = (G)e.dir.z;
+    r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
+    for (int p = 0; p < 2; ++p)
       for (int x = 0; x < 3; ++x) {
-        fp[((p * 3 + x) * 2 + 0) * NN] = e.f[p][x].re;
-        fp[((p * 3 + x) * 2 + 1) * NN] = e.f[p][x].im;
+        r.f[(p * 3 + x) * 2 + 0] = p < rec.n_pol ? (G)e.f[p][x].re : (G)0;
+        r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)e.f[p][x].im : (G)0;
       }
+    rec.rr[e.slot * NN + id] = r;
   }
 };
 
@@ -125,6 +146,32 @@ __host__ __device__ __forceinline__ int upper_idx(const double* v, int n, double
   return lo;
 }
 
+// First index with v[i] >= x (lower) or v[i] > x (upper), from the run table
+// when there is one.  Both may err towards including one more node when x is
+// within rounding of a node -- the callers only need a superset.
+__host__ __device__ __forceinline__ int seg_lower(const AxisSeg* sg, const double* v, int n, double x) {
+  const int ns = sg->nseg;
+  if (ns == 0) return lower_idx(v, n, x);
+  for (int k = 0; k < ns; ++k)
+    if (x <= sg->vend[k]) {
+      double f = (x - sg->v0[k]) / sg->step[k];
+      int i = sg->start[k] + (f <= 0.0 ? 0 : (int)ceil(f - 1e-9));
+      return min(i, sg->end[k]);
+    }
+  return n;
+}
+__host__ __device__ __forceinline__ int seg_upper(const AxisSeg* sg, const double* v, int n, double x) {
+  const int ns = sg->nseg;
+  if (ns == 0) return upper_idx(v, n, x);
+  for (int k = 0; k < ns; ++k)
+    if (x < sg->vend[k]) {
+      double f = (x - sg->v0[k]) / sg->step[k];
+      int i = sg->start[k] + (f < 0.0 ? 0 : (int)floor(f + 1e-9) + 1);
+      return min(i, sg->end[k] + 1);
+    }
+  return n;
+}
+
 // Candidate node set of one triangle: rows [i0, i1) x (phi segment a  U  segment b).
 struct Cand {
   int i0, i1, ja0, ja1, jb0, jb1;
@@ -132,125 +179,27 @@ struct Cand {
   __device__ int count() const { return (i1 - i0) * len(); }
 };
 
-// Conservative candidate set: the spherical cap of radius rho about the unit
-// vector c contains the triangle; nodes outside the cap's (theta, phi) box
-// cannot be inside it.
-__device__ inline Cand cap_candidates(const NodeGrid& ng, const v3<double>& c, double rho) {
-  const double PI_ = 3.141592653589793, TWO_PI = 6.283185307179586;
-  Cand cd;
-  double cz = fmin(1.0, fmax(-1.0, c.z));
-  double thc = acos(cz);
-  double phc = atan2(c.y, c.x);
-  if (phc < 0) phc += TWO_PI;
-  double tlo = thc - rho, thi = thc + rho;
-  cd.i0 = lower_idx(ng.th, ng.n_theta, tlo);
-  cd.i1 = upper_idx(ng.th, ng.n_theta, thi);
-  cd.jb0 = cd.jb1 = 0;
-  bool full = (tlo <= 0.0) || (thi >= PI_) || (rho >= 0.5 * PI_);
-  double dphi = 0.0;
-  if (!full) {
-    double sr = sin(rho) / sin(thc);
-    if (sr >= 1.0) full = true;
-    else dphi = asin(sr);
-  }
-  if (full) {
-    cd.ja0 = 0; cd.ja1 = ng.n_phi;
-    return cd;
-  }
-  double lo = phc - dphi, hi = phc + dphi;
-  if (lo < 0.0) {
-    cd.ja0 = lower_idx(ng.ph, ng.n_phi, lo + TWO_PI); cd.ja1 = ng.n_phi;
-    cd.jb0 = 0; cd.jb1 = upper_idx(ng.ph, ng.n_phi, hi);
-  } else if (hi >= TWO_PI) {
-    cd.ja0 = lower_idx(ng.ph, ng.n_phi, lo); cd.ja1 = ng.n_phi;
-    cd.jb0 = 0; cd.jb1 = upper_idx(ng.ph, ng.n_phi, hi - TWO_PI);
-  } else {
-    cd.ja0 = lower_idx(ng.ph, ng.n_phi, lo); cd.ja1 = upper_idx(ng.ph, ng.n_phi, hi);
-  }
-  return cd;
-}
-
-// phi intervals (up to two, absolute radians, each within [lo, lo + 2 pi)) of
-// the latitude circle (sin t, cos t) inside the three oriented half-spaces
-// m_e . n >= 0.  Each is R cos(phi - phi_e) >= -c on the circle.  Widened by eps.
-struct Arcs {
-  int n;
-  double lo[4], hi[4];
-};
-__host__ __device__ inline Arcs row_arcs(const v3<double>* m, double st, double ct, double eps) {
-  const double TWO_PI = 6.283185307179586;
-  Arcs A;
-  A.n = 1;
-  A.lo[0] = 0.0;
-  A.hi[0] = TWO_PI;  // start with the full circle, relative frame origin 0
-  bool full_so_far = true;
-  double base = 0.0;  // absolute angle of the relative frame origin
-  for (int e = 0; e < 3; ++e) {
-    double R = st * sqrt(m[e].x * m[e].x + m[e].y * m[e].y);
-    double c = m[e].z * ct;
-    double scale = fabs(R) + fabs(c);
-    if (R <= fabs(c)) {
-      if (c + eps * scale >= 0.0) continue;  // whole circle satisfies this edge
-      A.n = 0;
-      return A;
-    }
-    double alpha = acos(fmax(-1.0, fmin(1.0, -c / R))) + eps;
-    double ph0 = atan2(m[e].y, m[e].x);
-    if (alpha >= 0.5 * TWO_PI) continue;
-    double a0 = ph0 - alpha, len = 2.0 * alpha;
-    if (full_so_far) {
-      base = a0;
-      A.n = 1;
-      A.lo[0] = 0.0;
-      A.hi[0] = len;
-      full_so_far = false;
-      continue;
-    }
-    // arc [s, s + len] in the relative frame, s in [0, 2 pi)
-    double sr = fmod(a0 - base, TWO_PI);
-    if (sr < 0) sr += TWO_PI;
-    double ilo[2] = {sr, 0.0}, ihi[2] = {sr + len, sr + len - TWO_PI};
-    int ni = (sr + len > TWO_PI) ? 2 : 1;
-    if (ni == 1) ihi[0] = sr + len; else ihi[0] = TWO_PI;
-    Arcs B;
-    B.n = 0;
-    for (int i = 0; i < A.n; ++i)
-      for (int j = 0; j < ni; ++j) {
-        double lo = fmax(A.lo[i], ilo[j]), hi = fmin(A.hi[i], ihi[j]);
-        if (lo <= hi && B.n < 4) { B.lo[B.n] = lo; B.hi[B.n] = hi; ++B.n; }
-      }
-    A = B;
-    if (A.n == 0) return A;
-  }
-  if (full_so_far) {
-    A.n = 1; A.lo[0] = 0.0; A.hi[0] = TWO_PI;
-    return A;
-  }
-  for (int i = 0; i < A.n; ++i) { A.lo[i] += base; A.hi[i] += base; }
-  return A;
-}
-
 // Node index ranges [j0, j1) of the phi list inside the absolute interval
 // [lo, hi] (length < 2 pi, possibly wrapping): up to two ranges.
-__host__ __device__ inline int phi_ranges(const NodeGrid& ng, double lo, double hi, int* j0, int* j1) {
+__device__ inline int phi_ranges(const NodeGrid& ng, double lo, double hi, int* j0, int* j1) {
   const double TWO_PI = 6.283185307179586;
   if (hi - lo >= TWO_PI) { j0[0] = 0; j1[0] = ng.n_phi; return 1; }
   double l = fmod(lo, TWO_PI);
   if (l < 0) l += TWO_PI;
   double h = l + (hi - lo);
   if (h < TWO_PI) {
-    j0[0] = lower_idx(ng.ph, ng.n_phi, l); j1[0] = upper_idx(ng.ph, ng.n_phi, h);
+    j0[0] = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l); j1[0] = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h);
     return 1;
   }
-  j0[0] = lower_idx(ng.ph, ng.n_phi, l); j1[0] = ng.n_phi;
-  j0[1] = 0; j1[1] = upper_idx(ng.ph, ng.n_phi, h - TWO_PI);
+  j0[0] = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l); j1[0] = ng.n_phi;
+  j0[1] = 0; j1[1] = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h - TWO_PI);
   return 2;
 }
 
 template <typename G>
 __device__ __forceinline__ v3<G> load_dir(const Records<G>& rec, int slot, long id) {
-  const G* p = rec.dir + (long)slot * 3 * rec.NN + id;
-  return mk3<G>(p[0], p[rec.NN], p[2 * rec.NN]);
+  const G* p = rec.rr[(long)slot * rec.NN + id].dir;
+  return mk3<G>(p[0], p[1], p[2]);
 }
 
 // One triangle of one order, as the rasteriser needs it.
@@ -286,49 +235,126 @@ __device__ inline void tri_load(const Records<G>& rec, int N, int slot, long qua
   for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
 }
 
-// Bounding cap (centre, radius) of the triangle: chords of the normalised
-// directions, which stay accurate for tiny triangles.
+// Bounding (theta, phi) box of the spherical triangle, in FP32 with an angular
+// margin (it only prunes; membership is decided exactly).  Longitude is
+// monotonic along a great-circle arc that avoids the poles, so without a pole
+// inside, the phi extent is the shortest circular interval holding the three
+// vertex longitudes; theta is extremal at a vertex or at an edge's closest
+// approach to a pole.  A triangle holding a pole spans every phi.
 template <typename G>
-__device__ inline void tri_cap(const Tri<G>& T, double margin, v3<double>& s, double& rho) {
-  v3<double> un[3];
+__device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin) {
+  const float PI_F = 3.14159265f, TWO_PI_F = 6.2831853f;
+  const double TWO_PI = 6.283185307179586;
+  v3<float> u[3];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    v3<double> dd = cvt<double>(T.dv[k]);
-    un[k] = scl(1.0 / sqrt(dot(dd, dd)), dd);
+    const v3<float> dd = cvt<float>(T.dv[k]);
+    u[k] = scl(rsqrtf(dot(dd, dd)), dd);
   }
-  s = mk3<double>(un[0].x + un[1].x + un[2].x, un[0].y + un[1].y + un[2].y, un[0].z + un[1].z + un[2].z);
-  s = scl(1.0 / sqrt(dot(s, s)), s);
-  double chord = 0.0;
+  const float o = (float)T.orient;
+  float tmin = PI_F, tmax = 0.0f;
+  float ph[3];
+  bool has_n = true, has_s = true;  // triangle contains the north / south pole
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    v3<double> df = mk3<double>(un[k].x - s.x, un[k].y - s.y, un[k].z - s.z);
-    chord = fmax(chord, sqrt(dot(df, df)));
+    const float rho = sqrtf(u[k].x * u[k].x + u[k].y * u[k].y);
+    const float th = atan2f(rho, u[k].z);
+    tmin = fminf(tmin, th);
+    tmax = fmaxf(tmax, th);
+    float p = atan2f(u[k].y, u[k].x);
+    ph[k] = p < 0.0f ? p + TWO_PI_F : p;
+    // edge opposite vertex k, cyclic order: m = u_a x u_b, inside is o m.n >= 0
+    const v3<float>& ua = u[(k + 1) % 3];
+    const v3<float>& ub = u[(k + 2) % 3];
+    const v3<float> m = cross(ua, ub);
+    const float mz = o * m.z;
+    has_n = has_n && (mz > -1e-6f);
+    has_s = has_s && (mz < 1e-6f);
+    // closest approach of the edge's great circle to the poles: p = z - (z.mh) mh
+    const float mm = dot(m, m);
+    if (mm > 1e-30f) {
+      const float im = rsqrtf(mm);
+      const v3<float> mh = scl(im, m);
+      v3<float> pz = mk3<float>(-mh.z * mh.x, -mh.z * mh.y, 1.0f - mh.z * mh.z);
+      const float pl = dot(pz, pz);
+      if (pl > 1e-30f) {
+        pz = scl(rsqrtf(pl), pz);
+        // on the arc from ua to ub?  (ua x p) and (p x ub) both along m
+        const bool on_n = dot(cross(ua, pz), m) >= 0.0f && dot(cross(pz, ub), m) >= 0.0f;
+        const v3<float> ps = scl(-1.0f, pz);
+        const bool on_s = dot(cross(ua, ps), m) >= 0.0f && dot(cross(ps, ub), m) >= 0.0f;
+        const float thp = atan2f(sqrtf(pz.x * pz.x + pz.y * pz.y), pz.z);
+        if (on_n) tmin = fminf(tmin, thp);
+        if (on_s) tmax = fmaxf(tmax, PI_F - thp);
+      }
+    }
   }
-  rho = 2.0 * asin(fmin(1.0, 0.5 * chord)) * (1.0 + 1e-6) + margin;
+  if (has_n) tmin = 0.0f;
+  if (has_s) tmax = PI_F;
+  Cand cd;
+  cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
+  const float tlo = tmin - margin, thi = tmax + margin;
+  cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
+  cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
+  if (cd.i1 <= cd.i0) return cd;  // no node row crosses the box
+  const float smin = sinf(fmaxf(tlo, 0.0f)), smax = sinf(fminf(thi, PI_F));
+  const float sden = fminf(smin, smax);
+  if (has_n || has_s || tlo <= 1e-3f || thi >= PI_F - 1e-3f) {
+    cd.ja0 = 0; cd.ja1 = ng.n_phi;
+    return cd;
+  }
+  // shortest circular interval holding the three longitudes
+  float a0 = ph[0], a1 = ph[1], a2 = ph[2], t;
+  if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
+  if (a1 > a2) { t = a1; a1 = a2; a2 = t; }
+  if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
+  const float g01 = a1 - a0, g12 = a2 - a1, g20 = a0 + TWO_PI_F - a2;
+  float lo_f, hi_f;
+  if (g20 >= g01 && g20 >= g12) { lo_f = a0; hi_f = a2; }
+  else if (g01 >= g12) { lo_f = a1; hi_f = a0 + TWO_PI_F; }
+  else { lo_f = a2; hi_f = a1 + TWO_PI_F; }
+  const double pm = (double)margin / (double)sden + 1e-6;
+  const double lo = (double)lo_f - pm, hi = (double)hi_f + pm;
+  if (hi - lo >= TWO_PI) { cd.ja0 = 0; cd.ja1 = ng.n_phi; return cd; }
+  double l = lo < 0.0 ? lo + TWO_PI : lo;
+  const double h = l + (hi - lo);
+  if (h < TWO_PI) {
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l);
+    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h);
+  } else {
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l); cd.ja1 = ng.n_phi;
+    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h - TWO_PI);
+  }
+  return cd;
 }
 
 // Membership of node direction n (watertight canonical-edge rule) and its
 // barycentric weights; dl receives d_v - n.
 template <typename G>
-__device__ inline bool tri_member(const Tri<G>& T, const v3<double>& n, G lam[3], v3<G> dl[3]) {
+__device__ __forceinline__ G canon_edge(const v3<G>& a, const v3<G>& b, int sig, const v3<G>& n) {
+  // canonical edge function (lower ray index first), shared bit-for-bit with
+  // the neighbouring triangle across this edge; returned in cyclic order
+  const v3<G> lo = sig > 0 ? a : b, hi = sig > 0 ? b : a;
+  const G ev = edge_fn(lo, hi, n);
+  return ev;
+}
+template <typename G>
+__device__ __forceinline__ bool tri_member(const Tri<G>& T, const v3<double>& n, G lam[3], v3<G> dl[3]) {
+#pragma unroll
   for (int k = 0; k < 3; ++k)
     dl[k] = mk3<G>((G)((double)T.dv[k].x - n.x), (G)((double)T.dv[k].y - n.y), (G)((double)T.dv[k].z - n.z));
   const v3<G> nG = cvt<G>(n);
-  bool inside = true;
-  G w[3];
   const int o = T.orient;
-  for (int e = 0; e < 3; ++e) {
-    // canonical edge function (lower ray index first), shared bit-for-bit
-    // with the neighbouring triangle across this edge
-    int i = (e + 1) % 3, j = (e + 2) % 3;
-    if (T.sig[e] < 0) { int tmp = i; i = j; j = tmp; }
-    G ev = edge_fn(dl[i], dl[j], nG);
-    G se = T.sig[e] > 0 ? ev : -ev;  // cyclic-order edge function = barycentric weight of vertex e
-    w[e] = se;
-    bool ok = (o > 0 ? se > 0 : se < 0) || (ev == 0 && T.sig[e] * o > 0);
-    inside = inside && ok;
-  }
-  if (!inside) return false;
-  G sw = 1 / (w[0] + w[1] + w[2]);
-  lam[0] = w[0] * sw; lam[1] = w[1] * sw; lam[2] = w[2] * sw;
+  const G e0 = canon_edge(dl[1], dl[2], T.sig[0], nG);
+  const G e1 = canon_edge(dl[2], dl[0], T.sig[1], nG);
+  const G e2 = canon_edge(dl[0], dl[1], T.sig[2], nG);
+  const G w0 = T.sig[0] > 0 ? e0 : -e0, w1 = T.sig[1] > 0 ? e1 : -e1, w2 = T.sig[2] > 0 ? e2 : -e2;
+  const bool ok0 = (o > 0 ? w0 > 0 : w0 < 0) || (e0 == 0 && T.sig[0] * o > 0);
+  const bool ok1 = (o > 0 ? w1 > 0 : w1 < 0) || (e1 == 0 && T.sig[1] * o > 0);
+  const bool ok2 = (o > 0 ? w2 > 0 : w2 < 0) || (e2 == 0 && T.sig[2] * o > 0);
+  if (!(ok0 && ok1 && ok2)) return false;
+  const G sw = 1 / (w0 + w1 + w2);
+  lam[0] = w0 * sw; lam[1] = w1 * sw; lam[2] = w2 * sw;
   return true;
 }
 
@@ -345,17 +371,16 @@ __device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, 
   for (int p = 0; p < 2; ++p)
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
   for (int k = 0; k < 3; ++k) {
-    const long id = T.vid[k];
-    const G* kp = rec.kr + (long)T.slot * 3 * NN + id;
-    G psi = kp[0] * dl[k].x + kp[NN] * dl[k].y + kp[2 * NN] * dl[k].z;  // k r.(d - n)
+    const RayRec<G>& vr = rec.rr[(long)T.slot * NN + T.vid[k]];
+    G psi = vr.kr[0] * dl[k].x + vr.kr[1] * dl[k].y + vr.kr[2] * dl[k].z;  // k r.(d - n)
     G s_, c_;
     sincos_t(psi, &s_, &c_);
     const G lr = lam[k] * c_, li = lam[k] * s_;
-    const G* fp = rec.field + (long)T.slot * rec.n_pol * 6 * NN + id;
+    const G* fp = vr.f;
     for (int p = 0; p < rec.n_pol; ++p) {
-      G fxr = fp[(p * 6 + 0) * NN], fxi = fp[(p * 6 + 1) * NN];
-      G fyr = fp[(p * 6 + 2) * NN], fyi = fp[(p * 6 + 3) * NN];
-      G fzr = fp[(p * 6 + 4) * NN], fzi = fp[(p * 6 + 5) * NN];
+      G fxr = fp[p * 6 + 0], fxi = fp[p * 6 + 1];
+      G fyr = fp[p * 6 + 2], fyi = fp[p * 6 + 3];
+      G fzr = fp[p * 6 + 4], fzi = fp[p * 6 + 5];
       G tr = fxr * eth.x + fyr * eth.y + fzr * eth.z, ti = fxi * eth.x + fyi * eth.y + fzi * eth.z;
       G pr = fxr * eph.x + fyr * eph.y, pi_ = fxi * eph.x + fyi * eph.y;
       acc[p][0][0] += lr * tr - li * ti;  acc[p][0][1] += lr * ti + li * tr;
@@ -393,10 +418,33 @@ __device__ inline int wave_partition() {
                 (threadIdx.x >> 6)) % NPART);
 }
 
+// Rasterise one triangle's box candidates (wave-uniform loop over the lanes'
+// candidate counts).
+template <typename G>
+__device__ __forceinline__ void raster_box(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
+                                           const Tri<G>& T, const Cand& cd, int total, int part) {
+  const int la = cd.ja1 - cd.ja0, len = la + (cd.jb1 - cd.jb0);
+  for (int c = 0; __any(c < total); ++c) {
+    bool hit = false;
+    int it = 0, ip = 0;
+    G lam[3];
+    v3<G> dl[3];
+    if (c < total) {
+      it = cd.i0 + c / len;
+      const int jj = c - (c / len) * len;
+      ip = jj < la ? cd.ja0 + jj : cd.jb0 + (jj - la);
+      const v3<double> n = mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
+      hit = tri_member(T, n, lam, dl);
+    }
+    const long idx = wave_reserve(hit, pool.counter, part, pool.cap_part);
+    if (idx >= 0) tri_store_hit(rec, ng, pool, T, it, ip, lam, dl, idx);
+  }
+}
+
 // One thread per (order slot, quad).  Small triangles are rasterised here from
 // their cap box; triangles whose box holds more than CAND_INLINE nodes are
-// listed row by row for k_raster_rows (exact per-row arcs, one row per thread),
-// which keeps one large triangle from stalling its wave.
+// listed row by row for k_raster_rows (one row per thread, candidates from the
+// row's arc), which keeps one large triangle from stalling its wave.
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
                                                 const HitPool<G> pool, const double rho_margin) {
@@ -406,42 +454,42 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
   const long quad = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long NN = rec.NN;
 
-  Tri<G> T[2];
-  Cand cand[2];
-  int ncand[2] = {0, 0};
-  int nrow[2] = {0, 0};
+  Tri<G> T0, T1;
+  Cand c0, c1;
+  int n0 = 0, n1 = 0, r0 = 0, r1 = 0;  // inline candidates, rows to list
   if (quad < nquad) {
-    int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
-    long v00 = (long)iy * P.N + ix;
-    int fl[4];
-    fl[0] = rec.flags[slot * NN + v00];
-    fl[1] = rec.flags[slot * NN + v00 + 1];
-    fl[2] = rec.flags[slot * NN + v00 + P.N];
-    fl[3] = rec.flags[slot * NN + v00 + P.N + 1];
-    const int nf0 = fl[0] >> 1 & 127;
-    bool tv[2];
-    tv[0] = (fl[0] & 1) && (fl[1] & 1) && (fl[3] & 1) && nf0 == (fl[1] >> 1 & 127) && nf0 == (fl[3] >> 1 & 127);
-    tv[1] = (fl[0] & 1) && (fl[2] & 1) && (fl[3] & 1) && nf0 == (fl[2] >> 1 & 127) && nf0 == (fl[3] >> 1 & 127);
-    for (int t = 0; t < 2; ++t) {
-      if (!tv[t]) continue;
-      tri_load(rec, P.N, slot, quad, t, T[t]);
-      if (T[t].orient == 0) continue;
-      v3<double> s;
-      double rho;
-      tri_cap(T[t], rho_margin, s, rho);
-      cand[t] = cap_candidates(ng, s, rho);
-      int cnt = cand[t].count();
-      if (cnt <= CAND_INLINE) ncand[t] = cnt;
-      else nrow[t] = cand[t].i1 - cand[t].i0;  // listed below
+    const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
+    const long v00 = (long)iy * P.N + ix;
+    const int f0 = rec.flags[slot * NN + v00], f1 = rec.flags[slot * NN + v00 + 1];
+    const int f2 = rec.flags[slot * NN + v00 + P.N], f3 = rec.flags[slot * NN + v00 + P.N + 1];
+    const int nf0 = f0 >> 1 & 127;
+    const bool tv0 = (f0 & 1) && (f1 & 1) && (f3 & 1) && nf0 == (f1 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
+    const bool tv1 = (f0 & 1) && (f2 & 1) && (f3 & 1) && nf0 == (f2 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
+    if (tv0) {
+      tri_load(rec, P.N, slot, quad, 0, T0);
+      if (T0.orient != 0) {
+        c0 = tri_box(ng, T0, (float)rho_margin);
+        const int cnt = c0.count();
+        if (cnt <= CAND_INLINE) n0 = cnt; else r0 = c0.i1 - c0.i0;
+      }
+    }
+    if (tv1) {
+      tri_load(rec, P.N, slot, quad, 1, T1);
+      if (T1.orient != 0) {
+        c1 = tri_box(ng, T1, (float)rho_margin);
+        const int cnt = c1.count();
+        if (cnt <= CAND_INLINE) n1 = cnt; else r1 = c1.i1 - c1.i0;
+      }
     }
   }
   // wave-level exclusive scan of the rows to list, one atomic per wave
   {
     const int lane = threadIdx.x & 63;
-    int mine = nrow[0] + nrow[1];
+    const int mine = r0 + r1;
     int incl = mine;
+#pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      int y = __shfl_up(incl, off);
+      const int y = __shfl_up(incl, off);
       if (lane >= off) incl += y;
     }
     const int wave_total = __shfl(incl, 63);
@@ -451,44 +499,25 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
       base = __shfl(base, 63);
       const unsigned at = base + (unsigned)(incl - mine);
       const bool fits = (unsigned long long)base + (unsigned)wave_total <= (unsigned long long)pool.rows_cap;
-      int r = 0;
-      for (int t = 0; t < 2; ++t)
-        for (int k = 0; k < nrow[t]; ++k, ++r) {
-          const unsigned pos = at + r;
-          if (fits) pool.rows[pos] = make_int2(T[t].key, cand[t].i0 + k);
-          else if (pos < (unsigned)pool.rows_cap) pool.rows[pos] = make_int2(-1, 0);  // unused slot
-        }
-      if (!fits)  // list full: rasterise from the cap box here (slow but exact)
-        for (int t = 0; t < 2; ++t)
-          if (nrow[t] > 0) ncand[t] = cand[t].count();
+      for (int k = 0; k < mine; ++k) {
+        const unsigned pos = at + k;
+        const int key = k < r0 ? T0.key : T1.key;
+        const int row = k < r0 ? c0.i0 + k : c1.i0 + (k - r0);
+        if (fits) pool.rows[pos] = make_int2(key, row);
+        else if (pos < (unsigned)pool.rows_cap) pool.rows[pos] = make_int2(-1, 0);  // unused slot
+      }
+      if (!fits) {  // list full: rasterise from the cap box here (slow but exact)
+        if (r0 > 0) n0 = c0.count();
+        if (r1 > 0) n1 = c1.count();
+      }
     }
   }
-  const int total = ncand[0] + ncand[1];
   const int part = wave_partition();
-
-  for (int ci = 0; __any(ci < total); ++ci) {
-    bool hit = false;
-    int t = 0, it = 0, ip = 0;
-    G lam[3];
-    v3<G> dl[3];
-    if (ci < total) {
-      t = ci < ncand[0] ? 0 : 1;
-      const Cand& cd = cand[t];
-      int c = t == 0 ? ci : ci - ncand[0];
-      int len = cd.len();
-      it = cd.i0 + c / len;
-      int jj = c - (c / len) * len;
-      ip = jj < (cd.ja1 - cd.ja0) ? cd.ja0 + jj : cd.jb0 + (jj - (cd.ja1 - cd.ja0));
-      v3<double> n = mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
-      hit = tri_member(T[t], n, lam, dl);
-    }
-    long idx = wave_reserve(hit, pool.counter, part, pool.cap_part);
-    if (idx >= 0) tri_store_hit(rec, ng, pool, T[t], it, ip, lam, dl, idx);
-  }
+  raster_box(rec, ng, pool, T0, c0, n0, part);
+  raster_box(rec, ng, pool, T1, c1, n1, part);
 }
 
-// One thread per listed (triangle, theta row): the exact phi arcs of the row
-// inside the triangle, then the membership test node by node.
+// One thread per listed (triangle, theta row).
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
                                                      const HitPool<G> pool, const double arc_eps) {
@@ -501,49 +530,25 @@ __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, cons
   for (unsigned base_item = first; base_item < n_items; base_item += stride) {
     const unsigned item = base_item + (threadIdx.x & 63);
     Tri<G> T;
-    int it = 0, nr = 0;
-    int j0[8], j1[8];
+    Cand cd;
+    cd.i0 = cd.i1 = cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
     int2 w = make_int2(-1, 0);
     if (item < n_items) w = pool.rows[item];
     if (w.x >= 0) {
       const int key = w.x;
-      it = w.y;
+      const int it = w.y;
       const int t = key & 1;
       const long sq = key >> 1;
       const int slot = (int)(sq / nquad);
       const long quad = sq - (long)slot * nquad;
       tri_load(rec, P.N, slot, quad, t, T);
-      // oriented edge normals o (d_a x d_b), cyclic edges
-      v3<double> m[3];
-      for (int e = 0; e < 3; ++e) {
-        v3<double> a = cvt<double>(T.dv[(e + 1) % 3]), b = cvt<double>(T.dv[(e + 2) % 3]);
-        m[e] = scl((double)T.orient, cross(a, b));
-      }
-      Arcs A = row_arcs(m, ng.sth[it], ng.cth[it], arc_eps);
-      for (int a = 0; a < A.n; ++a) {
-        int r0[2], r1[2];
-        int k = phi_ranges(ng, A.lo[a], A.hi[a], r0, r1);
-        for (int q = 0; q < k; ++q)
-          if (r1[q] > r0[q]) { j0[nr] = r0[q]; j1[nr] = r1[q]; ++nr; }
+      if (T.orient != 0) {
+        cd = tri_box(ng, T, (float)arc_eps);
+        cd.i0 = it;
+        cd.i1 = it + 1;
       }
     }
-    int total = 0;
-    for (int q = 0; q < nr; ++q) total += j1[q] - j0[q];
-    int q = 0, ip = nr > 0 ? j0[0] : 0;
-    for (int ci = 0; __any(ci < total); ++ci) {
-      bool hit = false;
-      G lam[3];
-      v3<G> dl[3];
-      int cur = ip;
-      if (ci < total) {
-        while (cur >= j1[q]) { ++q; cur = j0[q]; }
-        ip = cur + 1;
-        v3<double> n = mk3<double>(ng.sth[it] * ng.cph[cur], ng.sth[it] * ng.sph[cur], ng.cth[it]);
-        hit = T.orient != 0 && tri_member(T, n, lam, dl);
-      }
-      long idx = wave_reserve(hit, pool.counter, part, pool.cap_part);
-      if (idx >= 0) tri_store_hit(rec, ng, pool, T, it, cur, lam, dl, idx);
-    }
+    raster_box(rec, ng, pool, T, cd, cd.count(), part);
   }
 }
 
