@@ -130,6 +130,8 @@ int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* in
  *              interleaved (re, im): double for RTW_FP64, float for RTW_MIXED.
  *   ncontrib   DEVICE int32 [n_theta*n_phi] or NULL: triangle contributions per node.
  *   workspace  DEVICE, >= rtw_farfield_workspace_size bytes, 256-byte aligned.
+ * Errors as rtw_trace, plus RTW_ERR_UNSUPPORTED when 2 (p_max - p_min + 1)
+ * (grid_n - 1)^2 >= 2^31 (triangle keys are 32-bit).
  * The per-node sum is taken in a fixed order (deterministic).  If the hit pool
  * in the workspace overflows, the result is incomplete and
  * rtw_farfield_status() reports RTW_ERR_WORKSPACE with the size needed. */

@@ -349,6 +349,14 @@ long cap_from_bytes(const Layout& base, size_t bytes) {
   return per;
 }
 
+// Triangle keys (order slot, quad, half) are 32-bit: 2 n_ord (N-1)^2 < 2^31.
+int check_keys(const rtw_trace_opts* o) {
+  const long nq = (long)(o->grid_n - 1) * (o->grid_n - 1);
+  if (2L * (o->p_max - o->p_min + 1) * nq >= (1L << 31))
+    return fail(RTW_ERR_UNSUPPORTED, "far field needs 2 (p_max - p_min + 1) (grid_n - 1)^2 < 2^31");
+  return RTW_OK;
+}
+
 int check_grid(const rtw_grid* g) {
   if (!g) return fail(RTW_ERR_INVALID_ARG, "NULL grid");
   if (g->n_theta < 1 || g->n_phi < 1 || !g->theta_deg || !g->phi_deg)
@@ -502,6 +510,8 @@ int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* in
   if (rc) return rc;
   if (!bytes) return fail(RTW_ERR_INVALID_ARG, "NULL bytes");
   if (!grid || grid->n_theta < 1 || grid->n_phi < 1) return fail(RTW_ERR_INVALID_ARG, "empty node grid");
+  rc = check_keys(opts);
+  if (rc) return rc;
   if (!(hits_per_node > 0.0)) hits_per_node = 6.0;
   ParticleConst P = make_const(part, inc, opts);
   const long n_nodes = (long)grid->n_theta * grid->n_phi;
@@ -517,6 +527,8 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
   int rc = check_particle(part, inc, opts);
   if (rc) return rc;
   rc = check_grid(grid);
+  if (rc) return rc;
+  rc = check_keys(opts);
   if (rc) return rc;
   if (!out_field || !workspace) return fail(RTW_ERR_INVALID_ARG, "NULL output or workspace");
   if (((uintptr_t)workspace & 255) != 0) return fail(RTW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");

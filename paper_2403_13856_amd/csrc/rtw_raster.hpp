@@ -179,6 +179,14 @@ struct Cand {
   __device__ int count() const { return (i1 - i0) * len(); }
 };
 
+// Angular bounding box: colatitudes [tlo, thi] (rad) x longitudes [plo, phi]
+// (0 <= plo < 2 pi, phi - plo < 2 pi) or every longitude (full).
+struct Box {
+  float tlo, thi;
+  double plo, phi;
+  bool full;
+};
+
 // Node index ranges [j0, j1) of the phi list inside the absolute interval
 // [lo, hi] (length < 2 pi, possibly wrapping): up to two ranges.
 __device__ inline int phi_ranges(const NodeGrid& ng, double lo, double hi, int* j0, int* j1) {
@@ -242,7 +250,7 @@ __device__ inline void tri_load(const Records<G>& rec, int N, int slot, long qua
 // vertex longitudes; theta is extremal at a vertex or at an edge's closest
 // approach to a pole.  A triangle holding a pole spans every phi.
 template <typename G>
-__device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin) {
+__device__ inline Box tri_box(const Tri<G>& T, float margin) {
   const float PI_F = 3.14159265f, TWO_PI_F = 6.2831853f;
   const double TWO_PI = 6.283185307179586;
   v3<float> u[3];
@@ -251,7 +259,6 @@ __device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin
     const v3<float> dd = cvt<float>(T.dv[k]);
     u[k] = scl(rsqrtf(dot(dd, dd)), dd);
   }
-  const float o = (float)T.orient;
   float tmin = PI_F, tmax = 0.0f;
   float ph[3];
   bool has_n = true, has_s = true;  // triangle contains the north / south pole
@@ -263,27 +270,29 @@ __device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin
     tmax = fmaxf(tmax, th);
     float p = atan2f(u[k].y, u[k].x);
     ph[k] = p < 0.0f ? p + TWO_PI_F : p;
-    // edge opposite vertex k, cyclic order: m = u_a x u_b, inside is o m.n >= 0
-    const v3<float>& ua = u[(k + 1) % 3];
-    const v3<float>& ub = u[(k + 2) % 3];
-    const v3<float> m = cross(ua, ub);
-    const float mz = o * m.z;
-    has_n = has_n && (mz > -1e-6f);
-    has_s = has_s && (mz < 1e-6f);
-    // closest approach of the edge's great circle to the poles: p = z - (z.mh) mh
-    const float mm = dot(m, m);
-    if (mm > 1e-30f) {
-      const float im = rsqrtf(mm);
-      const v3<float> mh = scl(im, m);
-      v3<float> pz = mk3<float>(-mh.z * mh.x, -mh.z * mh.y, 1.0f - mh.z * mh.z);
-      const float pl = dot(pz, pz);
-      if (pl > 1e-30f) {
-        pz = scl(rsqrtf(pl), pz);
+    // edge opposite vertex k, cyclic order: m = d_a x d_b, inside is o m.n >= 0.
+    // m is formed in FP64 from the stored directions (products of FP32 values
+    // are exact there), so the pole tests and the edge's closest approach to
+    // a pole stay accurate for very short edges too.
+    const v3<double> da = cvt<double>(T.dv[(k + 1) % 3]), db = cvt<double>(T.dv[(k + 2) % 3]);
+    const v3<double> m64 = cross(da, db);
+    const double mz = (double)T.orient * m64.z;
+    has_n = has_n && (mz >= 0.0);
+    has_s = has_s && (mz <= 0.0);
+    const double mm = dot(m64, m64);
+    if (mm > 0.0) {
+      const v3<float> mh = cvt<float>(scl(rsqrt(mm), m64));
+      const v3<float>& ua = u[(k + 1) % 3];
+      const v3<float>& ub = u[(k + 2) % 3];
+      // closest point of the edge's great circle to the north pole: z - (z.mh) mh
+      const float rz = sqrtf(fmaxf(0.0f, 1.0f - mh.z * mh.z));
+      if (rz > 1e-20f) {
+        const v3<float> pz = mk3<float>(-mh.z * mh.x / rz, -mh.z * mh.y / rz, rz);
         // on the arc from ua to ub?  (ua x p) and (p x ub) both along m
-        const bool on_n = dot(cross(ua, pz), m) >= 0.0f && dot(cross(pz, ub), m) >= 0.0f;
+        const bool on_n = dot(cross(ua, pz), mh) >= 0.0f && dot(cross(pz, ub), mh) >= 0.0f;
         const v3<float> ps = scl(-1.0f, pz);
-        const bool on_s = dot(cross(ua, ps), m) >= 0.0f && dot(cross(ps, ub), m) >= 0.0f;
-        const float thp = atan2f(sqrtf(pz.x * pz.x + pz.y * pz.y), pz.z);
+        const bool on_s = dot(cross(ua, ps), mh) >= 0.0f && dot(cross(ps, ub), mh) >= 0.0f;
+        const float thp = asinf(fminf(1.0f, fabsf(mh.z)));  // pole distance of the great circle
         if (on_n) tmin = fminf(tmin, thp);
         if (on_s) tmax = fmaxf(tmax, PI_F - thp);
       }
@@ -291,18 +300,14 @@ __device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin
   }
   if (has_n) tmin = 0.0f;
   if (has_s) tmax = PI_F;
-  Cand cd;
-  cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
-  const float tlo = tmin - margin, thi = tmax + margin;
-  cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
-  cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
-  if (cd.i1 <= cd.i0) return cd;  // no node row crosses the box
-  const float smin = sinf(fmaxf(tlo, 0.0f)), smax = sinf(fminf(thi, PI_F));
-  const float sden = fminf(smin, smax);
-  if (has_n || has_s || tlo <= 1e-3f || thi >= PI_F - 1e-3f) {
-    cd.ja0 = 0; cd.ja1 = ng.n_phi;
-    return cd;
-  }
+  Box bx;
+  bx.tlo = tmin - margin;
+  bx.thi = tmax + margin;
+  bx.full = true;
+  bx.plo = 0.0;
+  bx.phi = TWO_PI;
+  if (has_n || has_s || bx.tlo <= 1e-3f || bx.thi >= PI_F - 1e-3f) return bx;
+  const float sden = fminf(sinf(bx.tlo), sinf(bx.thi));
   // shortest circular interval holding the three longitudes
   float a0 = ph[0], a1 = ph[1], a2 = ph[2], t;
   if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
@@ -315,17 +320,96 @@ __device__ inline Cand tri_box(const NodeGrid& ng, const Tri<G>& T, float margin
   else { lo_f = a2; hi_f = a1 + TWO_PI_F; }
   const double pm = (double)margin / (double)sden + 1e-6;
   const double lo = (double)lo_f - pm, hi = (double)hi_f + pm;
-  if (hi - lo >= TWO_PI) { cd.ja0 = 0; cd.ja1 = ng.n_phi; return cd; }
-  double l = lo < 0.0 ? lo + TWO_PI : lo;
-  const double h = l + (hi - lo);
-  if (h < TWO_PI) {
-    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l);
-    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h);
+  if (hi - lo >= TWO_PI) return bx;
+  bx.full = false;
+  bx.plo = lo < 0.0 ? lo + TWO_PI : lo;
+  bx.phi = bx.plo + (hi - lo);
+  return bx;
+}
+
+// Node index ranges of a box: rows [i0, i1) x the phi ranges of [plo, phi].
+__device__ inline Cand box_cand(const NodeGrid& ng, const Box& bx) {
+  const double TWO_PI = 6.283185307179586;
+  Cand cd;
+  cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
+  cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)bx.tlo);
+  cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)bx.thi);
+  if (cd.i1 <= cd.i0) return cd;  // no node row crosses the box
+  if (bx.full) { cd.ja1 = ng.n_phi; return cd; }
+  if (bx.phi < TWO_PI) {
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, bx.plo);
+    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, bx.phi);
   } else {
-    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, l); cd.ja1 = ng.n_phi;
-    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, h - TWO_PI);
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, bx.plo); cd.ja1 = ng.n_phi;
+    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, bx.phi - TWO_PI);
   }
   return cd;
+}
+
+// Longitude window of the triangle on one node row (colatitude theta_r): the
+// box window with every part removed that lies more than `margin` outside one
+// of the three edge hemispheres o (d_a x d_b).x >= 0.  On the row circle, the
+// points outside an edge form one arc (a "hole") centred opposite the edge
+// normal's longitude; holes are cut from the window's ends, which keeps the
+// window a single interval holding the triangle's part of the row.  FP64,
+// because near-tangent rows make the hole ends ill-conditioned.
+template <typename G>
+__device__ inline bool row_window(const Tri<G>& T, const Box& bx, double theta_r, double margin, double& lo,
+                                  double& hi) {
+  const double TWO_PI = 6.283185307179586, PI = 3.141592653589793;
+  lo = bx.plo;
+  hi = bx.phi;
+  bool full = bx.full;
+  const double sr = sin(theta_r), cr = cos(theta_r), sm = sin(margin);
+  double hc[3], hw[3];
+  bool has[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const v3<double> da = cvt<double>(T.dv[(k + 1) % 3]), db = cvt<double>(T.dv[(k + 2) % 3]);
+    v3<double> m = scl((double)T.orient, cross(da, db));
+    const double mm = dot(m, m);
+    has[k] = false;
+    hc[k] = 0.0;
+    hw[k] = 0.0;
+    if (!(mm > 0.0)) continue;
+    m = scl(rsqrt(mm), m);
+    const double R = sqrt(m.x * m.x + m.y * m.y);
+    // outside by more than the margin:  R sr cos(phi - phi0) + m.z cr < -sin(margin)
+    const double rhs = -m.z * cr - sm;
+    if (R * sr <= 1e-300) {
+      if (rhs > 0.0) return false;  // the whole row is outside this edge
+      continue;
+    }
+    const double th = rhs / (R * sr);
+    if (th <= -1.0) continue;     // no point of the row is outside
+    if (th >= 1.0) return false;  // every point of the row is outside
+    has[k] = true;
+    hc[k] = atan2(m.y, m.x) + PI;  // hole centre
+    hw[k] = PI - acos(th);         // hole half-width
+  }
+  // cut holes from the window ends (two passes: a cut can expose another hole)
+  for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!has[k]) continue;
+      if (full) {
+        lo = hc[k] + hw[k];
+        hi = hc[k] + TWO_PI - hw[k];
+        full = false;
+        continue;
+      }
+      double d = remainder(lo - hc[k], TWO_PI);
+      if (fabs(d) < hw[k]) lo += hw[k] - d;
+      d = remainder(hi - hc[k], TWO_PI);
+      if (fabs(d) < hw[k]) hi -= hw[k] + d;
+      if (hi <= lo) return false;
+    }
+  }
+  if (full) { lo = 0.0; hi = TWO_PI; }
+  lo = fmod(lo, TWO_PI);
+  if (lo < 0.0) lo += TWO_PI;
+  hi = lo + fmin(hi - lo, TWO_PI);
+  return true;
 }
 
 // Membership of node direction n (watertight canonical-edge rule) and its
@@ -418,21 +502,87 @@ __device__ inline int wave_partition() {
                 (threadIdx.x >> 6)) % NPART);
 }
 
-// Rasterise one triangle's box candidates (wave-uniform loop over the lanes'
-// candidate counts).
+// A triangle staged in LDS for the wave's flattened candidate loop.
 template <typename G>
-__device__ __forceinline__ void raster_box(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
-                                           const Tri<G>& T, const Cand& cd, int total, int part) {
-  const int la = cd.ja1 - cd.ja0, len = la + (cd.jb1 - cd.jb0);
-  for (int c = 0; __any(c < total); ++c) {
+struct TriSlot {
+  G dv[9];       // stored exit directions of the three vertices
+  int v00;       // ray id of the quad's (ix, iy) corner
+  int meta;      // bit 0: t (which half of the quad), bit 1: orient > 0, bits 2..: order slot
+  int key;       // per-node summation order
+  int i0, len;   // candidate rows start at i0; len candidates per row
+  int ja0, la;   // phi range a: [ja0, ja0 + la)
+  int jb0;       // phi range b starts here (len - la nodes)
+};
+
+template <typename G>
+__device__ __forceinline__ void slot_put(TriSlot<G>& S, const Tri<G>& T, const Cand& cd) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    S.dv[3 * k] = T.dv[k].x; S.dv[3 * k + 1] = T.dv[k].y; S.dv[3 * k + 2] = T.dv[k].z;
+  }
+  S.v00 = (int)T.vid[0];
+  S.meta = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.orient > 0 ? 2 : 0) | (T.slot << 2);
+  S.key = T.key;
+  S.i0 = cd.i0;
+  S.len = cd.len();
+  S.ja0 = cd.ja0;
+  S.la = cd.ja1 - cd.ja0;
+  S.jb0 = cd.jb0;
+}
+
+template <typename G>
+__device__ __forceinline__ void slot_get(const TriSlot<G>& S, int N, Tri<G>& T) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) T.dv[k] = mk3<G>(S.dv[3 * k], S.dv[3 * k + 1], S.dv[3 * k + 2]);
+  const int t = S.meta & 1;
+  const long v00 = S.v00;
+  T.vid[0] = v00;
+  T.vid[1] = t == 0 ? v00 + 1 : v00 + N + 1;
+  T.vid[2] = t == 0 ? v00 + N + 1 : v00 + N;
+  T.orient = (S.meta & 2) ? 1 : -1;
+  T.slot = S.meta >> 2;
+  T.key = S.key;
+  for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
+}
+
+// Per-wave LDS area of the flattened loop: up to two staged triangles per lane.
+template <typename G>
+struct WaveStage {
+  TriSlot<G> tri[128];  // [2 * lane + which]
+  int excl[64];         // exclusive prefix of the lanes' candidate counts
+  int n0[64];           // candidates of each lane's first triangle
+};
+
+// Test every staged candidate of the wave, 64 at a time: candidate g of the
+// wave goes to lane g mod 64 whatever triangle owns it, so one large triangle
+// costs its size / 64 iterations instead of its size.  The lanes must have
+// written their slots, n0 and counts (c0 + c1) before the call, and the block
+// must have passed a barrier since.
+template <typename G>
+__device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, int N,
+                             const WaveStage<G>& W, int wave_total, int part) {
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < wave_total; base += 64) {
+    const int g = base + lane;
     bool hit = false;
     int it = 0, ip = 0;
+    Tri<G> T;
     G lam[3];
     v3<G> dl[3];
-    if (c < total) {
-      it = cd.i0 + c / len;
-      const int jj = c - (c / len) * len;
-      ip = jj < la ? cd.ja0 + jj : cd.jb0 + (jj - la);
+    if (g < wave_total) {
+      int L = 0;  // last lane whose prefix is <= g
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (W.excl[L + step] <= g) L += step;
+      int c = g - W.excl[L];
+      const int n0 = W.n0[L];
+      const TriSlot<G>& S = W.tri[2 * L + (c < n0 ? 0 : 1)];
+      if (c >= n0) c -= n0;
+      const int row = c / S.len;
+      const int jj = c - row * S.len;
+      it = S.i0 + row;
+      ip = jj < S.la ? S.ja0 + jj : S.jb0 + (jj - S.la);
+      slot_get(S, N, T);
       const v3<double> n = mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
       hit = tri_member(T, n, lam, dl);
     }
@@ -441,13 +591,28 @@ __device__ __forceinline__ void raster_box(const Records<G>& rec, const NodeGrid
   }
 }
 
-// One thread per (order slot, quad).  Small triangles are rasterised here from
-// their cap box; triangles whose box holds more than CAND_INLINE nodes are
-// listed row by row for k_raster_rows (one row per thread, candidates from the
-// row's arc), which keeps one large triangle from stalling its wave.
+// Exclusive wave prefix of v; *total receives the wave's sum.
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+  const int lane = threadIdx.x & 63;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  *total = __shfl(incl, 63);
+  return incl - v;
+}
+
+// One thread per (order slot, quad).  Triangles whose bounding box holds at
+// most CAND_INLINE nodes are staged for the wave's flattened candidate loop;
+// larger ones are listed row by row for k_raster_rows.
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
-                                                const HitPool<G> pool, const double rho_margin) {
+                                                const HitPool<G> pool, const double margin) {
+  __shared__ WaveStage<G> stage[4];
+  WaveStage<G>& W = stage[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
   const int slot = blockIdx.y;
   const int Nq = P.N - 1;
   const long nquad = (long)Nq * Nq;
@@ -468,7 +633,7 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
     if (tv0) {
       tri_load(rec, P.N, slot, quad, 0, T0);
       if (T0.orient != 0) {
-        c0 = tri_box(ng, T0, (float)rho_margin);
+        c0 = box_cand(ng, tri_box(T0, (float)margin));
         const int cnt = c0.count();
         if (cnt <= CAND_INLINE) n0 = cnt; else r0 = c0.i1 - c0.i0;
       }
@@ -476,29 +641,23 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
     if (tv1) {
       tri_load(rec, P.N, slot, quad, 1, T1);
       if (T1.orient != 0) {
-        c1 = tri_box(ng, T1, (float)rho_margin);
+        c1 = box_cand(ng, tri_box(T1, (float)margin));
         const int cnt = c1.count();
         if (cnt <= CAND_INLINE) n1 = cnt; else r1 = c1.i1 - c1.i0;
       }
     }
   }
-  // wave-level exclusive scan of the rows to list, one atomic per wave
+  // rows of large triangles: wave-level exclusive scan, one atomic per wave
   {
-    const int lane = threadIdx.x & 63;
     const int mine = r0 + r1;
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    const int wave_total = __shfl(incl, 63);
-    if (wave_total > 0) {
+    int wave_rows;
+    const int before = wave_excl_scan(mine, &wave_rows);
+    if (wave_rows > 0) {
       unsigned base = 0;
-      if (lane == 63) base = atomicAdd(pool.n_rows, (unsigned)wave_total);
+      if (lane == 63) base = atomicAdd(pool.n_rows, (unsigned)wave_rows);
       base = __shfl(base, 63);
-      const unsigned at = base + (unsigned)(incl - mine);
-      const bool fits = (unsigned long long)base + (unsigned)wave_total <= (unsigned long long)pool.rows_cap;
+      const unsigned at = base + (unsigned)before;
+      const bool fits = (unsigned long long)base + (unsigned)wave_rows <= (unsigned long long)pool.rows_cap;
       for (int k = 0; k < mine; ++k) {
         const unsigned pos = at + k;
         const int key = k < r0 ? T0.key : T1.key;
@@ -506,32 +665,36 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
         if (fits) pool.rows[pos] = make_int2(key, row);
         else if (pos < (unsigned)pool.rows_cap) pool.rows[pos] = make_int2(-1, 0);  // unused slot
       }
-      if (!fits) {  // list full: rasterise from the cap box here (slow but exact)
+      if (!fits) {  // list full: rasterise the whole box in this kernel (slow but exact)
         if (r0 > 0) n0 = c0.count();
         if (r1 > 0) n1 = c1.count();
       }
     }
   }
-  const int part = wave_partition();
-  raster_box(rec, ng, pool, T0, c0, n0, part);
-  raster_box(rec, ng, pool, T1, c1, n1, part);
+  if (n0 > 0) slot_put(W.tri[2 * lane], T0, c0);
+  if (n1 > 0) slot_put(W.tri[2 * lane + 1], T1, c1);
+  int wave_total;
+  W.excl[lane] = wave_excl_scan(n0 + n1, &wave_total);
+  W.n0[lane] = n0;
+  __syncthreads();
+  raster_drain(rec, ng, pool, P.N, W, wave_total, wave_partition());
 }
 
-// One thread per listed (triangle, theta row).
+// One thread per listed (triangle, theta row); the block walks the list in
+// blocks of 256 items.  Each row's candidates are the nodes of the row's
+// longitude window (row_window).
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
-                                                     const HitPool<G> pool, const double arc_eps) {
+                                                     const HitPool<G> pool, const double margin) {
+  __shared__ WaveStage<G> stage[4];
+  WaveStage<G>& W = stage[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
   const unsigned n_items = min(*pool.n_rows, (unsigned)pool.rows_cap);
   const long nquad = (long)(P.N - 1) * (P.N - 1);
   const int part = wave_partition();
-  // every lane runs the same number of outer iterations (wave-uniform)
-  const unsigned stride = gridDim.x * blockDim.x;
-  const unsigned first = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
-  for (unsigned base_item = first; base_item < n_items; base_item += stride) {
-    const unsigned item = base_item + (threadIdx.x & 63);
-    Tri<G> T;
-    Cand cd;
-    cd.i0 = cd.i1 = cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
+  for (unsigned first = blockIdx.x * blockDim.x; first < n_items; first += gridDim.x * blockDim.x) {
+    const unsigned item = first + threadIdx.x;
+    int n = 0;
     int2 w = make_int2(-1, 0);
     if (item < n_items) w = pool.rows[item];
     if (w.x >= 0) {
@@ -541,14 +704,32 @@ __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, cons
       const long sq = key >> 1;
       const int slot = (int)(sq / nquad);
       const long quad = sq - (long)slot * nquad;
+      Tri<G> T;
       tri_load(rec, P.N, slot, quad, t, T);
       if (T.orient != 0) {
-        cd = tri_box(ng, T, (float)arc_eps);
-        cd.i0 = it;
-        cd.i1 = it + 1;
+        const Box bx = tri_box(T, (float)margin);
+        double lo, hi;
+        if (row_window(T, bx, ng.th[it], margin, lo, hi)) {
+          int j0[2], j1[2];
+          const int nr = phi_ranges(ng, lo, hi, j0, j1);
+          Cand cd;
+          cd.i0 = it;
+          cd.i1 = it + 1;
+          cd.ja0 = j0[0];
+          cd.ja1 = j1[0];
+          cd.jb0 = nr > 1 ? j0[1] : 0;
+          cd.jb1 = nr > 1 ? j1[1] : 0;
+          n = cd.count();
+          if (n > 0) slot_put(W.tri[2 * lane], T, cd);
+        }
       }
     }
-    raster_box(rec, ng, pool, T, cd, cd.count(), part);
+    int wave_total;
+    W.excl[lane] = wave_excl_scan(n, &wave_total);
+    W.n0[lane] = n;
+    __syncthreads();
+    raster_drain(rec, ng, pool, P.N, W, wave_total, part);
+    __syncthreads();  // the stage is rewritten by the next block of items
   }
 }
 
