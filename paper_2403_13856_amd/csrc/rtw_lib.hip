@@ -265,15 +265,18 @@ constexpr int ROWS_CAP = 1 << 24;  // (triangle, row) items of large triangles
 
 // Split each node-angle list into uniformly spaced runs (block 0: theta,
 // block 1: phi).  A "break" is an index where the spacing changes; more than
-// MAXSEG - 1 breaks leaves the list to binary search.
+// MAXSEG - 1 breaks leaves the list to binary search, and so does a run whose
+// nodes deviate from its arithmetic model by more than 1e-10 of its step
+// (the lookups allow 1e-9).
 __global__ void __launch_bounds__(256) k_axis_segments(const double* th, int n_t, const double* ph, int n_p,
                                                        AxisSeg* seg_t, AxisSeg* seg_p) {
   const double* v = blockIdx.x == 0 ? th : ph;
   const int n = blockIdx.x == 0 ? n_t : n_p;
   AxisSeg* out = blockIdx.x == 0 ? seg_t : seg_p;
-  __shared__ int nbreak;
+  __shared__ int nbreak, bad;
   __shared__ int brk[MAXSEG];
-  if (threadIdx.x == 0) nbreak = 0;
+  __shared__ AxisSeg sg;
+  if (threadIdx.x == 0) { nbreak = 0; bad = 0; }
   __syncthreads();
   for (int i = 1 + (int)threadIdx.x; i < n - 1; i += blockDim.x) {
     const double d0 = v[i] - v[i - 1], d1 = v[i + 1] - v[i];
@@ -283,33 +286,46 @@ __global__ void __launch_bounds__(256) k_axis_segments(const double* th, int n_t
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
   const int nb = nbreak;
   if (n < 2 || nb > MAXSEG - 1) {
-    out->nseg = 0;
+    if (threadIdx.x == 0) out->nseg = 0;
     return;
   }
-  for (int a = 1; a < nb; ++a) {  // sort the few break indices
-    int x = brk[a], b = a;
-    while (b > 0 && brk[b - 1] > x) { brk[b] = brk[b - 1]; --b; }
-    brk[b] = x;
+  if (threadIdx.x == 0) {
+    for (int a = 1; a < nb; ++a) {  // sort the few break indices
+      int x = brk[a], b = a;
+      while (b > 0 && brk[b - 1] > x) { brk[b] = brk[b - 1]; --b; }
+      brk[b] = x;
+    }
+    int lo = 0;
+    for (int k = 0; k <= nb; ++k) {
+      const int hi = k < nb ? brk[k] : n - 1;
+      sg.start[k] = lo;
+      sg.end[k] = hi;
+      sg.v0[k] = v[lo];
+      sg.vend[k] = v[hi];
+      sg.step[k] = (v[hi] - v[lo]) / (double)(hi - lo);
+      sg.inv_step[k] = 1.0 / sg.step[k];
+      lo = hi;
+    }
+    sg.nseg = nb + 1;
   }
-  int lo = 0;
-  for (int k = 0; k <= nb; ++k) {
-    const int hi = k < nb ? brk[k] : n - 1;
-    out->start[k] = lo;
-    out->end[k] = hi;
-    out->v0[k] = v[lo];
-    out->vend[k] = v[hi];
-    out->step[k] = (v[hi] - v[lo]) / (double)(hi - lo);
-    lo = hi;
+  __syncthreads();
+  for (int k = 0; k < sg.nseg; ++k)
+    for (int i = sg.start[k] + (int)threadIdx.x; i <= sg.end[k]; i += blockDim.x) {
+      const double model = sg.v0[k] + (double)(i - sg.start[k]) * sg.step[k];
+      if (!(fabs(v[i] - model) <= 1e-10 * sg.step[k])) bad = 1;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bad) sg.nseg = 0;
+    *out = sg;
   }
-  out->nseg = nb + 1;
 }
 
 // Workspace layout of rtw_farfield.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, flags, rr, head, redo, rows, link, contrib, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, flags, rr, ang, head, redo, rows, link, contrib, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -330,6 +346,7 @@ Layout layout(const ParticleConst& P, int precision, int n_theta, int n_phi, lon
   L.seg = take(2 * sizeof(AxisSeg));
   L.flags = take(4 * (size_t)n_ord * NN);
   L.rr = take((precision == RTW_FP64 ? sizeof(RayRec<double>) : sizeof(RayRec<float>)) * (size_t)n_ord * NN);
+  L.ang = take(sizeof(float2) * (size_t)n_ord * NN);
   L.head = take(4 * (size_t)n_nodes);
   L.redo = take(precision == RTW_FP64 ? 4 : 4 * (size_t)NN);
   L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
@@ -397,6 +414,7 @@ int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid,
   Records<G> rec;
   rec.flags = (int32_t*)(ws + L.flags);
   rec.rr = (RayRec<G>*)(ws + L.rr);
+  rec.ang = (float2*)(ws + L.ang);
   rec.NN = NN;
   rec.n_pol = P.n_pol;
   rec.n_fp64 = (unsigned*)(ws + L.counter) + NPART;

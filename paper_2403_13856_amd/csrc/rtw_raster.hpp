@@ -35,7 +35,7 @@ constexpr int MAXSEG = 8;
 struct AxisSeg {
   int nseg;
   int start[MAXSEG], end[MAXSEG];  // index range [start, end] of each run (ends shared)
-  double v0[MAXSEG], step[MAXSEG], vend[MAXSEG];
+  double v0[MAXSEG], step[MAXSEG], inv_step[MAXSEG], vend[MAXSEG];
 };
 
 struct NodeGrid {
@@ -63,6 +63,7 @@ template <typename G>
 struct Records {
   int32_t* flags;  // [n_ord][NN]  bit0 valid, bits 1..7 nf, bit 8 det_neg
   RayRec<G>* rr;   // [n_ord][NN]
+  float2* ang;     // [n_ord][NN]  (theta, phi) of the exit direction (rad), phi in [0, 2 pi)
   long NN;
   int n_pol;
   unsigned* n_fp64;  // rays re-traced in FP64 (mixed path)
@@ -110,6 +111,11 @@ struct RecordSink {
         r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)e.f[p][x].im : (G)0;
       }
     rec.rr[e.slot * NN + id] = r;
+    const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
+    float phi = atan2f(dy, dx);
+    if (phi < 0.0f) phi += 6.28318531f;
+    if (phi >= 6.28318531f) phi = 0.0f;
+    rec.ang[e.slot * NN + id] = make_float2(atan2f(sqrtf(dx * dx + dy * dy), dz), phi);
   }
 };
 
@@ -154,7 +160,7 @@ __host__ __device__ __forceinline__ int seg_lower(const AxisSeg* sg, const doubl
   if (ns == 0) return lower_idx(v, n, x);
   for (int k = 0; k < ns; ++k)
     if (x <= sg->vend[k]) {
-      double f = (x - sg->v0[k]) / sg->step[k];
+      double f = (x - sg->v0[k]) * sg->inv_step[k];
       int i = sg->start[k] + (f <= 0.0 ? 0 : (int)ceil(f - 1e-9));
       return min(i, sg->end[k]);
     }
@@ -165,7 +171,7 @@ __host__ __device__ __forceinline__ int seg_upper(const AxisSeg* sg, const doubl
   if (ns == 0) return upper_idx(v, n, x);
   for (int k = 0; k < ns; ++k)
     if (x < sg->vend[k]) {
-      double f = (x - sg->v0[k]) / sg->step[k];
+      double f = (x - sg->v0[k]) * sg->inv_step[k];
       int i = sg->start[k] + (f < 0.0 ? 0 : (int)floor(f + 1e-9) + 1);
       return min(i, sg->end[k] + 1);
     }
@@ -344,6 +350,57 @@ __device__ inline Cand box_cand(const NodeGrid& ng, const Box& bx) {
     cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, bx.phi - TWO_PI);
   }
   return cd;
+}
+
+// Bounding box of a small triangle away from the poles from its vertices'
+// (theta, phi) alone (no directions needed).  Returns false when the triangle
+// is too large or too close to a pole for the bounds below; tri_box decides
+// those.  With l the longest edge (l^2 <= 1.1 q, q from the angle
+// differences and sin theta <= s_hi):
+//   - every point of the triangle lies within l of each vertex, so a pole
+//     farther than l from the nearest vertex is outside;
+//   - along a great-circle arc of length l, cos theta exceeds its end values
+//     by at most l^2 / 8, so theta leaves the vertex range by at most
+//     l^2 / (8 sin theta); the test below keeps that under 2e-6 rad, which
+//     the margin absorbs;
+//   - longitude is monotonic along pole-free arcs: the phi extent is the
+//     shortest circular interval holding the three vertex longitudes.
+__device__ inline bool fast_box(float2 a, float2 b, float2 c, float margin, Box& bx) {
+  const float PI_F = 3.14159265f, TWO_PI_F = 6.2831853f;
+  const float tmin = fminf(a.x, fminf(b.x, c.x)), tmax = fmaxf(a.x, fmaxf(b.x, c.x));
+  const float s_hi = fminf(1.0f, fminf(tmax, PI_F - tmin));
+  auto dp = [&](float p, float q) { const float d = fabsf(p - q); return fminf(d, TWO_PI_F - d); };
+  auto e2 = [&](float2 u, float2 v) {
+    const float dt = u.x - v.x, dph = dp(u.y, v.y) * s_hi;
+    return dt * dt + dph * dph;
+  };
+  const float q = 1.1f * fmaxf(e2(a, b), fmaxf(e2(b, c), e2(c, a)));
+  if (!(q < 1e-2f)) return false;
+  const float l = sqrtf(q);
+  const float pole_gap = fminf(tmin, PI_F - tmax) - l;  // lower bound of the pole distance of any point
+  if (!(pole_gap > 2.0f * margin + 1e-3f)) return false;
+  const float s_lo = 0.63661977f * pole_gap;  // sin x >= 2x / pi on [0, pi/2]
+  if (!(0.132f * q <= 2e-6f * s_lo)) return false;
+  const float m = margin + 2e-6f;
+  bx.full = false;
+  bx.tlo = tmin - m;
+  bx.thi = tmax + m;
+  float a0 = a.y, a1 = b.y, a2 = c.y, t;
+  if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
+  if (a1 > a2) { t = a1; a1 = a2; a2 = t; }
+  if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
+  const float g01 = a1 - a0, g12 = a2 - a1, g20 = a0 + TWO_PI_F - a2;
+  float lo_f, hi_f;
+  if (g20 >= g01 && g20 >= g12) { lo_f = a0; hi_f = a2; }
+  else if (g01 >= g12) { lo_f = a1; hi_f = a0 + TWO_PI_F; }
+  else { lo_f = a2; hi_f = a1 + TWO_PI_F; }
+  const double pm = (double)m / (double)(0.63661977f * fminf(bx.tlo, PI_F - bx.thi)) + 1e-6;
+  const double TWO_PI = 6.283185307179586;
+  const double lo = (double)lo_f - pm, hi = (double)hi_f + pm;
+  if (hi - lo >= TWO_PI) return false;
+  bx.plo = lo < 0.0 ? lo + TWO_PI : lo;
+  bx.phi = bx.plo + (hi - lo);
+  return true;
 }
 
 // Longitude window of the triangle on one node row (colatitude theta_r): the
@@ -546,48 +603,96 @@ __device__ __forceinline__ void slot_get(const TriSlot<G>& S, int N, Tri<G>& T) 
 }
 
 // Per-wave LDS area of the flattened loop: up to two staged triangles per lane.
+constexpr int HITBUF = 128;  // node hits buffered per wave before their pool slots are taken
 template <typename G>
 struct WaveStage {
   TriSlot<G> tri[128];  // [2 * lane + which]
   int excl[64];         // exclusive prefix of the lanes' candidate counts
   int n0[64];           // candidates of each lane's first triangle
+  int hits[HITBUF];     // wave candidate numbers of buffered hits
 };
+
+// Candidate g of the wave: its triangle and node (row it, column ip).
+template <typename G>
+__device__ __forceinline__ void locate(const WaveStage<G>& W, int g, int N, Tri<G>& T, int& it, int& ip) {
+  int L = 0;  // last lane whose prefix is <= g
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (W.excl[L + step] <= g) L += step;
+  int c = g - W.excl[L];
+  const int n0 = W.n0[L];
+  const TriSlot<G>& S = W.tri[2 * L + (c < n0 ? 0 : 1)];
+  if (c >= n0) c -= n0;
+  const int row = c / S.len;
+  const int jj = c - row * S.len;
+  it = S.i0 + row;
+  ip = jj < S.la ? S.ja0 + jj : S.jb0 + (jj - S.la);
+  slot_get(S, N, T);
+}
+
+__device__ __forceinline__ v3<double> node_dir(const NodeGrid& ng, int it, int ip) {
+  return mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
+}
+
+// Take pool slots for the nh buffered hits with one atomic, then store each
+// hit's contribution (its membership weights are recomputed, bit for bit).
+template <typename G>
+__device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, int N,
+                           const WaveStage<G>& W, int nh, int part) {
+  const int lane = threadIdx.x & 63;
+  unsigned first = 0;
+  if (lane == 0) first = atomicAdd(&pool.counter[part], (unsigned)nh);
+  first = __shfl(first, 0);
+  for (int h0 = 0; h0 < nh; h0 += 64) {
+    const int h = h0 + lane;
+    if (h < nh) {
+      Tri<G> T;
+      int it, ip;
+      locate(W, W.hits[h], N, T, it, ip);
+      G lam[3];
+      v3<G> dl[3];
+      tri_member(T, node_dir(ng, it, ip), lam, dl);
+      const unsigned pos = first + (unsigned)h;
+      if (pos < (unsigned)pool.cap_part)  // beyond: overflow, reported by the status call
+        tri_store_hit(rec, ng, pool, T, it, ip, lam, dl, (long)part * pool.cap_part + pos);
+    }
+  }
+}
 
 // Test every staged candidate of the wave, 64 at a time: candidate g of the
 // wave goes to lane g mod 64 whatever triangle owns it, so one large triangle
-// costs its size / 64 iterations instead of its size.  The lanes must have
-// written their slots, n0 and counts (c0 + c1) before the call, and the block
-// must have passed a barrier since.
+// costs its size / 64 iterations instead of its size.  Hits are buffered in
+// LDS and stored in batches, so the membership loop never waits on an atomic.
+// The lanes must have written their slots, n0 and prefix before the call, and
+// the block must have passed a barrier since.
 template <typename G>
 __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, int N,
-                             const WaveStage<G>& W, int wave_total, int part) {
+                             WaveStage<G>& W, int wave_total, int part) {
   const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int nh = 0;  // buffered hits (wave-uniform)
   for (int base = 0; base < wave_total; base += 64) {
     const int g = base + lane;
     bool hit = false;
-    int it = 0, ip = 0;
-    Tri<G> T;
-    G lam[3];
-    v3<G> dl[3];
     if (g < wave_total) {
-      int L = 0;  // last lane whose prefix is <= g
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (W.excl[L + step] <= g) L += step;
-      int c = g - W.excl[L];
-      const int n0 = W.n0[L];
-      const TriSlot<G>& S = W.tri[2 * L + (c < n0 ? 0 : 1)];
-      if (c >= n0) c -= n0;
-      const int row = c / S.len;
-      const int jj = c - row * S.len;
-      it = S.i0 + row;
-      ip = jj < S.la ? S.ja0 + jj : S.jb0 + (jj - S.la);
-      slot_get(S, N, T);
-      const v3<double> n = mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
-      hit = tri_member(T, n, lam, dl);
+      Tri<G> T;
+      int it, ip;
+      locate(W, g, N, T, it, ip);
+      G lam[3];
+      v3<G> dl[3];
+      hit = tri_member(T, node_dir(ng, it, ip), lam, dl);
     }
-    const long idx = wave_reserve(hit, pool.counter, part, pool.cap_part);
-    if (idx >= 0) tri_store_hit(rec, ng, pool, T, it, ip, lam, dl, idx);
+    const unsigned long long mask = __ballot(hit);
+    if (hit) W.hits[nh + __popcll(mask & below)] = g;
+    nh += __popcll(mask);
+    if (nh > HITBUF - 64 || (base + 64 >= wave_total && nh > 0)) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      flush_hits(rec, ng, pool, N, W, nh, part);
+      nh = 0;
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
@@ -630,21 +735,33 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
     const int nf0 = f0 >> 1 & 127;
     const bool tv0 = (f0 & 1) && (f1 & 1) && (f3 & 1) && nf0 == (f1 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
     const bool tv1 = (f0 & 1) && (f2 & 1) && (f3 & 1) && nf0 == (f2 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
-    if (tv0) {
-      tri_load(rec, P.N, slot, quad, 0, T0);
-      if (T0.orient != 0) {
-        c0 = box_cand(ng, tri_box(T0, (float)margin));
-        const int cnt = c0.count();
-        if (cnt <= CAND_INLINE) n0 = cnt; else r0 = c0.i1 - c0.i0;
-      }
-    }
-    if (tv1) {
-      tri_load(rec, P.N, slot, quad, 1, T1);
-      if (T1.orient != 0) {
-        c1 = box_cand(ng, tri_box(T1, (float)margin));
-        const int cnt = c1.count();
-        if (cnt <= CAND_INLINE) n1 = cnt; else r1 = c1.i1 - c1.i0;
-      }
+    if (tv0 || tv1) {
+      const float2* an = rec.ang + slot * NN;
+      const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + P.N], a11 = an[v00 + P.N + 1];
+      // box of one triangle: from the vertex angles when fast_box applies, else
+      // from the directions; the directions (and orientation) are loaded only
+      // for triangles with candidate nodes
+      auto setup = [&](int t, bool tv, float2 b, float2 c, Tri<G>& T, Cand& cd, int& n, int& r) {
+        if (!tv) return;
+        Box bx;
+        bool loaded = false;
+        if (!fast_box(a00, b, c, (float)margin, bx)) {
+          tri_load(rec, P.N, slot, quad, t, T);
+          loaded = true;
+          if (T.orient == 0) return;
+          bx = tri_box(T, (float)margin);
+        }
+        cd = box_cand(ng, bx);
+        const int cnt = cd.count();
+        if (cnt == 0) return;
+        if (!loaded) {
+          tri_load(rec, P.N, slot, quad, t, T);
+          if (T.orient == 0) return;
+        }
+        if (cnt <= CAND_INLINE) n = cnt; else r = cd.i1 - cd.i0;
+      };
+      setup(0, tv0, a01, a11, T0, c0, n0, r0);
+      setup(1, tv1, a11, a10, T1, c1, n1, r1);
     }
   }
   // rows of large triangles: wave-level exclusive scan, one atomic per wave
