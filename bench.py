@@ -24,32 +24,76 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic floating-point work (adds, multiplies, divides, square roots and
-# elementary functions counted once each, an FMA as two), per unit:
-#   trace: per active ray, p = 0..3 (4 interactions, 3 propagations, 4 emissions)
-#   raster: per valid triangle set-up, per candidate node test, per node hit (2 polarisations)
-#   node sum: per hit accumulated (8 components)
-FLOP_TRACE_PER_RAY = 4 * 183 + 3 * 130 + 4 * 250 + 40
-FLOP_RASTER_PER_TRIANGLE = 110
-FLOP_RASTER_PER_CANDIDATE = 55
-FLOP_RASTER_PER_HIT = 320
-PEAK_VALU_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published, packed-math figure)
-PEAK_VALU_FP64_TFLOPS = 78.6   # MI355X vector FP64
+# Algorithmic floating-point work of the rasteriser (adds, multiplies,
+# divides and square roots counted once each, an FMA as two, an elementary
+# function as one), per unit of the method:
+#   per valid triangle: orientation triple product (20) and angular bounds (40)
+#   per node hit: membership and barycentric weights (58) + carrying and
+#   projecting the three vertex fields for two polarisations (180)
+FLOP_RASTER_PER_TRIANGLE = 60
+FLOP_RASTER_PER_HIT = 238
+# per active ray, p = 0..3: four interactions (both branches), three
+# propagations, four emissions
+FLOP_TRACE_PER_RAY = 4 * 300 + 3 * 60 + 4 * 200
+PEAK_VALU_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_raster_mixed_c2_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_13856_amd", "csrc", f)
+                  for f in ("rtw_lib.hip", "rtw_device.hpp", "rtw_raster.hpp")]
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the rasteriser from the committed PMC summary,
+    or None if the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "\t")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def active_rays(rtw, w, grid_n):
-    """Incident rays that meet the particle (rays that emit order 0)."""
+def count_units(rtw, w, grid_n):
+    """Active incident rays (rays that emit order 0) and valid triangles (three
+    rays emitting the order with equal focal-line counts), from rtw_trace."""
     import torch
     part = rtw.make_particle(w.semi_axes, w.euler_deg, w.m)
-    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1), rtw.make_opts(0, 0, grid_n, rtw.FP64))
-    n = int((rec["flags"][0] & 1).sum().item())
-    del rec
+    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1),
+                    rtw.make_opts(w.p_min, w.p_max, grid_n, rtw.FP64))
+    fl = rec["flags"]
+    n_active = int((fl[0] & 1).sum().item()) if w.p_min == 0 else None
+    f = fl.view(fl.shape[0], grid_n, grid_n)
+    v = (f & 1) == 1
+    nf = (f >> 1) & 127
+    a, b, c, d = (v[:, :-1, :-1], nf[:, :-1, :-1]), (v[:, :-1, 1:], nf[:, :-1, 1:]), \
+        (v[:, 1:, :-1], nf[:, 1:, :-1]), (v[:, 1:, 1:], nf[:, 1:, 1:])
+    t0 = a[0] & b[0] & d[0] & (a[1] == b[1]) & (a[1] == d[1])
+    t1 = a[0] & c[0] & d[0] & (a[1] == c[1]) & (a[1] == d[1])
+    n_tri = int(t0.sum().item() + t1.sum().item())
+    del rec, fl, f, v, nf
     torch.cuda.empty_cache()
-    return n
+    return n_active, n_tri
 
 
 def time_path(rtw, w, grid_n, precision, steps, warmup):
@@ -104,16 +148,20 @@ def main():
     torch.cuda.set_device(0)
     rtw.load()
     if args.copy_calibration_mib > 0:
+        # one plain streaming kernel of known traffic (reads and writes this
+        # many bytes) to scale the HBM counters of a profiled run
         n = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        src = torch.zeros(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        torch.cuda.empty_cache()
     w = inputs.ellipsoid_mixed(args.grid_n)
-    n_active = active_rays(rtw, w, args.grid_n)
+    n_active, n_tri = count_units(rtw, w, args.grid_n)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "
-        f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}")
+        f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}, {n_tri} valid triangles")
 
     ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup)
     log(f"[bench] mixed: {ms_mixed:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
@@ -130,20 +178,24 @@ def main():
                     kernels_ms={k: round(t / n, 5) for k, (t, n) in prof64.items()})
 
     value = n_active / (ms_mixed * 1e-3)
-    # roofline of the dominant kernel (ALU-bound: plain VALU arithmetic)
+    # roofline of the dominant kernel (plain VALU arithmetic: "alu")
     dom, (tot, cnt) = max(prof_mixed.items(), key=lambda kv: kv[1][0])
     avg_s = tot / cnt * 1e-3
-    n_ord = w.p_max - w.p_min + 1
     if dom.startswith("k_trace"):
         flops = FLOP_TRACE_PER_RAY * n_active
+    elif dom.startswith("k_raster_rows"):
+        flops = FLOP_RASTER_PER_HIT * hits  # share of hits unknown per kernel: upper bound
     elif dom.startswith("k_raster"):
-        flops = (FLOP_RASTER_PER_TRIANGLE * 2 * n_active * n_ord + FLOP_RASTER_PER_HIT * hits)
+        flops = FLOP_RASTER_PER_TRIANGLE * n_tri + FLOP_RASTER_PER_HIT * hits
     else:
         flops = 8 * hits
     achieved = flops / avg_s / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 4), traffic=None, kernel=dom,
-                    kernel_ms=round(avg_s * 1e3, 4))
+    traffic = measured_traffic() if dom == "k_raster_mixed" else None
+    roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
+                    traffic=round(traffic) if traffic is not None else None, kernel=dom,
+                    kernel_ms=round(avg_s * 1e3, 4), flop_per_launch=flops,
+                    traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic is not None else None)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -171,7 +223,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"ellipsoid 60/50/40 um, Euler (30,20,10) deg, m=1.333, lambda=0.6328 um, "
                                f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed",
-                   "active_rays": n_active, "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
+                   "active_rays": n_active, "valid_triangles": n_tri, "source_hash": source_hash(), "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(w.n_nodes * w.n_pol / (ms_mixed * 1e-3), 1),
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},
         "fp64_path": fp64,
