@@ -14,8 +14,9 @@
  * (intrinsic Z-Y-Z Euler angles).  Time dependence exp(-i w t), so the
  * propagation phase grows as +k * path.
  *
- * Parity status of each entry point is stated in oracle/README (section
- * "pins"); every function here is pinned by a test under tests/.
+ * Every entry point is pinned by the CPU tests tests/test_oracle_*.py against
+ * closed forms, identities, symmetries, finite differences and the paper's
+ * Table 1, not against its own formulas.
  */
 #ifndef RTW_ORACLE_H
 #define RTW_ORACLE_H
