@@ -129,6 +129,7 @@ int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* in
  *   out_field  DEVICE, [n_pol][2 (theta, phi)][n_theta][n_phi] complex,
  *              interleaved (re, im): double for RTW_FP64, float for RTW_MIXED.
  *   ncontrib   DEVICE int32 [n_theta*n_phi] or NULL: triangle contributions per node.
+ * Node grids have fewer than 65536 angles per side (RTW_ERR_INVALID_ARG).
  *   workspace  DEVICE, >= rtw_farfield_workspace_size bytes, 256-byte aligned.
  * Errors as rtw_trace, plus RTW_ERR_UNSUPPORTED when 2 (p_max - p_min + 1)
  * (grid_n - 1)^2 >= 2^31 (triangle keys are 32-bit).
@@ -139,15 +140,68 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
                  const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* workspace,
                  size_t workspace_bytes, void* hip_stream);
 
-/* Synchronises hip_stream and reports whether the last rtw_farfield that used
- * this workspace fitted: RTW_OK, or RTW_ERR_WORKSPACE with *bytes_needed set to
- * a workspace size that fits.  bytes_needed may be NULL. */
+/* ---- Batches of particles (many ellipsoids, one call) -------------------
+ * The same far field for n particles that share the incident wave, the
+ * orders, the precision and the node grid, each with its own shape,
+ * orientation, index and ray-grid side grid_n[i].  Particles are taken
+ * largest first and grouped into chunks of at most rays_per_chunk incident
+ * rays; each chunk is traced by one persistent kernel whose blocks take work
+ * items (tiles of tile_rays rays of one particle) from a queue, then
+ * rasterised and summed like rtw_farfield.  Results are bitwise identical to
+ * rtw_farfield of each particle alone with the same tuning. */
+typedef struct {
+  int tile_rays;     /* incident rays per trace work item, multiple of 256 (0 = 1024) */
+  int blocks_per_cu; /* persistent trace blocks per compute unit (0 = 8) */
+  int cand_inline;   /* triangles whose bounding box holds more nodes are rasterised
+                        row by row (0 = 32) */
+} rtw_tune;
+
+typedef struct {
+  long long rays_per_chunk; /* incident rays per chunk; the workspace scales with it
+                               (0 = 2^26; a larger particle is a chunk of its own) */
+  double hits_per_node;     /* hit-pool sizing per node of a chunk (0 = 6) */
+} rtw_batch_opts;
+
+/* Workspace bytes for rtw_batch with these arguments (bopts may be NULL). */
+int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+                             const rtw_trace_opts* opts, const rtw_grid* grid, const rtw_batch_opts* bopts,
+                             size_t* bytes);
+
+/* Far fields of n particles.  parts and grid_n are HOST arrays [n]; opts gives
+ * the orders and precision (its grid_n is ignored).
+ *   out_field  DEVICE [n][n_pol][2][n_theta][n_phi] complex (layout and type as
+ *              rtw_farfield), particle i at index i.
+ *   ncontrib   DEVICE int32 [n][n_theta*n_phi] or NULL.
+ *   tune       NULL = defaults (see rtw_tune); rtw_batch_autotune picks one.
+ * Synchronises hip_stream once to upload the per-particle metadata (a few
+ * hundred bytes per particle) into the workspace, then queues the kernels and
+ * returns.  Errors as rtw_farfield for any particle (the message names it), plus
+ * RTW_ERR_UNSUPPORTED when n_ord grid_n^2 >= 2^30.  Overflow of the hit pool is
+ * reported by rtw_farfield_status on the same workspace. */
+int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib,
+              const rtw_tune* tune, const rtw_batch_opts* bopts, void* workspace, size_t workspace_bytes,
+              void* hip_stream);
+
+/* Project autotuner: times rtw_batch on a sample of up to 64 of the particles
+ * (spread over the size range) for a coordinate search over tile_rays,
+ * blocks_per_cu and then cand_inline, and returns the fastest in *best.
+ * out_field and workspace are used as scratch (sized as for rtw_batch of all n
+ * particles); the call synchronises hip_stream. */
+int rtw_batch_autotune(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+                       const rtw_trace_opts* opts, const rtw_grid* grid, const rtw_batch_opts* bopts,
+                       void* out_field, void* workspace, size_t workspace_bytes, void* hip_stream, rtw_tune* best);
+
+/* Synchronises hip_stream and reports whether the last rtw_farfield or
+ * rtw_batch that used this workspace fitted: RTW_OK, or RTW_ERR_WORKSPACE with
+ * *bytes_needed set to a workspace size that fits.  bytes_needed may be NULL. */
 int rtw_farfield_status(const void* workspace, void* hip_stream, size_t* bytes_needed);
 
-/* Synchronises hip_stream and reads counters of the last rtw_farfield that used
- * this workspace: the number of node contributions (triangle hits) and, for
- * RTW_MIXED, the number of rays traced again in FP64 because their divergence
- * factor was ill-conditioned in FP32.  Either pointer may be NULL. */
+/* Synchronises hip_stream and reads counters of the last rtw_farfield or
+ * rtw_batch that used this workspace: the number of node contributions
+ * (triangle hits) and, for RTW_MIXED, the number of rays traced again in FP64
+ * because their divergence factor was ill-conditioned in FP32.  Either pointer
+ * may be NULL. */
 int rtw_farfield_stats(const void* workspace, void* hip_stream, uint64_t* hits, uint64_t* fp64_rays);
 
 /* Per-kernel timing for benchmarks: while enabled, every kernel the library

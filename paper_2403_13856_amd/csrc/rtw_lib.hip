@@ -134,39 +134,93 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+
+// Counters after the workspace header (unsigned): the NPART hit-pool partition
+// fills, then per-chunk and per-call counters.
+enum : int {
+  C_REDO = NPART,  // rays listed for the FP64 re-trace in the current chunk
+  C_ROWS,          // row-list items of the current chunk
+  C_QUEUE,         // trace work items taken in the current chunk
+  C_NEED,          // fullest hit-pool partition over the chunks of the call
+  C_FP64_TOTAL,    // rays re-traced in FP64 over the call
+  C_PAD,
+  C_HITS,          // node hits over the call (64-bit, two slots)
+  C_HITS_HI,
+  C_COUNT
+};
+
+// Particle constants of a wave-uniform particle index, kept in scalar
+// registers (each 32-bit word is made uniform explicitly: the compiler cannot
+// prove that the record stores of the kernel leave the array untouched).
+__device__ __forceinline__ ParticleConst load_uniform(const ParticleConst* src) {
+  ParticleConst r;
+  const int* s = reinterpret_cast<const int*>(src);
+  int* d = reinterpret_cast<int*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ParticleConst) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+  return r;
+}
+
+// Persistent trace: every block takes work items (a tile of `tile` incident
+// rays of one particle) from the chunk's queue until it is empty.  Items are
+// numbered particle by particle in launch order (largest particles first),
+// so the cheap items of small particles fill the tail.
 template <typename G>
-__global__ void __launch_bounds__(256) k_trace(const ParticleConst P, const Records<G> rec) {
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= rec.NN) return;
-  const int n_ord = P.p_max - P.p_min + 1;
-  for (int o = 0; o < n_ord; ++o) rec.flags[o * rec.NN + id] = 0;
-  RecordSink<G> sink{rec, id, P.k, P.amplif_limit, false};
-  const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
-  trace_ray<G>(P, ix, iy, sink);
-  if (sizeof(G) == 4) {
-    // Rays whose divergence factor is ill-conditioned in FP32 are listed for the
-    // FP64 pass (one append per wave).
-    const bool redo = sink.need64;
-    const unsigned long long mask = __ballot(redo);
-    if (mask) {
-      const int lane = threadIdx.x & 63, leader = __ffsll((long long)mask) - 1;
-      unsigned base = 0;
-      if (lane == leader) base = atomicAdd(rec.n_fp64, (unsigned)__popcll(mask));
-      base = __shfl(base, leader);
-      if (redo) rec.redo_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int)id;
+__global__ void __launch_bounds__(256, 3) k_trace_tiles(const BatchDev B, const Records<G> rec, unsigned* queue) {
+  __shared__ long s_item;
+  const long n_items = B.tile_off[B.n] - B.tile_base;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (long)atomicAdd(queue, 1u);
+    __syncthreads();
+    const long item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int p = __builtin_amdgcn_readfirstlane(find_part(B.tile_off, B.n, B.tile_base, item));
+    const ParticleConst P = load_uniform(B.P + p);
+    const long NN = (long)P.N * P.N;
+    const long first = (item - (B.tile_off[p] - B.tile_base)) * B.tile;
+    const long last = min(first + (long)B.tile, NN);
+    const long rbase = B.n_ord * (B.ray_off[p] - B.ray_base);
+    const long chunk_ray0 = B.ray_off[p] - B.ray_base;
+    for (long r0 = first; r0 < last; r0 += blockDim.x) {
+      const long id = r0 + threadIdx.x;
+      bool redo = false;
+      if (id < last) {
+        for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
+        RecordSink<G> sink{rec, rbase, NN, id, P.k, P.amplif_limit, false};
+        const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
+        trace_ray<G>(P, ix, iy, sink);
+        redo = sink.need64;
+      }
+      if (sizeof(G) == 4) {
+        // rays whose divergence factor is ill-conditioned in FP32 are listed
+        // for the FP64 pass (one append per wave)
+        const unsigned long long mask = __ballot(redo);
+        if (mask) {
+          const int lane = threadIdx.x & 63, leader = __ffsll((long long)mask) - 1;
+          unsigned base = 0;
+          if (lane == leader) base = atomicAdd(rec.n_fp64, (unsigned)__popcll(mask));
+          base = __shfl(base, leader);
+          if (redo) rec.redo_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int)(chunk_ray0 + id);
+        }
+      }
     }
   }
 }
 
 // FP64 re-trace of the listed rays, writing into the FP32 records.  A fixed
 // grid strides over the list, whose length is only known on the device.
-__global__ void __launch_bounds__(256) k_retrace64(const ParticleConst P, const Records<float> rec) {
+__global__ void __launch_bounds__(256) k_retrace64(const BatchDev B, const Records<float> rec) {
   const unsigned n = *rec.n_fp64;
-  const int n_ord = P.p_max - P.p_min + 1;
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const long id = rec.redo_list[i];
-    for (int o = 0; o < n_ord; ++o) rec.flags[o * rec.NN + id] = 0;
-    RecordSink<float> sink{rec, id, P.k, 0.0, false};
+    const long g = rec.redo_list[i];
+    const int p = find_part(B.ray_off, B.n, B.ray_base, g);
+    const ParticleConst& P = B.P[p];
+    const long NN = (long)P.N * P.N;
+    const long id = g - (B.ray_off[p] - B.ray_base);
+    const long rbase = B.n_ord * (B.ray_off[p] - B.ray_base);
+    for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
+    RecordSink<float> sink{rec, rbase, NN, id, P.k, 0.0, false};
     const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
     trace_ray<double>(P, ix, iy, sink);
   }
@@ -238,10 +292,13 @@ __global__ void __launch_bounds__(256) k_trace_diag(const ParticleConst P, const
   }
 }
 
-// Node tables from the degree lists, reset of the hit pool, workspace header.
+// Node tables from the degree lists, workspace header and counters (once per
+// call).  With P1 != nullptr the call has one particle, whose metadata is
+// written here from the kernel arguments (no host upload).
 __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg, double* th,
-                        double* ph, double* sth, double* cth, double* sph, double* cph, int* head, int n_nodes,
-                        unsigned* counter, WsHeader* hdr, WsHeader hv) {
+                        double* ph, double* sth, double* cth, double* sph, double* cph, unsigned* counter,
+                        WsHeader* hdr, WsHeader hv, ParticleConst* meta_P, long* meta_off, int* meta_out,
+                        ParticleConst P1, int tile, int one) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const double D2R = 3.14159265358979323846 / 180.0;
   if (i < n_theta) {
@@ -256,9 +313,52 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
     sph[i] = sin(p);
     cph[i] = cos(p);
   }
-  if (i < n_nodes) head[i] = -1;
-  if (i <= NPART + 1) counter[i] = 0u;
-  if (i == 0) *hdr = hv;
+  if (i < C_COUNT) counter[i] = 0u;
+  if (i == 0) {
+    *hdr = hv;
+    if (one) {
+      const long NN = (long)P1.N * P1.N, nq = (long)(P1.N - 1) * (P1.N - 1);
+      meta_P[0] = P1;
+      meta_off[0] = 0; meta_off[1] = NN;                    // rays
+      meta_off[2] = 0; meta_off[3] = nq;                    // quads
+      meta_off[4] = 0; meta_off[5] = (NN + tile - 1) / tile;  // trace items
+      meta_out[0] = 0;
+    }
+  }
+}
+
+// Reset of the per-chunk state: node lists and per-chunk counters.
+__global__ void k_chunk_reset(int* head, long n_heads, unsigned* counter) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_heads) head[i] = -1;
+  if (i <= C_QUEUE) counter[i] = 0u;
+}
+
+// End of a chunk: fullest partition (overflow check), hit and FP64 totals.
+__global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter) {
+  __shared__ unsigned mx[1024];
+  __shared__ unsigned long long sm[1024];
+  unsigned m = 0;
+  unsigned long long sum = 0;
+  for (int i = threadIdx.x; i < NPART; i += blockDim.x) {
+    m = max(m, counter[i]);
+    sum += counter[i];
+  }
+  mx[threadIdx.x] = m;
+  sm[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + w]);
+      sm[threadIdx.x] += sm[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&counter[C_NEED], mx[0]);
+    atomicAdd((unsigned long long*)&counter[C_HITS], sm[0]);
+    atomicAdd(&counter[C_FP64_TOTAL], counter[C_REDO]);
+  }
 }
 
 constexpr int ROWS_CAP = 1 << 24;  // (triangle, row) items of large triangles
@@ -323,37 +423,58 @@ __global__ void __launch_bounds__(256) k_axis_segments(const double* th, int n_t
   }
 }
 
-// Workspace layout of rtw_farfield.
+// Triangle keys (order slot, quad, half) are 32-bit: 2 n_ord (N-1)^2 < 2^31.
+int check_keys(const rtw_trace_opts* o) {
+  const long nq = (long)(o->grid_n - 1) * (o->grid_n - 1);
+  if (2L * (o->p_max - o->p_min + 1) * nq >= (1L << 31))
+    return fail(RTW_ERR_UNSUPPORTED, "far field needs 2 (p_max - p_min + 1) (grid_n - 1)^2 < 2^31");
+  return RTW_OK;
+}
+
+// Workspace layout (256-byte aligned sections).  Record arrays are sized for
+// the largest chunk; metadata for every particle of the call.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, flags, rr, ang, head, redo, rows, link, contrib, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, mP, moff, mout, flags, rr, ang, head, redo, rows, link,
+      contrib, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
 
-Layout layout(const ParticleConst& P, int precision, int n_theta, int n_phi, long cap_total) {
+struct Shape {
+  int precision, n_pol, n_ord;
+  int n_theta, n_phi;
+  int n_parts;          // particles of the call
+  long max_chunk_rays;  // incident rays of the largest chunk
+  int max_chunk_parts;  // particles of the largest chunk
+};
+
+Layout layout(const Shape& S, long cap_total) {
   Layout L;
-  const size_t gs = precision == RTW_FP64 ? 8 : 4;
-  const long NN = (long)P.N * P.N;
-  const int n_ord = P.p_max - P.p_min + 1;
-  const long n_nodes = (long)n_theta * n_phi;
+  const size_t gs = S.precision == RTW_FP64 ? 8 : 4;
+  const size_t rr = S.precision == RTW_FP64 ? sizeof(RayRec<double>) : sizeof(RayRec<float>);
+  const long n_nodes = (long)S.n_theta * S.n_phi;
+  const size_t nrec = (size_t)S.n_ord * S.max_chunk_rays;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
   L.hdr = take(sizeof(WsHeader));
-  L.counter = take(sizeof(unsigned) * (NPART + 2));  // hit-pool partitions, FP64 re-trace count, row-list count
-  L.th = take(8 * n_theta); L.ph = take(8 * n_phi);
-  L.sth = take(8 * n_theta); L.cth = take(8 * n_theta);
-  L.sph = take(8 * n_phi); L.cph = take(8 * n_phi);
+  L.counter = take(sizeof(unsigned) * C_COUNT);
+  L.th = take(8 * S.n_theta); L.ph = take(8 * S.n_phi);
+  L.sth = take(8 * S.n_theta); L.cth = take(8 * S.n_theta);
+  L.sph = take(8 * S.n_phi); L.cph = take(8 * S.n_phi);
   L.seg = take(2 * sizeof(AxisSeg));
-  L.flags = take(4 * (size_t)n_ord * NN);
-  L.rr = take((precision == RTW_FP64 ? sizeof(RayRec<double>) : sizeof(RayRec<float>)) * (size_t)n_ord * NN);
-  L.ang = take(sizeof(float2) * (size_t)n_ord * NN);
-  L.head = take(4 * (size_t)n_nodes);
-  L.redo = take(precision == RTW_FP64 ? 4 : 4 * (size_t)NN);
+  L.mP = take(sizeof(ParticleConst) * (size_t)S.n_parts);
+  L.moff = take(sizeof(long) * 3 * (size_t)(S.n_parts + 1));
+  L.mout = take(sizeof(int) * (size_t)S.n_parts);
+  L.flags = take(4 * nrec);
+  L.rr = take(rr * nrec);
+  L.ang = take(sizeof(float2) * nrec);
+  L.head = take(4 * (size_t)S.max_chunk_parts * n_nodes);
+  L.redo = take(S.precision == RTW_FP64 ? 4 : 4 * (size_t)S.max_chunk_rays);
   L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
   L.fixed = off;
-  L.bytes_per_hit = sizeof(int2) + gs * 4 * P.n_pol;
+  L.bytes_per_hit = sizeof(int2) + gs * 4 * S.n_pol;
   L.link = take(sizeof(int2) * (size_t)cap_total);
-  L.contrib = take(gs * 4 * P.n_pol * (size_t)cap_total);
+  L.contrib = take(gs * 4 * S.n_pol * (size_t)cap_total);
   L.total = off;
   return L;
 }
@@ -366,34 +487,133 @@ long cap_from_bytes(const Layout& base, size_t bytes) {
   return per;
 }
 
-// Triangle keys (order slot, quad, half) are 32-bit: 2 n_ord (N-1)^2 < 2^31.
-int check_keys(const rtw_trace_opts* o) {
-  const long nq = (long)(o->grid_n - 1) * (o->grid_n - 1);
-  if (2L * (o->p_max - o->p_min + 1) * nq >= (1L << 31))
-    return fail(RTW_ERR_UNSUPPORTED, "far field needs 2 (p_max - p_min + 1) (grid_n - 1)^2 < 2^31");
-  return RTW_OK;
-}
-
 int check_grid(const rtw_grid* g) {
   if (!g) return fail(RTW_ERR_INVALID_ARG, "NULL grid");
   if (g->n_theta < 1 || g->n_phi < 1 || !g->theta_deg || !g->phi_deg)
     return fail(RTW_ERR_INVALID_ARG, "empty node grid");
+  if (g->n_theta > 65535 || g->n_phi > 65535) return fail(RTW_ERR_INVALID_ARG, "node grid sides must be < 65536");
   if ((long)g->n_theta * g->n_phi > (1L << 30)) return fail(RTW_ERR_INVALID_ARG, "node grid too large");
   return RTW_OK;
 }
 
+// Launch order, chunks and per-particle metadata of a call.
+struct Plan {
+  Shape S;
+  std::vector<ParticleConst> P;  // launch order
+  std::vector<long> ray_off, quad_off, tile_off;
+  std::vector<int> out_index;
+  std::vector<std::pair<int, int>> chunks;  // [first, last) in launch order
+  int tile;
+};
+
+constexpr long DEFAULT_RAYS_PER_CHUNK = 1L << 26;
+constexpr double DEFAULT_HITS_PER_NODE = 6.0;
+
+// Largest particles first (LPT); chunks are filled greedily up to the ray
+// budget (a larger particle is a chunk of its own).  Every chunk keeps its
+// 32-bit triangle keys and record indices in range.
+int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+              const rtw_trace_opts* opts, const rtw_grid* grid, long rays_per_chunk, int tile, Plan& pl) {
+  if (n < 1 || !parts || !grid_n) return fail(RTW_ERR_INVALID_ARG, "need n >= 1 particles and grid sides");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  const int n_ord = opts ? opts->p_max - opts->p_min + 1 : 0;
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) {
+    rtw_trace_opts o = *opts;
+    o.grid_n = grid_n[i];
+    rc = check_particle(&parts[i], inc, &o);
+    if (rc) return fail(rc, "particle %d: %s", i, g_err.c_str());
+    idx[i] = i;
+  }
+  const long key_limit = (1L << 30) / n_ord;  // chunk rays: 2 n_ord quads < 2^31
+  for (int i = 0; i < n; ++i)
+    if ((long)grid_n[i] * grid_n[i] > key_limit)
+      return fail(RTW_ERR_UNSUPPORTED, "particle %d: n_ord grid_n^2 must stay below 2^30", i);
+  if (rays_per_chunk <= 0) rays_per_chunk = DEFAULT_RAYS_PER_CHUNK;
+  rays_per_chunk = std::min(rays_per_chunk, key_limit);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return grid_n[a] > grid_n[b]; });
+  pl.tile = tile;
+  pl.P.resize(n);
+  pl.out_index.resize(n);
+  pl.ray_off.assign(n + 1, 0);
+  pl.quad_off.assign(n + 1, 0);
+  pl.tile_off.assign(n + 1, 0);
+  for (int j = 0; j < n; ++j) {
+    const int i = idx[j];
+    rtw_trace_opts o = *opts;
+    o.grid_n = grid_n[i];
+    pl.P[j] = make_const(&parts[i], inc, &o);
+    pl.out_index[j] = i;
+    const long NN = (long)grid_n[i] * grid_n[i];
+    pl.ray_off[j + 1] = pl.ray_off[j] + NN;
+    pl.quad_off[j + 1] = pl.quad_off[j] + (long)(grid_n[i] - 1) * (grid_n[i] - 1);
+    pl.tile_off[j + 1] = pl.tile_off[j] + (NN + tile - 1) / tile;
+  }
+  pl.S.precision = opts->precision;
+  pl.S.n_pol = inc->n_pol;
+  pl.S.n_ord = n_ord;
+  pl.S.n_theta = grid->n_theta;
+  pl.S.n_phi = grid->n_phi;
+  pl.S.n_parts = n;
+  pl.S.max_chunk_rays = 0;
+  pl.S.max_chunk_parts = 0;
+  int c0 = 0;
+  while (c0 < n) {
+    int c1 = c0 + 1;
+    while (c1 < n && c1 - c0 < 65535 && pl.ray_off[c1 + 1] - pl.ray_off[c0] <= rays_per_chunk) ++c1;
+    pl.chunks.push_back({c0, c1});
+    pl.S.max_chunk_rays = std::max(pl.S.max_chunk_rays, pl.ray_off[c1] - pl.ray_off[c0]);
+    pl.S.max_chunk_parts = std::max(pl.S.max_chunk_parts, c1 - c0);
+    c0 = c1;
+  }
+  return RTW_OK;
+}
+
+struct Tuning {
+  int tile, blocks_per_cu, cand_inline;
+};
+
+Tuning tuning_of(const rtw_tune* t) {
+  Tuning u{1024, 8, CAND_INLINE};
+  if (t) {
+    if (t->tile_rays > 0) u.tile = t->tile_rays;
+    if (t->blocks_per_cu > 0) u.blocks_per_cu = t->blocks_per_cu;
+    if (t->cand_inline > 0) u.cand_inline = t->cand_inline;
+  }
+  return u;
+}
+
+int check_tuning(const Tuning& u) {
+  if (u.tile % 256 != 0 || u.tile > (1 << 20)) return fail(RTW_ERR_INVALID_ARG, "tile_rays must be a multiple of 256");
+  if (u.blocks_per_cu > 64) return fail(RTW_ERR_INVALID_ARG, "blocks_per_cu must be at most 64");
+  if (u.cand_inline > 4096) return fail(RTW_ERR_INVALID_ARG, "cand_inline must be at most 4096");
+  return RTW_OK;
+}
+
+int compute_units() {
+  static int cu = 0;
+  if (cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
+  }
+  return cu;
+}
+
+// Queue every kernel of a call on the stream.  With one_meta the single
+// particle's metadata is written by k_setup; otherwise the caller uploaded it.
 template <typename G>
-int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid, void* out, int32_t* ncontrib,
-                    char* ws, size_t ws_bytes, hipStream_t st) {
-  const long NN = (long)P.N * P.N;
-  const int n_ord = P.p_max - P.p_min + 1;
+int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* out, int32_t* ncontrib, char* ws,
+                size_t ws_bytes, hipStream_t st, bool one_meta) {
+  const Shape& S = pl.S;
   const int n_nodes = grid->n_theta * grid->n_phi;
-  Layout base = layout(P, precision, grid->n_theta, grid->n_phi, 0);
+  Layout base = layout(S, 0);
   long cap_part = cap_from_bytes(base, ws_bytes);
   if (cap_part < 1) return fail(RTW_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu-byte minimum",
                                 ws_bytes, base.fixed + base.bytes_per_hit * NPART + 512);
   if (cap_part > (1L << 30) / NPART) cap_part = (1L << 30) / NPART;
-  Layout L = layout(P, precision, grid->n_theta, grid->n_phi, cap_part * NPART);
+  Layout L = layout(S, cap_part * NPART);
   if (L.total > ws_bytes) return fail(RTW_ERR_WORKSPACE, "internal layout exceeds workspace");
 
   WsHeader hv;
@@ -411,51 +631,111 @@ int launch_farfield(const ParticleConst& P, int precision, const rtw_grid* grid,
   ng.sph = (double*)(ws + L.sph); ng.cph = (double*)(ws + L.cph);
   ng.seg_t = (const AxisSeg*)(ws + L.seg);
   ng.seg_p = (const AxisSeg*)(ws + L.seg) + 1;
+  unsigned* counter = (unsigned*)(ws + L.counter);
   Records<G> rec;
   rec.flags = (int32_t*)(ws + L.flags);
   rec.rr = (RayRec<G>*)(ws + L.rr);
   rec.ang = (float2*)(ws + L.ang);
-  rec.NN = NN;
-  rec.n_pol = P.n_pol;
-  rec.n_fp64 = (unsigned*)(ws + L.counter) + NPART;
+  rec.n_pol = S.n_pol;
+  rec.n_fp64 = counter + C_REDO;
   rec.redo_list = (int*)(ws + L.redo);
   HitPool<G> pool;
   pool.head = (int*)(ws + L.head);
   pool.link = (int2*)(ws + L.link);
   pool.contrib = (G*)(ws + L.contrib);
-  pool.counter = (unsigned*)(ws + L.counter);
+  pool.counter = counter;
   pool.cap_part = (int)cap_part;
   pool.rows = (int2*)(ws + L.rows);
-  pool.n_rows = (unsigned*)(ws + L.counter) + NPART + 1;
+  pool.n_rows = counter + C_ROWS;
   pool.rows_cap = ROWS_CAP;
 
-  long setup_n = std::max<long>({(long)n_nodes, (long)grid->n_theta, (long)grid->n_phi, (long)NPART + 2});
+  ParticleConst* mP = (ParticleConst*)(ws + L.mP);
+  long* moff = (long*)(ws + L.moff);
+  int* mout = (int*)(ws + L.mout);
+  const int n = S.n_parts;
+  long* m_ray = moff;
+  long* m_quad = moff + (n + 1);
+  long* m_tile = moff + 2 * (n + 1);
+  if (one_meta) { m_ray = moff; m_quad = moff + 2; m_tile = moff + 4; }
+
+  long setup_n = std::max<long>({(long)grid->n_theta, (long)grid->n_phi, (long)C_COUNT});
   { ProfScope ps("k_setup", st);
   hipLaunchKernelGGL(k_setup, dim3((unsigned)((setup_n + 255) / 256)), dim3(256), 0, st, grid->n_theta,
                      grid->theta_deg, grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth,
-                     (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, pool.head, n_nodes, pool.counter,
-                     (WsHeader*)(ws + L.hdr), hv);
+                     (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, counter, (WsHeader*)(ws + L.hdr), hv, mP,
+                     moff, mout, pl.P[0], pl.tile, one_meta ? 1 : 0);
   hipLaunchKernelGGL(k_axis_segments, dim3(2), dim3(256), 0, st, ng.th, ng.n_theta, ng.ph, ng.n_phi,
                      (AxisSeg*)(ws + L.seg), (AxisSeg*)(ws + L.seg) + 1); }
-  { ProfScope ps(precision == RTW_FP64 ? "k_trace_fp64" : "k_trace_mixed", st);
-  hipLaunchKernelGGL(k_trace<G>, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, P, rec); }
-  if (precision == RTW_MIXED) {
-    ProfScope ps("k_retrace64", st);
-    hipLaunchKernelGGL(k_retrace64, dim3((unsigned)std::min<long>(2048, (NN + 255) / 256)), dim3(256), 0, st, P,
-                       *reinterpret_cast<Records<float>*>(&rec));
+
+  const bool fp64 = S.precision == RTW_FP64;
+  const int cu = compute_units();
+  for (const auto& ch : pl.chunks) {
+    const int c0 = ch.first, c1 = ch.second, nc = c1 - c0;
+    BatchDev B;
+    B.n = nc;
+    B.n_ord = S.n_ord;
+    B.P = mP + c0;
+    B.ray_off = m_ray + c0;
+    B.quad_off = m_quad + c0;
+    B.tile_off = m_tile + c0;
+    B.out_index = mout + c0;
+    B.ray_base = pl.ray_off[c0];
+    B.quad_base = pl.quad_off[c0];
+    B.tile_base = pl.tile_off[c0];
+    B.tile = pl.tile;
+    const long rays = pl.ray_off[c1] - pl.ray_off[c0];
+    const long quads = pl.quad_off[c1] - pl.quad_off[c0];
+    const long items = pl.tile_off[c1] - pl.tile_off[c0];
+    const long n_heads = (long)nc * n_nodes;
+    hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_heads, C_COUNT) + 255) / 256)), dim3(256),
+                       0, st, pool.head, n_heads, counter);
+    { ProfScope ps(fp64 ? "k_trace_fp64" : "k_trace_mixed", st);
+    const long grid_t = std::min<long>(items, (long)cu * tu.blocks_per_cu);
+    hipLaunchKernelGGL(k_trace_tiles<G>, dim3((unsigned)grid_t), dim3(256), 0, st, B, rec, counter + C_QUEUE); }
+    if (!fp64) {
+      ProfScope ps("k_retrace64", st);
+      hipLaunchKernelGGL(k_retrace64, dim3((unsigned)std::min<long>(2048, (rays + 255) / 256)), dim3(256), 0, st, B,
+                         *reinterpret_cast<Records<float>*>(&rec));
+    }
+    { ProfScope ps(fp64 ? "k_raster_fp64" : "k_raster_mixed", st);
+    hipLaunchKernelGGL(k_raster<G>, dim3((unsigned)((quads + 255) / 256), S.n_ord), dim3(256), 0, st, B, rec, ng,
+                       pool, BOX_MARGIN, tu.cand_inline); }
+    { ProfScope ps(fp64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
+    hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
+    { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
+    hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_heads + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
+                       S.n_pol, (G*)out, ncontrib); }
+    hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter);
   }
-  const long nquad = (long)(P.N - 1) * (P.N - 1);
-  { ProfScope ps(precision == RTW_FP64 ? "k_raster_fp64" : "k_raster_mixed", st);
-  hipLaunchKernelGGL(k_raster<G>, dim3((unsigned)((nquad + 255) / 256), n_ord), dim3(256), 0, st, P, rec, ng, pool,
-                     BOX_MARGIN); }
-  { ProfScope ps(precision == RTW_FP64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
-  hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, P, rec, ng, pool, BOX_MARGIN); }
-  { ProfScope ps(precision == RTW_FP64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
-  hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, st, pool, n_nodes,
-                     P.n_pol, (G*)out, ncontrib); }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return RTW_OK;
+}
+
+// Upload of the plan's metadata into the workspace (synchronises the stream:
+// the host copy must outlive the transfer).
+int upload_plan(const Plan& pl, const Layout& L, char* ws, hipStream_t st) {
+  const int n = pl.S.n_parts;
+  std::vector<long> off(3 * (size_t)(n + 1));
+  std::copy(pl.ray_off.begin(), pl.ray_off.end(), off.begin());
+  std::copy(pl.quad_off.begin(), pl.quad_off.end(), off.begin() + (n + 1));
+  std::copy(pl.tile_off.begin(), pl.tile_off.end(), off.begin() + 2 * (n + 1));
+  hipError_t e = hipMemcpyAsync(ws + L.mP, pl.P.data(), sizeof(ParticleConst) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.moff, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.mout, pl.out_index.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "metadata upload failed: %s", hipGetErrorString(e));
+  return RTW_OK;
+}
+
+size_t plan_bytes(const Plan& pl, double hits_per_node) {
+  if (!(hits_per_node > 0.0)) hits_per_node = DEFAULT_HITS_PER_NODE;
+  const long n_nodes = (long)pl.S.n_theta * pl.S.n_phi;
+  long cap_part = (long)std::ceil(hits_per_node * (double)n_nodes * pl.S.max_chunk_parts / NPART) + 256;
+  cap_part = std::min(cap_part, (1L << 30) / NPART);
+  return layout(pl.S, cap_part * NPART).total + 512;
 }
 
 }  // namespace
@@ -503,7 +783,7 @@ int rtw_profile_read(int max_kernels, char* names, double* total_ms, int* launch
   return rc;
 }
 
-const char* rtw_version(void) { return "rtw-mi355x 0.1 (gfx950)"; }
+const char* rtw_version(void) { return "rtw-mi355x 0.2 (gfx950)"; }
 
 int rtw_trace(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
               const rtw_ray_records* out, void* hip_stream) {
@@ -524,44 +804,148 @@ int rtw_trace(const rtw_particle* part, const rtw_incident* inc, const rtw_trace
 
 int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
                                 const rtw_grid* grid, double hits_per_node, size_t* bytes) {
+  if (!bytes) return fail(RTW_ERR_INVALID_ARG, "NULL bytes");
+  if (!opts) return fail(RTW_ERR_INVALID_ARG, "NULL argument struct");
   int rc = check_particle(part, inc, opts);
   if (rc) return rc;
-  if (!bytes) return fail(RTW_ERR_INVALID_ARG, "NULL bytes");
-  if (!grid || grid->n_theta < 1 || grid->n_phi < 1) return fail(RTW_ERR_INVALID_ARG, "empty node grid");
   rc = check_keys(opts);
   if (rc) return rc;
-  if (!(hits_per_node > 0.0)) hits_per_node = 6.0;
-  ParticleConst P = make_const(part, inc, opts);
-  const long n_nodes = (long)grid->n_theta * grid->n_phi;
-  long cap_part = (long)std::ceil(hits_per_node * (double)n_nodes / NPART) + 256;
-  Layout L = layout(P, opts->precision, grid->n_theta, grid->n_phi, cap_part * NPART);
-  *bytes = L.total + 512;
+  Plan pl;
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tuning_of(nullptr).tile, pl);
+  if (rc) return rc;
+  *bytes = plan_bytes(pl, hits_per_node);
   return RTW_OK;
 }
 
 int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
                  const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* workspace, size_t workspace_bytes,
                  void* hip_stream) {
+  if (!opts) return fail(RTW_ERR_INVALID_ARG, "NULL argument struct");
   int rc = check_particle(part, inc, opts);
-  if (rc) return rc;
-  rc = check_grid(grid);
   if (rc) return rc;
   rc = check_keys(opts);
   if (rc) return rc;
   if (!out_field || !workspace) return fail(RTW_ERR_INVALID_ARG, "NULL output or workspace");
   if (((uintptr_t)workspace & 255) != 0) return fail(RTW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  ParticleConst P = make_const(part, inc, opts);
+  const Tuning tu = tuning_of(nullptr);
+  Plan pl;
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, pl);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   if (opts->precision == RTW_FP64)
-    return launch_farfield<double>(P, RTW_FP64, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st);
-  return launch_farfield<float>(P, RTW_MIXED, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st);
+    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, true);
+  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, true);
+}
+
+int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+                             const rtw_trace_opts* opts, const rtw_grid* grid, const rtw_batch_opts* bopts,
+                             size_t* bytes) {
+  if (!bytes || !opts || !inc) return fail(RTW_ERR_INVALID_ARG, "NULL argument");
+  Plan pl;
+  int rc = make_plan(n, parts, grid_n, inc, opts, grid, bopts ? (long)bopts->rays_per_chunk : 0,
+                     tuning_of(nullptr).tile, pl);
+  if (rc) return rc;
+  *bytes = plan_bytes(pl, bopts ? bopts->hits_per_node : 0.0);
+  return RTW_OK;
+}
+
+int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib,
+              const rtw_tune* tune, const rtw_batch_opts* bopts, void* workspace, size_t workspace_bytes,
+              void* hip_stream) {
+  if (!opts || !inc) return fail(RTW_ERR_INVALID_ARG, "NULL argument struct");
+  if (!out_field || !workspace) return fail(RTW_ERR_INVALID_ARG, "NULL output or workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(RTW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const Tuning tu = tuning_of(tune);
+  int rc = check_tuning(tu);
+  if (rc) return rc;
+  Plan pl;
+  rc = make_plan(n, parts, grid_n, inc, opts, grid, bopts ? (long)bopts->rays_per_chunk : 0, tu.tile, pl);
+  if (rc) return rc;
+  Layout base = layout(pl.S, 0);
+  if (workspace_bytes < base.fixed + base.bytes_per_hit * NPART + 512)
+    return fail(RTW_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu-byte minimum", workspace_bytes,
+                base.fixed + base.bytes_per_hit * NPART + 512);
+  hipStream_t st = (hipStream_t)hip_stream;
+  rc = upload_plan(pl, base, (char*)workspace, st);
+  if (rc) return rc;
+  if (opts->precision == RTW_FP64)
+    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, false);
+  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, false);
+}
+
+int rtw_batch_autotune(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
+                       const rtw_trace_opts* opts, const rtw_grid* grid, const rtw_batch_opts* bopts,
+                       void* out_field, void* workspace, size_t workspace_bytes, void* hip_stream, rtw_tune* best) {
+  if (!best) return fail(RTW_ERR_INVALID_ARG, "NULL result");
+  if (n < 1 || !parts || !grid_n) return fail(RTW_ERR_INVALID_ARG, "need n >= 1 particles");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // Sample: every k-th particle in size order, at most 64, so that the trial
+  // runs see the batch's mix of sizes.
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return grid_n[a] > grid_n[b]; });
+  const int m = std::min(n, 64);
+  std::vector<rtw_particle> sp(m);
+  std::vector<int> sg(m);
+  for (int j = 0; j < m; ++j) {
+    const int i = idx[(long)j * n / m];
+    sp[j] = parts[i];
+    sg[j] = grid_n[i];
+  }
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(RTW_ERR_DEVICE, "event creation failed");
+  auto trial = [&](const rtw_tune& t, float* ms) -> int {
+    int rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, &t, bopts, workspace,
+                       workspace_bytes, st);  // warm-up and upload
+    if (rc) return rc;
+    hipEventRecord(a, st);
+    rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, &t, bopts, workspace,
+                   workspace_bytes, st);
+    if (rc) return rc;
+    hipEventRecord(b, st);
+    if (hipEventSynchronize(b) != hipSuccess) return fail(RTW_ERR_DEVICE, "event wait failed");
+    hipEventElapsedTime(ms, a, b);
+    return rtw_farfield_status(workspace, hip_stream, nullptr);
+  };
+  // coordinate search: trace tile and persistence, then the binning threshold
+  rtw_tune cur{1024, 8, CAND_INLINE};
+  float best_ms = 0.f;
+  int rc = trial(cur, &best_ms);
+  const int tiles[] = {256, 512, 1024, 2048, 4096};
+  const int bpcs[] = {4, 8, 16};
+  const int cands[] = {8, 16, 32, 64, 128};
+  for (int t : tiles)
+    for (int bp : bpcs) {
+      if (rc) break;
+      rtw_tune c{t, bp, cur.cand_inline};
+      if (t == cur.tile_rays && bp == cur.blocks_per_cu) continue;
+      float ms = 0.f;
+      rc = trial(c, &ms);
+      if (!rc && ms < best_ms) { best_ms = ms; cur = c; }
+    }
+  rtw_tune base = cur;
+  for (int c : cands) {
+    if (rc) break;
+    if (c == base.cand_inline) continue;
+    rtw_tune t{base.tile_rays, base.blocks_per_cu, c};
+    float ms = 0.f;
+    rc = trial(t, &ms);
+    if (!rc && ms < best_ms) { best_ms = ms; cur = t; }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (rc) return rc;
+  *best = cur;
+  return RTW_OK;
 }
 
 int rtw_farfield_stats(const void* workspace, void* hip_stream, uint64_t* hits, uint64_t* fp64_rays) {
   if (!workspace) return fail(RTW_ERR_INVALID_ARG, "NULL workspace");
   hipStream_t st = (hipStream_t)hip_stream;
   WsHeader h;
-  unsigned cnt[NPART + 2];
+  unsigned cnt[C_COUNT];
   hipError_t e = hipMemcpyAsync(&h, workspace, sizeof(h), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(cnt, (const char*)workspace + align256(sizeof(WsHeader)), sizeof(cnt), hipMemcpyDeviceToHost,
@@ -570,9 +954,9 @@ int rtw_farfield_stats(const void* workspace, void* hip_stream, uint64_t* hits, 
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "stats read failed: %s", hipGetErrorString(e));
   if (h.magic != WS_MAGIC) return fail(RTW_ERR_INVALID_ARG, "workspace was not used by rtw_farfield");
   uint64_t tot = 0;
-  for (int i = 0; i < NPART; ++i) tot += cnt[i];
+  std::memcpy(&tot, &cnt[C_HITS], sizeof(tot));
   if (hits) *hits = tot;
-  if (fp64_rays) *fp64_rays = cnt[NPART];
+  if (fp64_rays) *fp64_rays = cnt[C_FP64_TOTAL];
   return RTW_OK;
 }
 
@@ -580,7 +964,7 @@ int rtw_farfield_status(const void* workspace, void* hip_stream, size_t* bytes_n
   if (!workspace) return fail(RTW_ERR_INVALID_ARG, "NULL workspace");
   hipStream_t st = (hipStream_t)hip_stream;
   WsHeader h;
-  unsigned cnt[NPART];
+  unsigned cnt[C_COUNT];
   hipError_t e = hipMemcpyAsync(&h, workspace, sizeof(h), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "status read failed: %s", hipGetErrorString(e));
@@ -589,8 +973,7 @@ int rtw_farfield_status(const void* workspace, void* hip_stream, size_t* bytes_n
   e = hipMemcpyAsync(cnt, (const char*)workspace + align256(sizeof(WsHeader)), sizeof(cnt), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "status read failed: %s", hipGetErrorString(e));
-  unsigned mx = 0;
-  for (int i = 0; i < NPART; ++i) mx = std::max(mx, cnt[i]);
+  const unsigned mx = cnt[C_NEED];
   if (bytes_needed) {
     size_t per = (size_t)mx + (mx >> 2) + 64;
     *bytes_needed = (size_t)h.fixed_bytes + per * NPART * h.bytes_per_hit + 1024;

@@ -59,16 +59,43 @@ struct alignas(16) RayRec {
   G f[12];    // [pol][xyz][re|im] lab field amp e^{i phase} (J_perp e_perp + J_par e_par)
 };
 
+// Emission records of the particles of one chunk: particle p owns the index
+// range [n_ord (ray_off[p] - ray_base), ... + n_ord N_p^2), laid out
+// [order slot][ray], so that record (p, slot, ray) is at rb(p, slot) + ray.
 template <typename G>
 struct Records {
-  int32_t* flags;  // [n_ord][NN]  bit0 valid, bits 1..7 nf, bit 8 det_neg
-  RayRec<G>* rr;   // [n_ord][NN]
-  float2* ang;     // [n_ord][NN]  (theta, phi) of the exit direction (rad), phi in [0, 2 pi)
-  long NN;
+  int32_t* flags;  // bit0 valid, bits 1..7 nf, bit 8 det_neg
+  RayRec<G>* rr;
+  float2* ang;     // (theta, phi) of the exit direction (rad), phi in [0, 2 pi)
   int n_pol;
-  unsigned* n_fp64;  // rays re-traced in FP64 (mixed path)
-  int* redo_list;    // their ray indices
+  unsigned* n_fp64;  // rays listed for the FP64 re-trace (mixed path)
+  int* redo_list;    // their chunk ray indices
 };
+
+// The particles of one launch (a chunk of a batch, or one particle).  Offsets
+// are prefix sums over the whole batch in batch-launch order; subtracting the
+// chunk's base gives chunk-local values.
+struct BatchDev {
+  int n;                    // particles in the chunk
+  int n_ord;                // orders p_min..p_max
+  const ParticleConst* P;   // [n]
+  const long* ray_off;      // [n + 1] first incident ray of each particle (N^2 rays each)
+  const long* quad_off;     // [n + 1] first grid quad ((N - 1)^2 quads each)
+  const long* tile_off;     // [n + 1] first trace work item (ceil(N^2 / tile) each)
+  const int* out_index;     // [n] position of each particle in the caller's output
+  long ray_base, quad_base, tile_base;
+  int tile;                 // incident rays per trace work item
+};
+
+// Largest p in [0, n) with off[p] - base <= x (off non-decreasing, x >= 0).
+__device__ __forceinline__ int find_part(const long* off, int n, long base, long x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] - base <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 template <typename G>
 struct HitPool {
@@ -82,7 +109,7 @@ struct HitPool {
   int rows_cap;
 };
 
-constexpr int CAND_INLINE = 32;  // triangles with more box candidates go to the row list
+constexpr int CAND_INLINE = 32;  // default: triangles with more box candidates go to the row list
 // Angular margin (rad) of the FP32 bounding box: well above its rounding error,
 // so the box never excludes a node that the exact membership test accepts.
 constexpr double BOX_MARGIN = 4e-6;
@@ -93,6 +120,8 @@ constexpr double BOX_MARGIN = 4e-6;
 template <typename G>
 struct RecordSink {
   Records<G> rec;
+  long base;  // record index of (this particle, slot 0, ray 0)
+  long NN;    // rays of this particle
   long id;
   double k;
   double amplif_limit;
@@ -100,22 +129,35 @@ struct RecordSink {
   template <typename E>
   __device__ void emit(const Emission<E>& e) {
     if (sizeof(E) == 4 && e.amplif > amplif_limit) need64 = true;
-    const long NN = rec.NN;
-    rec.flags[e.slot * NN + id] = 1 | (e.nf << 1) | (e.det_neg << 8);
+    const long at = base + e.slot * NN + id;
+    rec.flags[at] = 1 | (e.nf << 1) | (e.det_neg << 8);
     RayRec<G> r;
     r.dir[0] = (G)e.dir.x; r.dir[1] = (G)e.dir.y; r.dir[2] = (G)e.dir.z;
     r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
+    // The field's phase contains -k dir.r_exit and the rasteriser carries it
+    // with k r_exit.(dir - n) using the stored direction, so the two must use
+    // the same direction.  An FP64 emission stored in FP32 records is turned
+    // to the rounded direction: phase += k r_exit.(dir - (G)dir), in FP64
+    // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
+    double cre = 1.0, cim = 0.0;
+    if (sizeof(E) > sizeof(G)) {
+      const double dpx = (double)e.dir.x - (double)r.dir[0], dpy = (double)e.dir.y - (double)r.dir[1],
+                   dpz = (double)e.dir.z - (double)r.dir[2];
+      const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz);
+      sincos(dphi, &cim, &cre);
+    }
     for (int p = 0; p < 2; ++p)
       for (int x = 0; x < 3; ++x) {
-        r.f[(p * 3 + x) * 2 + 0] = p < rec.n_pol ? (G)e.f[p][x].re : (G)0;
-        r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)e.f[p][x].im : (G)0;
+        const double fr = (double)e.f[p][x].re, fi = (double)e.f[p][x].im;
+        r.f[(p * 3 + x) * 2 + 0] = p < rec.n_pol ? (G)(fr * cre - fi * cim) : (G)0;
+        r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)(fr * cim + fi * cre) : (G)0;
       }
-    rec.rr[e.slot * NN + id] = r;
+    rec.rr[at] = r;
     const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
     float phi = atan2f(dy, dx);
     if (phi < 0.0f) phi += 6.28318531f;
     if (phi >= 6.28318531f) phi = 0.0f;
-    rec.ang[e.slot * NN + id] = make_float2(atan2f(sqrtf(dx * dx + dy * dy), dz), phi);
+    rec.ang[at] = make_float2(atan2f(sqrtf(dx * dx + dy * dy), dz), phi);
   }
 };
 
@@ -211,33 +253,45 @@ __device__ inline int phi_ranges(const NodeGrid& ng, double lo, double hi, int* 
 }
 
 template <typename G>
-__device__ __forceinline__ v3<G> load_dir(const Records<G>& rec, int slot, long id) {
-  const G* p = rec.rr[(long)slot * rec.NN + id].dir;
+__device__ __forceinline__ v3<G> load_dir(const Records<G>& rec, long at) {
+  const G* p = rec.rr[at].dir;
   return mk3<G>(p[0], p[1], p[2]);
 }
 
-// One triangle of one order, as the rasteriser needs it.
+// One triangle of one order of one particle, as the rasteriser needs it.
 template <typename G>
 struct Tri {
-  long vid[3];  // global ray ids in triangle order
+  long vid[3];  // ray ids (within the particle) in triangle order
   v3<G> dv[3];  // stored exit directions
   int sig[3];   // +1 if edge e (cyclic, opposite vertex e) runs from the lower ray id
   int orient;   // sign of the triple product of the directions
-  int slot;
-  int key;      // ((slot * nquad + quad) * 2 + t): the per-node summation order
+  long rb;      // record index of (particle, order slot, ray 0)
+  int part;     // particle within the chunk (selects its node lists)
+  int N;        // rays per side of the particle
+  int key;      // 2 (n_ord quad_off + slot (N-1)^2 + quad) + t: the per-node summation order
 };
 
+// Key of triangle t of quad `quad` of order slot `slot` of a particle whose
+// quads start at chunk quad qoff: unique within the chunk, increasing in
+// (slot, quad, t) within a particle.
+__device__ __forceinline__ int tri_key(int n_ord, long qoff, int slot, long nq, long quad, int t) {
+  return (int)((n_ord * qoff + (long)slot * nq + quad) * 2 + t);
+}
+
 template <typename G>
-__device__ inline void tri_load(const Records<G>& rec, int N, int slot, long quad, int t, Tri<G>& T) {
+__device__ inline void tri_load(const Records<G>& rec, long rb, int N, long quad, int t, int key, int part,
+                                Tri<G>& T) {
   const int Nq = N - 1;
   const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
   const long v00 = (long)iy * N + ix;
   T.vid[0] = v00;
   T.vid[1] = t == 0 ? v00 + 1 : v00 + N + 1;
   T.vid[2] = t == 0 ? v00 + N + 1 : v00 + N;
-  for (int k = 0; k < 3; ++k) T.dv[k] = load_dir(rec, slot, T.vid[k]);
-  T.slot = slot;
-  T.key = (int)(((long)slot * Nq * Nq + quad) * 2 + t);
+  for (int k = 0; k < 3; ++k) T.dv[k] = load_dir(rec, rb + T.vid[k]);
+  T.rb = rb;
+  T.part = part;
+  T.N = N;
+  T.key = key;
   // orientation from the FP64 triple product (d1 - d0) x (d2 - d0) . d0 of the
   // stored directions (their differences are exact in FP64)
   v3<double> e1 = mk3<double>((double)T.dv[1].x - (double)T.dv[0].x, (double)T.dv[1].y - (double)T.dv[0].y,
@@ -499,23 +553,32 @@ __device__ __forceinline__ bool tri_member(const Tri<G>& T, const v3<double>& n,
   return true;
 }
 
+// Unit direction of node (it, ip).
+__device__ __forceinline__ v3<double> node_dir(const NodeGrid& ng, int it, int ip) {
+  return mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
+}
+
 // Contribution of triangle T at node (it, ip), stored at pool slot idx and
 // pushed on the node's list.
 template <typename G>
 __device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, const Tri<G>& T,
                                      int it, int ip, const G lam[3], const v3<G> dl[3], long idx) {
-  const long NN = rec.NN;
   const G st = (G)ng.sth[it], ct = (G)ng.cth[it], sp = (G)ng.sph[ip], cp = (G)ng.cph[ip];
   const v3<G> eth = mk3<G>(ct * cp, ct * sp, -st);
   const v3<G> eph = mk3<G>(-sp, cp, (G)0);
   G acc[2][2][2];
   for (int p = 0; p < 2; ++p)
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
+  const v3<double> n = node_dir(ng, it, ip);
   for (int k = 0; k < 3; ++k) {
-    const RayRec<G>& vr = rec.rr[(long)T.slot * NN + T.vid[k]];
-    G psi = vr.kr[0] * dl[k].x + vr.kr[1] * dl[k].y + vr.kr[2] * dl[k].z;  // k r.(d - n)
+    const RayRec<G>& vr = rec.rr[T.rb + T.vid[k]];
+    // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
+    // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
+    const double psi = (double)vr.kr[0] * ((double)T.dv[k].x - n.x) + (double)vr.kr[1] * ((double)T.dv[k].y - n.y) +
+                       (double)vr.kr[2] * ((double)T.dv[k].z - n.z);
     G s_, c_;
-    sincos_t(psi, &s_, &c_);
+    if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
+    else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
     const G lr = lam[k] * c_, li = lam[k] * s_;
     const G* fp = vr.f;
     for (int p = 0; p < rec.n_pol; ++p) {
@@ -533,7 +596,7 @@ __device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, 
     out[p * 4 + 0] = acc[p][0][0]; out[p * 4 + 1] = acc[p][0][1];
     out[p * 4 + 2] = acc[p][1][0]; out[p * 4 + 3] = acc[p][1][1];
   }
-  const int node = it * ng.n_phi + ip;
+  const long node = ((long)T.part * ng.n_theta + it) * ng.n_phi + ip;
   int prev = atomicExch(&pool.head[node], (int)idx);
   pool.link[idx] = make_int2(T.key, prev);
 }
@@ -559,16 +622,19 @@ __device__ inline int wave_partition() {
                 (threadIdx.x >> 6)) % NPART);
 }
 
-// A triangle staged in LDS for the wave's flattened candidate loop.
+// A triangle staged in LDS for the wave's flattened candidate loop (64 bytes
+// in the mixed path).  Node-grid sides and chunk particle counts are below
+// 2^16 (checked on the host), so index pairs share a word.
 template <typename G>
 struct TriSlot {
-  G dv[9];       // stored exit directions of the three vertices
-  int v00;       // ray id of the quad's (ix, iy) corner
-  int meta;      // bit 0: t (which half of the quad), bit 1: orient > 0, bits 2..: order slot
-  int key;       // per-node summation order
-  int i0, len;   // candidate rows start at i0; len candidates per row
-  int ja0, la;   // phi range a: [ja0, ja0 + la)
-  int jb0;       // phi range b starts here (len - la nodes)
+  G dv[9];   // stored exit directions of the three vertices
+  int v00;   // ray id of the quad's (ix, iy) corner
+  int meta;  // bit 0: t (which half of the quad), bit 1: orient > 0, bits 2..16: N
+  int key;   // per-node summation order
+  int rb;    // record index of (particle, slot, ray 0)
+  int pk0;   // i0 | len << 16: candidate rows start at i0; len candidates per row
+  int pk1;   // ja0 | la << 16: phi range a = [ja0, ja0 + la)
+  int pk2;   // jb0 | part << 16: phi range b starts at jb0 (len - la nodes); chunk particle
 };
 
 template <typename G>
@@ -578,26 +644,28 @@ __device__ __forceinline__ void slot_put(TriSlot<G>& S, const Tri<G>& T, const C
     S.dv[3 * k] = T.dv[k].x; S.dv[3 * k + 1] = T.dv[k].y; S.dv[3 * k + 2] = T.dv[k].z;
   }
   S.v00 = (int)T.vid[0];
-  S.meta = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.orient > 0 ? 2 : 0) | (T.slot << 2);
+  S.meta = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.orient > 0 ? 2 : 0) | (T.N << 2);
   S.key = T.key;
-  S.i0 = cd.i0;
-  S.len = cd.len();
-  S.ja0 = cd.ja0;
-  S.la = cd.ja1 - cd.ja0;
-  S.jb0 = cd.jb0;
+  S.rb = (int)T.rb;
+  S.pk0 = cd.i0 | (cd.len() << 16);
+  S.pk1 = cd.ja0 | ((cd.ja1 - cd.ja0) << 16);
+  S.pk2 = cd.jb0 | (T.part << 16);
 }
 
 template <typename G>
-__device__ __forceinline__ void slot_get(const TriSlot<G>& S, int N, Tri<G>& T) {
+__device__ __forceinline__ void slot_get(const TriSlot<G>& S, Tri<G>& T) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) T.dv[k] = mk3<G>(S.dv[3 * k], S.dv[3 * k + 1], S.dv[3 * k + 2]);
   const int t = S.meta & 1;
+  const int N = (S.meta >> 2) & 0x7fff;
   const long v00 = S.v00;
   T.vid[0] = v00;
   T.vid[1] = t == 0 ? v00 + 1 : v00 + N + 1;
   T.vid[2] = t == 0 ? v00 + N + 1 : v00 + N;
   T.orient = (S.meta & 2) ? 1 : -1;
-  T.slot = S.meta >> 2;
+  T.N = N;
+  T.rb = S.rb;
+  T.part = (int)((unsigned)S.pk2 >> 16);
   T.key = S.key;
   for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
 }
@@ -614,7 +682,7 @@ struct WaveStage {
 
 // Candidate g of the wave: its triangle and node (row it, column ip).
 template <typename G>
-__device__ __forceinline__ void locate(const WaveStage<G>& W, int g, int N, Tri<G>& T, int& it, int& ip) {
+__device__ __forceinline__ void locate(const WaveStage<G>& W, int g, Tri<G>& T, int& it, int& ip) {
   int L = 0;  // last lane whose prefix is <= g
 #pragma unroll
   for (int step = 32; step > 0; step >>= 1)
@@ -623,21 +691,19 @@ __device__ __forceinline__ void locate(const WaveStage<G>& W, int g, int N, Tri<
   const int n0 = W.n0[L];
   const TriSlot<G>& S = W.tri[2 * L + (c < n0 ? 0 : 1)];
   if (c >= n0) c -= n0;
-  const int row = c / S.len;
-  const int jj = c - row * S.len;
-  it = S.i0 + row;
-  ip = jj < S.la ? S.ja0 + jj : S.jb0 + (jj - S.la);
-  slot_get(S, N, T);
-}
-
-__device__ __forceinline__ v3<double> node_dir(const NodeGrid& ng, int it, int ip) {
-  return mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
+  const int i0 = S.pk0 & 0xffff, len = (int)((unsigned)S.pk0 >> 16);
+  const int ja0 = S.pk1 & 0xffff, la = (int)((unsigned)S.pk1 >> 16), jb0 = S.pk2 & 0xffff;
+  const int row = c / len;
+  const int jj = c - row * len;
+  it = i0 + row;
+  ip = jj < la ? ja0 + jj : jb0 + (jj - la);
+  slot_get(S, T);
 }
 
 // Take pool slots for the nh buffered hits with one atomic, then store each
 // hit's contribution (its membership weights are recomputed, bit for bit).
 template <typename G>
-__device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, int N,
+__device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
                            const WaveStage<G>& W, int nh, int part) {
   const int lane = threadIdx.x & 63;
   unsigned first = 0;
@@ -648,7 +714,7 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
     if (h < nh) {
       Tri<G> T;
       int it, ip;
-      locate(W, W.hits[h], N, T, it, ip);
+      locate(W, W.hits[h], T, it, ip);
       G lam[3];
       v3<G> dl[3];
       tri_member(T, node_dir(ng, it, ip), lam, dl);
@@ -666,7 +732,7 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
 // The lanes must have written their slots, n0 and prefix before the call, and
 // the block must have passed a barrier since.
 template <typename G>
-__device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, int N,
+__device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
                              WaveStage<G>& W, int wave_total, int part) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -677,7 +743,7 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
     if (g < wave_total) {
       Tri<G> T;
       int it, ip;
-      locate(W, g, N, T, it, ip);
+      locate(W, g, T, it, ip);
       G lam[3];
       v3<G> dl[3];
       hit = tri_member(T, node_dir(ng, it, ip), lam, dl);
@@ -689,7 +755,7 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      flush_hits(rec, ng, pool, N, W, nh, part);
+      flush_hits(rec, ng, pool, W, nh, part);
       nh = 0;
       __builtin_amdgcn_wave_barrier();
     }
@@ -709,44 +775,56 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
   return incl - v;
 }
 
-// One thread per (order slot, quad).  Triangles whose bounding box holds at
-// most CAND_INLINE nodes are staged for the wave's flattened candidate loop;
-// larger ones are listed row by row for k_raster_rows.
+// One thread per (order slot, quad) of the chunk: blockIdx.y is the slot,
+// blockIdx.x * 256 + threadIdx.x the chunk quad.  Triangles whose bounding box
+// holds at most cand_inline nodes are staged for the wave's flattened
+// candidate loop; larger ones are listed row by row for k_raster_rows.
 template <typename G>
-__global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
-                                                const HitPool<G> pool, const double margin) {
+__global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<G> rec, const NodeGrid ng,
+                                                const HitPool<G> pool, const double margin, const int cand_inline) {
   __shared__ WaveStage<G> stage[4];
+  __shared__ int s_p0;
   WaveStage<G>& W = stage[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const int slot = blockIdx.y;
-  const int Nq = P.N - 1;
-  const long nquad = (long)Nq * Nq;
-  const long quad = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long NN = rec.NN;
+  const long n_quads = B.quad_off[B.n] - B.quad_base;
+  const long gq0 = (long)blockIdx.x * blockDim.x;
+  if (threadIdx.x == 0) s_p0 = find_part(B.quad_off, B.n, B.quad_base, gq0);
+  __syncthreads();
+  const long gq = gq0 + threadIdx.x;
 
   Tri<G> T0, T1;
   Cand c0, c1;
   int n0 = 0, n1 = 0, r0 = 0, r1 = 0;  // inline candidates, rows to list
-  if (quad < nquad) {
+  if (gq < n_quads) {
+    int p = s_p0;  // a block spans few particles: walk forward from the block's first
+    while (B.quad_off[p + 1] - B.quad_base <= gq) ++p;
+    const int N = B.P[p].N;
+    const long qoff = B.quad_off[p] - B.quad_base;
+    const long quad = gq - qoff;
+    const int Nq = N - 1;
+    const long NN = (long)N * N;
+    const long rb = B.n_ord * (B.ray_off[p] - B.ray_base) + (long)slot * NN;
     const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
-    const long v00 = (long)iy * P.N + ix;
-    const int f0 = rec.flags[slot * NN + v00], f1 = rec.flags[slot * NN + v00 + 1];
-    const int f2 = rec.flags[slot * NN + v00 + P.N], f3 = rec.flags[slot * NN + v00 + P.N + 1];
+    const long v00 = (long)iy * N + ix;
+    const int f0 = rec.flags[rb + v00], f1 = rec.flags[rb + v00 + 1];
+    const int f2 = rec.flags[rb + v00 + N], f3 = rec.flags[rb + v00 + N + 1];
     const int nf0 = f0 >> 1 & 127;
     const bool tv0 = (f0 & 1) && (f1 & 1) && (f3 & 1) && nf0 == (f1 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
     const bool tv1 = (f0 & 1) && (f2 & 1) && (f3 & 1) && nf0 == (f2 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
     if (tv0 || tv1) {
-      const float2* an = rec.ang + slot * NN;
-      const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + P.N], a11 = an[v00 + P.N + 1];
+      const float2* an = rec.ang + rb;
+      const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + N], a11 = an[v00 + N + 1];
       // box of one triangle: from the vertex angles when fast_box applies, else
       // from the directions; the directions (and orientation) are loaded only
       // for triangles with candidate nodes
       auto setup = [&](int t, bool tv, float2 b, float2 c, Tri<G>& T, Cand& cd, int& n, int& r) {
         if (!tv) return;
+        const int key = tri_key(B.n_ord, qoff, slot, (long)Nq * Nq, quad, t);
         Box bx;
         bool loaded = false;
         if (!fast_box(a00, b, c, (float)margin, bx)) {
-          tri_load(rec, P.N, slot, quad, t, T);
+          tri_load(rec, rb, N, quad, t, key, p, T);
           loaded = true;
           if (T.orient == 0) return;
           bx = tri_box(T, (float)margin);
@@ -755,10 +833,10 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
         const int cnt = cd.count();
         if (cnt == 0) return;
         if (!loaded) {
-          tri_load(rec, P.N, slot, quad, t, T);
+          tri_load(rec, rb, N, quad, t, key, p, T);
           if (T.orient == 0) return;
         }
-        if (cnt <= CAND_INLINE) n = cnt; else r = cd.i1 - cd.i0;
+        if (cnt <= cand_inline) n = cnt; else r = cd.i1 - cd.i0;
       };
       setup(0, tv0, a01, a11, T0, c0, n0, r0);
       setup(1, tv1, a11, a10, T1, c1, n1, r1);
@@ -794,20 +872,19 @@ __global__ void __launch_bounds__(256) k_raster(const ParticleConst P, const Rec
   W.excl[lane] = wave_excl_scan(n0 + n1, &wave_total);
   W.n0[lane] = n0;
   __syncthreads();
-  raster_drain(rec, ng, pool, P.N, W, wave_total, wave_partition());
+  raster_drain(rec, ng, pool, W, wave_total, wave_partition());
 }
 
 // One thread per listed (triangle, theta row); the block walks the list in
 // blocks of 256 items.  Each row's candidates are the nodes of the row's
 // longitude window (row_window).
 template <typename G>
-__global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, const Records<G> rec, const NodeGrid ng,
+__global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Records<G> rec, const NodeGrid ng,
                                                      const HitPool<G> pool, const double margin) {
   __shared__ WaveStage<G> stage[4];
   WaveStage<G>& W = stage[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const unsigned n_items = min(*pool.n_rows, (unsigned)pool.rows_cap);
-  const long nquad = (long)(P.N - 1) * (P.N - 1);
   const int part = wave_partition();
   for (unsigned first = blockIdx.x * blockDim.x; first < n_items; first += gridDim.x * blockDim.x) {
     const unsigned item = first + threadIdx.x;
@@ -818,17 +895,28 @@ __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, cons
       const int key = w.x;
       const int it = w.y;
       const int t = key & 1;
-      const long sq = key >> 1;
-      const int slot = (int)(sq / nquad);
-      const long quad = sq - (long)slot * nquad;
+      const long sq = key >> 1;  // n_ord quad_off + slot nq + quad
+      // particle: largest p with n_ord (quad_off[p] - base) <= sq
+      int lo = 0, hi = B.n - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.n_ord * (B.quad_off[mid] - B.quad_base) <= sq) lo = mid; else hi = mid - 1;
+      }
+      const int p = lo;
+      const int N = B.P[p].N;
+      const long nq = (long)(N - 1) * (N - 1);
+      const long within = sq - B.n_ord * (B.quad_off[p] - B.quad_base);
+      const int slot = (int)(within / nq);
+      const long quad = within - (long)slot * nq;
+      const long rb = B.n_ord * (B.ray_off[p] - B.ray_base) + (long)slot * N * N;
       Tri<G> T;
-      tri_load(rec, P.N, slot, quad, t, T);
+      tri_load(rec, rb, N, quad, t, key, p, T);
       if (T.orient != 0) {
         const Box bx = tri_box(T, (float)margin);
-        double lo, hi;
-        if (row_window(T, bx, ng.th[it], margin, lo, hi)) {
+        double lo_phi, hi_phi;
+        if (row_window(T, bx, ng.th[it], margin, lo_phi, hi_phi)) {
           int j0[2], j1[2];
-          const int nr = phi_ranges(ng, lo, hi, j0, j1);
+          const int nr = phi_ranges(ng, lo_phi, hi_phi, j0, j1);
           Cand cd;
           cd.i0 = it;
           cd.i1 = it + 1;
@@ -845,21 +933,25 @@ __global__ void __launch_bounds__(256) k_raster_rows(const ParticleConst P, cons
     W.excl[lane] = wave_excl_scan(n, &wave_total);
     W.n0[lane] = n;
     __syncthreads();
-    raster_drain(rec, ng, pool, P.N, W, wave_total, part);
+    raster_drain(rec, ng, pool, W, wave_total, part);
     __syncthreads();  // the stage is rewritten by the next block of items
   }
 }
 
-// One thread per node: walk the node's hit list, order the hits by triangle
-// key, sum them in that order and write (F_theta, F_phi) for every polarisation.
+// One thread per node of the chunk (particle-major): walk the node's hit list,
+// order the hits by triangle key, sum them in that order and write (F_theta,
+// F_phi) for every polarisation into the particle's output block.
 template <typename G>
-__global__ void __launch_bounds__(256) k_node_sum(const HitPool<G> pool, int n_nodes, int n_pol, G* out,
-                                                  int32_t* ncontrib) {
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= n_nodes) return;
+__global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPool<G> pool, int n_nodes, int n_pol,
+                                                  G* out, int32_t* ncontrib) {
+  const long gn = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gn >= (long)B.n * n_nodes) return;
+  const int pl = (int)(gn / n_nodes);
+  const int node = (int)(gn - (long)pl * n_nodes);
+  const long ob = (long)B.out_index[pl];
   int keys[NODE_SORT_MAX], idxs[NODE_SORT_MAX];
   int cnt = 0;
-  for (int h = pool.head[node]; h >= 0; h = pool.link[h].y) {
+  for (int h = pool.head[gn]; h >= 0; h = pool.link[h].y) {
     int2 l = pool.link[h];
     if (cnt < NODE_SORT_MAX) {
       // insertion into the sorted prefix
@@ -883,7 +975,7 @@ __global__ void __launch_bounds__(256) k_node_sum(const HitPool<G> pool, int n_n
     for (int r = 0; r < cnt; ++r) {
       long best = 0x7fffffffffffL;
       int bi = -1;
-      for (int h = pool.head[node]; h >= 0; h = pool.link[h].y) {
+      for (int h = pool.head[gn]; h >= 0; h = pool.link[h].y) {
         long kk = pool.link[h].x;
         if (kk > last && kk < best) { best = kk; bi = h; }
       }
@@ -892,13 +984,14 @@ __global__ void __launch_bounds__(256) k_node_sum(const HitPool<G> pool, int n_n
       for (int k = 0; k < w; ++k) acc[k] += c[k];
     }
   }
+  G* po = out + ob * ((long)n_pol * 2 * n_nodes * 2);
   for (int p = 0; p < n_pol; ++p)
     for (int a = 0; a < 2; ++a) {
       long o = ((long)(p * 2 + a) * n_nodes + node) * 2;
-      out[o] = acc[p * 4 + a * 2];
-      out[o + 1] = acc[p * 4 + a * 2 + 1];
+      po[o] = acc[p * 4 + a * 2];
+      po[o + 1] = acc[p * 4 + a * 2 + 1];
     }
-  if (ncontrib) ncontrib[node] = cnt;
+  if (ncontrib) ncontrib[ob * n_nodes + node] = cnt;
 }
 
 }  // namespace rtw

@@ -45,8 +45,17 @@ class RayRecords(ctypes.Structure):
                 ("cond", ctypes.c_void_p)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("tile_rays", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("cand_inline", ctypes.c_int)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("rays_per_chunk", ctypes.c_longlong), ("hits_per_node", ctypes.c_double)]
+
+
 EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_status",
-            "rtw_farfield_stats", "rtw_profile_enable", "rtw_profile_read", "rtw_last_error", "rtw_version"]
+            "rtw_farfield_stats", "rtw_batch_workspace_size", "rtw_batch", "rtw_batch_autotune",
+            "rtw_profile_enable", "rtw_profile_read", "rtw_last_error", "rtw_version"]
 
 _lib = None
 
@@ -77,6 +86,14 @@ def load():
     L.rtw_farfield.argtypes = [P(Particle), P(Incident), P(TraceOpts), P(Grid), ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     L.rtw_farfield_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_size_t)]
+    L.rtw_batch_workspace_size.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts),
+                                           P(Grid), P(BatchOpts), P(ctypes.c_size_t)]
+    L.rtw_batch.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts), P(Grid),
+                            ctypes.c_void_p, ctypes.c_void_p, P(Tune), P(BatchOpts), ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.c_void_p]
+    L.rtw_batch_autotune.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts),
+                                     P(Grid), P(BatchOpts), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p, P(Tune)]
     L.rtw_farfield_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_uint64), P(ctypes.c_uint64)]
     L.rtw_profile_enable.argtypes = [ctypes.c_int]
     L.rtw_profile_read.argtypes = [ctypes.c_int, ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int),
@@ -229,5 +246,89 @@ class FarField:
 
     def field(self):
         """Complex view [n_pol, 2 (theta, phi), n_theta, n_phi]."""
+        import torch
+        return torch.view_as_complex(self.out)
+
+
+@dataclass
+class Batch:
+    """Far fields of many particles in one rtw_batch call (device output
+    [n, n_pol, 2, n_theta, n_phi] complex).  particles: (semi_axes, euler_deg,
+    m) triples; grid_n: ray-grid side of each."""
+    particles: Sequence
+    grid_n: Sequence[int]
+    inc: Incident
+    opts: TraceOpts
+    theta_deg: "object"
+    phi_deg: "object"
+    rays_per_chunk: int = 0
+    hits_per_node: float = 0.0
+    tune: Optional[Tune] = None
+    device: str = "cuda"
+
+    def __post_init__(self):
+        import torch
+        n = len(self.particles)
+        self.n = n
+        self.parts = (Particle * n)(*[make_particle(a, e, m) for (a, e, m) in self.particles])
+        self.gn = (ctypes.c_int * n)(*[int(g) for g in self.grid_n])
+        self.bopts = BatchOpts(int(self.rays_per_chunk), float(self.hits_per_node))
+        self.theta = torch.as_tensor(self.theta_deg, dtype=torch.float64, device=self.device).contiguous()
+        self.phi = torch.as_tensor(self.phi_deg, dtype=torch.float64, device=self.device).contiguous()
+        self.grid = Grid(self.theta.numel(), self.theta.data_ptr(), self.phi.numel(), self.phi.data_ptr())
+        nb = ctypes.c_size_t(0)
+        _check(load().rtw_batch_workspace_size(n, self.parts, self.gn, ctypes.byref(self.inc), ctypes.byref(self.opts),
+                                               ctypes.byref(self.grid), ctypes.byref(self.bopts), ctypes.byref(nb)))
+        self._alloc(nb.value)
+        dt = torch.float64 if self.opts.precision == FP64 else torch.float32
+        self.out = torch.empty((n, self.inc.n_pol, 2, self.theta.numel(), self.phi.numel(), 2), dtype=dt,
+                               device=self.device)
+        self.ncontrib = torch.empty((n, self.theta.numel(), self.phi.numel()), dtype=torch.int32, device=self.device)
+
+    def _alloc(self, nbytes):
+        import torch
+        self.ws_bytes = int(nbytes)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+
+    def launch(self, stream=None, with_counts=True):
+        _check(load().rtw_batch(self.n, self.parts, self.gn, ctypes.byref(self.inc), ctypes.byref(self.opts),
+                                ctypes.byref(self.grid), _ptr(self.out), _ptr(self.ncontrib) if with_counts else None,
+                                ctypes.byref(self.tune) if self.tune is not None else None, ctypes.byref(self.bopts),
+                                ctypes.c_void_p(self.ws_ptr), ctypes.c_size_t(self.ws_bytes), _stream_ptr(stream)))
+
+    def autotune(self, stream=None):
+        """Run the library's autotuner on this batch and keep its choice."""
+        best = Tune()
+        _check(load().rtw_batch_autotune(self.n, self.parts, self.gn, ctypes.byref(self.inc), ctypes.byref(self.opts),
+                                         ctypes.byref(self.grid), ctypes.byref(self.bopts), _ptr(self.out),
+                                         ctypes.c_void_p(self.ws_ptr), ctypes.c_size_t(self.ws_bytes),
+                                         _stream_ptr(stream), ctypes.byref(best)))
+        self.tune = best
+        return best
+
+    def status(self, stream=None):
+        need = ctypes.c_size_t(0)
+        rc = load().rtw_farfield_status(ctypes.c_void_p(self.ws_ptr), _stream_ptr(stream), ctypes.byref(need))
+        if rc not in (RTW_OK, RTW_ERR_WORKSPACE):
+            _check(rc)
+        return rc, need.value
+
+    def stats(self, stream=None):
+        hits, fp64 = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(load().rtw_farfield_stats(ctypes.c_void_p(self.ws_ptr), _stream_ptr(stream), ctypes.byref(hits),
+                                         ctypes.byref(fp64)))
+        return hits.value, fp64.value
+
+    def __call__(self, stream=None, with_counts=True):
+        for _ in range(4):
+            self.launch(stream, with_counts)
+            rc, need = self.status(stream)
+            if rc == RTW_OK:
+                return self.field()
+            self._alloc(max(need, 2 * self.ws_bytes))
+        raise RTWError(RTW_ERR_WORKSPACE, "hit pool kept overflowing")
+
+    def field(self):
         import torch
         return torch.view_as_complex(self.out)

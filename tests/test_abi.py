@@ -82,3 +82,50 @@ def test_workspace_size_scales_with_problem():
     assert n128 > n64 and m128 < n128
     _, big_nodes = _ws(part, inc, rtw.make_opts(0, 3, 64, rtw.FP64), 1801, 720)
     assert big_nodes > n64
+
+
+def _batch_ws(parts, sides, inc, opts, n_theta=361, n_phi=180, rays_per_chunk=0):
+    n = len(parts)
+    P = (rtw.Particle * n)(*parts)
+    G = (ctypes.c_int * n)(*sides)
+    g = rtw.Grid(n_theta, 1, n_phi, 1)
+    bo = rtw.BatchOpts(rays_per_chunk, 0.0)
+    out = ctypes.c_size_t(0)
+    rc = rtw.load().rtw_batch_workspace_size(n, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g),
+                                             ctypes.byref(bo), ctypes.byref(out))
+    return rc, out.value
+
+
+def test_batch_workspace_and_validation_without_device():
+    L = rtw.load()
+    inc, opts = rtw.make_incident(0.6328, 2), rtw.make_opts(0, 3, 2, rtw.MIXED)
+    parts = [rtw.make_particle((30 + i, 28, 25), (i, 2 * i, 3 * i), 1.33 + 0.01 * i) for i in range(6)]
+    sides = [256, 512, 256, 1024, 384, 256]
+    rc, whole = _batch_ws(parts, sides, inc, opts)
+    assert rc == rtw.RTW_OK and whole > 0
+    # a smaller chunk budget needs a smaller workspace (records are sized per chunk)
+    rc, chunked = _batch_ws(parts, sides, inc, opts, rays_per_chunk=1 << 18)
+    assert rc == rtw.RTW_OK and chunked < whole
+    # one bad particle is named in the error
+    bad = list(parts)
+    bad[3] = rtw.make_particle((30, 28, 25), m=1.0)
+    rc, _ = _batch_ws(bad, sides, inc, opts)
+    assert rc == rtw.RTW_ERR_UNSUPPORTED and "particle 3" in L.rtw_last_error().decode()
+    rc, _ = _batch_ws(parts, [256, 512, 1, 1024, 384, 256], inc, opts)
+    assert rc == rtw.RTW_ERR_INVALID_ARG
+    rc, _ = _batch_ws(parts, sides, inc, opts, n_theta=70000, n_phi=2)
+    assert rc == rtw.RTW_ERR_INVALID_ARG
+    # rtw_batch rejects NULL outputs, a misaligned workspace and a bad tuning before any device call
+    n = len(parts)
+    P = (rtw.Particle * n)(*parts)
+    G = (ctypes.c_int * n)(*sides)
+    g = rtw.Grid(361, 1, 180, 1)
+    args = (n, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g))
+    assert L.rtw_batch(*args, None, None, None, None, None, 0, None) == rtw.RTW_ERR_INVALID_ARG
+    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, None, None, ctypes.c_void_p(4096 + 8), 1 << 30,
+                       None) == rtw.RTW_ERR_INVALID_ARG
+    t = rtw.Tune(300, 8, 32)
+    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, ctypes.byref(t), None, ctypes.c_void_p(4096), 1 << 30,
+                       None) == rtw.RTW_ERR_INVALID_ARG
+    assert L.rtw_batch(0, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g), ctypes.c_void_p(256), None,
+                       None, None, ctypes.c_void_p(4096), 1 << 30, None) == rtw.RTW_ERR_INVALID_ARG
