@@ -419,7 +419,7 @@ __device__ inline Cand box_cand(const NodeGrid& ng, const Box& bx) {
 //     the margin absorbs;
 //   - longitude is monotonic along pole-free arcs: the phi extent is the
 //     shortest circular interval holding the three vertex longitudes.
-__device__ inline bool fast_box(float2 a, float2 b, float2 c, float margin, Box& bx) {
+__device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c, float margin, Cand& cd) {
   const float PI_F = 3.14159265f, TWO_PI_F = 6.2831853f;
   const float tmin = fminf(a.x, fminf(b.x, c.x)), tmax = fmaxf(a.x, fmaxf(b.x, c.x));
   const float s_hi = fminf(1.0f, fminf(tmax, PI_F - tmin));
@@ -436,9 +436,11 @@ __device__ inline bool fast_box(float2 a, float2 b, float2 c, float margin, Box&
   const float s_lo = 0.63661977f * pole_gap;  // sin x >= 2x / pi on [0, pi/2]
   if (!(0.132f * q <= 2e-6f * s_lo)) return false;
   const float m = margin + 2e-6f;
-  bx.full = false;
-  bx.tlo = tmin - m;
-  bx.thi = tmax + m;
+  const float tlo = tmin - m, thi = tmax + m;
+  cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
+  cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
+  cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
+  if (cd.i1 <= cd.i0) return true;  // no node row crosses the triangle: nothing else to do
   float a0 = a.y, a1 = b.y, a2 = c.y, t;
   if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
   if (a1 > a2) { t = a1; a1 = a2; a2 = t; }
@@ -448,12 +450,19 @@ __device__ inline bool fast_box(float2 a, float2 b, float2 c, float margin, Box&
   if (g20 >= g01 && g20 >= g12) { lo_f = a0; hi_f = a2; }
   else if (g01 >= g12) { lo_f = a1; hi_f = a0 + TWO_PI_F; }
   else { lo_f = a2; hi_f = a1 + TWO_PI_F; }
-  const double pm = (double)m / (double)(0.63661977f * fminf(bx.tlo, PI_F - bx.thi)) + 1e-6;
+  // phi margin: m / sin(theta) over the box, with sin bounded below by 2 theta / pi
+  const float pm = m * __frcp_rn(0.63661977f * fminf(tlo, PI_F - thi)) * 1.0001f + 1e-6f;
   const double TWO_PI = 6.283185307179586;
-  const double lo = (double)lo_f - pm, hi = (double)hi_f + pm;
+  const double lo = (double)lo_f - (double)pm, hi = (double)hi_f + (double)pm;
   if (hi - lo >= TWO_PI) return false;
-  bx.plo = lo < 0.0 ? lo + TWO_PI : lo;
-  bx.phi = bx.plo + (hi - lo);
+  const double plo = lo < 0.0 ? lo + TWO_PI : lo, phi = plo + (hi - lo);
+  if (phi < TWO_PI) {
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo);
+    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi);
+  } else {
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo); cd.ja1 = ng.n_phi;
+    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi - TWO_PI);
+  }
   return true;
 }
 
@@ -821,15 +830,13 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
       auto setup = [&](int t, bool tv, float2 b, float2 c, Tri<G>& T, Cand& cd, int& n, int& r) {
         if (!tv) return;
         const int key = tri_key(B.n_ord, qoff, slot, (long)Nq * Nq, quad, t);
-        Box bx;
         bool loaded = false;
-        if (!fast_box(a00, b, c, (float)margin, bx)) {
+        if (!fast_box(ng, a00, b, c, (float)margin, cd)) {
           tri_load(rec, rb, N, quad, t, key, p, T);
           loaded = true;
           if (T.orient == 0) return;
-          bx = tri_box(T, (float)margin);
+          cd = box_cand(ng, tri_box(T, (float)margin));
         }
-        cd = box_cand(ng, bx);
         const int cnt = cd.count();
         if (cnt == 0) return;
         if (!loaded) {
