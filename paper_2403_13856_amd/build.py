@@ -14,9 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "librtw.so")
-SOURCES = [os.path.join(HERE, "csrc", "rtw_lib.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rtw_lib.hip", "rtw_mlp.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("rtw_device.hpp", "rtw_raster.hpp")] + \
-    [os.path.join(ROOT, "include", "rtw.h")]
+    [os.path.join(ROOT, "include", f) for f in ("rtw.h", "rtw_surrogate.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -745,7 +745,8 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
                              WaveStage<G>& W, int wave_total, int part) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
-  int nh = 0;  // buffered hits (wave-uniform)
+  int nh = 0;      // buffered hits (wave-uniform)
+  int flushes = 0; // successive batches go to different pool partitions (97 is odd: every partition is reached)
   for (int base = 0; base < wave_total; base += 64) {
     const int g = base + lane;
     bool hit = false;
@@ -764,7 +765,8 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      flush_hits(rec, ng, pool, W, nh, part);
+      flush_hits(rec, ng, pool, W, nh, (part + 97 * flushes) % NPART);
+      ++flushes;
       nh = 0;
       __builtin_amdgcn_wave_barrier();
     }

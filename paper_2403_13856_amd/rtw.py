@@ -265,6 +265,7 @@ class Batch:
     hits_per_node: float = 0.0
     tune: Optional[Tune] = None
     device: str = "cuda"
+    allocate: bool = True  # False: describe the particles only (no workspace or output)
 
     def __post_init__(self):
         import torch
@@ -276,6 +277,8 @@ class Batch:
         self.theta = torch.as_tensor(self.theta_deg, dtype=torch.float64, device=self.device).contiguous()
         self.phi = torch.as_tensor(self.phi_deg, dtype=torch.float64, device=self.device).contiguous()
         self.grid = Grid(self.theta.numel(), self.theta.data_ptr(), self.phi.numel(), self.phi.data_ptr())
+        if not self.allocate:
+            return
         nb = ctypes.c_size_t(0)
         _check(load().rtw_batch_workspace_size(n, self.parts, self.gn, ctypes.byref(self.inc), ctypes.byref(self.opts),
                                                ctypes.byref(self.grid), ctypes.byref(self.bopts), ctypes.byref(nb)))
@@ -332,3 +335,193 @@ class Batch:
     def field(self):
         import torch
         return torch.view_as_complex(self.out)
+
+
+# ---------------------------------------------------------------------------
+# learned surrogate (include/rtw_surrogate.h)
+# ---------------------------------------------------------------------------
+SURROGATE_EXPORTED = ["rtw_surrogate_last_error", "rtw_surrogate_param_count", "rtw_surrogate_create",
+                      "rtw_surrogate_destroy", "rtw_surrogate_set_normalization", "rtw_surrogate_get_params",
+                      "rtw_surrogate_set_params", "rtw_surrogate_forward", "rtw_surrogate_grad",
+                      "rtw_surrogate_get_grads", "rtw_surrogate_train_step", "rtw_surrogate_features",
+                      "rtw_cell_log_intensity", "rtw_surrogate_query_scratch_size", "rtw_surrogate_query"]
+EXPORTED = EXPORTED + SURROGATE_EXPORTED
+N_FEATURES, WIDTH, DEPTH = 9, 512, 6
+
+
+class Cells(ctypes.Structure):
+    _fields_ = [("n_theta_cells", ctypes.c_int), ("theta0_deg", ctypes.c_double), ("dtheta_deg", ctypes.c_double),
+                ("n_phi_cells", ctypes.c_int), ("phi0_deg", ctypes.c_double), ("dphi_deg", ctypes.c_double)]
+
+    def centres(self):
+        import numpy as np
+        tc = self.theta0_deg + (np.arange(self.n_theta_cells) + 0.5) * self.dtheta_deg
+        pc = self.phi0_deg + (np.arange(self.n_phi_cells) + 0.5) * self.dphi_deg
+        T, P = np.meshgrid(tc, pc, indexing="ij")
+        return T.ravel(), P.ravel()
+
+
+_slib = None
+
+
+def sload():
+    global _slib
+    if _slib is not None:
+        return _slib
+    L = load()
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.rtw_surrogate_last_error.restype = ctypes.c_char_p
+    L.rtw_surrogate_param_count.argtypes = [P(ctypes.c_size_t)]
+    L.rtw_surrogate_create.argtypes = [ctypes.c_uint64, ctypes.c_int, P(vp)]
+    L.rtw_surrogate_destroy.argtypes = [vp]
+    L.rtw_surrogate_set_normalization.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float),
+                                                  P(ctypes.c_float)]
+    L.rtw_surrogate_get_params.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
+    L.rtw_surrogate_set_params.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
+    L.rtw_surrogate_get_grads.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
+    L.rtw_surrogate_forward.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.rtw_surrogate_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.rtw_surrogate_train_step.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_float, vp, vp]
+    L.rtw_surrogate_features.argtypes = [ctypes.c_int, P(Particle), P(Incident), ctypes.c_int, P(ctypes.c_double),
+                                         P(ctypes.c_double), P(ctypes.c_float)]
+    L.rtw_cell_log_intensity.argtypes = [ctypes.c_int, vp, ctypes.c_int, P(Grid), P(Cells), vp, vp]
+    L.rtw_surrogate_query_scratch_size.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident),
+                                                   P(TraceOpts), P(Grid), P(Cells), P(ctypes.c_size_t)]
+    L.rtw_surrogate_query.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_float, ctypes.c_int, P(Particle),
+                                      P(ctypes.c_int), P(Incident), P(TraceOpts), P(Grid), P(Cells), P(Tune), vp, vp,
+                                      vp, vp, ctypes.c_size_t, P(ctypes.c_int), vp]
+    _slib = L
+    return L
+
+
+def _scheck(rc):
+    if rc != RTW_OK:
+        raise RTWError(rc, sload().rtw_surrogate_last_error().decode())
+
+
+def param_count():
+    n = ctypes.c_size_t(0)
+    _scheck(sload().rtw_surrogate_param_count(ctypes.byref(n)))
+    return n.value
+
+
+def surrogate_features(particles, inc, cells):
+    """Host features [n_part * n_cells, 9] (float32) of every (particle, cell)."""
+    import numpy as np
+    n = len(particles)
+    parts = (Particle * n)(*[make_particle(a, e, m) for (a, e, m) in particles])
+    tc, pc = cells.centres()
+    tc = np.ascontiguousarray(tc, dtype=np.float64)
+    pc = np.ascontiguousarray(pc, dtype=np.float64)
+    out = np.empty((n, tc.size, N_FEATURES), dtype=np.float32)
+    _scheck(sload().rtw_surrogate_features(n, parts, ctypes.byref(inc), tc.size,
+                                           tc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           pc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out.reshape(-1, N_FEATURES)
+
+
+def cell_log_intensity(batch, cells, stream=None):
+    """ln cell-mean intensity [n_part, n_cells, n_pol] of a computed Batch (device tensor)."""
+    import torch
+    n_cells = cells.n_theta_cells * cells.n_phi_cells
+    out = torch.empty((batch.n, n_cells, batch.inc.n_pol), dtype=torch.float32, device=batch.device)
+    _scheck(sload().rtw_cell_log_intensity(batch.n, _ptr(batch.out), batch.inc.n_pol, ctypes.byref(batch.grid),
+                                           ctypes.byref(cells), _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+class Surrogate:
+    """Handle of the BF16 MLP surrogate (rtw_surrogate_*)."""
+
+    def __init__(self, seed=0, max_rows=65536):
+        self.h = ctypes.c_void_p(0)
+        _scheck(sload().rtw_surrogate_create(int(seed), int(max_rows), ctypes.byref(self.h)))
+        self.max_rows = max_rows
+
+    def close(self):
+        if self.h:
+            sload().rtw_surrogate_destroy(self.h)
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_normalization(self, feat_shift, feat_scale, target_shift, target_scale):
+        import numpy as np
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (feat_shift, feat_scale, target_shift, target_scale)]
+        fp = [x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) for x in a]
+        _scheck(sload().rtw_surrogate_set_normalization(self.h, *fp))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(param_count(), dtype=np.float32)
+        _scheck(sload().rtw_surrogate_get_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _scheck(sload().rtw_surrogate_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def get_grads(self):
+        import numpy as np
+        out = np.empty(param_count(), dtype=np.float32)
+        _scheck(sload().rtw_surrogate_get_grads(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size))
+        return out
+
+    def forward(self, feats, stream=None):
+        """feats: device float32 [n, 9] -> device [n, 4] (ln I_x, ln I_y, ln sigma_x, ln sigma_y)."""
+        import torch
+        n = feats.shape[0]
+        out = torch.empty((n, 4), dtype=torch.float32, device=feats.device)
+        for a in range(0, n, self.max_rows):
+            b = min(n, a + self.max_rows)
+            _scheck(sload().rtw_surrogate_forward(self.h, b - a, _ptr(feats[a:b]), _ptr(out[a:b]), _stream_ptr(stream)))
+        return out
+
+    def grad(self, feats, targets, stream=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        _scheck(sload().rtw_surrogate_grad(self.h, feats.shape[0], _ptr(feats), _ptr(targets), _ptr(loss),
+                                           _stream_ptr(stream)))
+        return loss
+
+    def train_step(self, feats, targets, lr, stream=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        _scheck(sload().rtw_surrogate_train_step(self.h, feats.shape[0], _ptr(feats), _ptr(targets), float(lr),
+                                                 _ptr(loss), _stream_ptr(stream)))
+        return loss
+
+    def query(self, feats, q_part, q_cell, tau, batch, cells, tune=None, stream=None):
+        """Answers with RTW fallback; batch: a Batch describing the queries'
+        particles (its workspace and output are not used).  Returns (answer
+        [n, 2], pred [n, 4], used_fallback [n], particles re-computed)."""
+        import torch
+        n = feats.shape[0]
+        dev = feats.device
+        pred = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        ans = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        used = torch.empty(n, dtype=torch.int32, device=dev)
+        nb = ctypes.c_size_t(0)
+        L = sload()
+        _scheck(L.rtw_surrogate_query_scratch_size(batch.n, batch.parts, batch.gn, ctypes.byref(batch.inc),
+                                                   ctypes.byref(batch.opts), ctypes.byref(batch.grid),
+                                                   ctypes.byref(cells), ctypes.byref(nb)))
+        if getattr(self, "_scratch", None) is None or self._scratch.numel() < nb.value:
+            self._scratch = None
+            torch.cuda.empty_cache()
+            self._scratch = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        nrec = ctypes.c_int(0)
+        _scheck(L.rtw_surrogate_query(self.h, n, _ptr(feats), _ptr(q_part), _ptr(q_cell), float(tau), batch.n,
+                                      batch.parts, batch.gn, ctypes.byref(batch.inc), ctypes.byref(batch.opts),
+                                      ctypes.byref(batch.grid), ctypes.byref(cells),
+                                      ctypes.byref(tune) if tune is not None else None, _ptr(pred), _ptr(ans),
+                                      _ptr(used), _ptr(self._scratch), ctypes.c_size_t(self._scratch.numel()),
+                                      ctypes.byref(nrec), _stream_ptr(stream)))
+        return ans, pred, used, nrec.value

@@ -1,0 +1,150 @@
+"""GPU checks of the learned surrogate (include/rtw_surrogate.h).
+
+* Forward and gradients of the BF16 MFMA network against the FP64 CPU
+  reference (oracle/mlp_ref.py) evaluated on the same BF16-rounded operands:
+  predictions within 2e-2 (1 + |value|), per-layer weight gradients within
+  5e-2 relative L2 with cosine > 0.995.  The reference's own gradients are
+  pinned against central differences by tests/test_oracle_mlp.py.
+* Training reduces the loss of a smooth synthetic target.
+* The query path: with tau below every sigma all answers are RTW cell values
+  (bitwise those of rtw_batch + rtw_cell_log_intensity); with tau above every
+  sigma all answers are the surrogate's predictions.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2403_13856_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_13856_amd import rtw
+    rtw.load()
+    rtw.sload()
+    return rtw
+
+
+FS = np.array([1.0, 1.0, 5.0, 1.4, 0.0, 90.0, 0.0, 145.0, 180.0], np.float32)
+FC = np.array([0.2, 0.2, 1.5, 0.1, 180.0, 90.0, 180.0, 25.0, 180.0], np.float32)
+TS = np.array([8.0, 8.0], np.float32)
+TC = np.array([3.0, 3.0], np.float32)
+NORM = (FS, FC, TS, TC)
+
+
+def _feats(rng, n):
+    f = np.empty((n, 9), np.float32)
+    f[:, 0] = rng.uniform(0.8, 1.2, n); f[:, 1] = rng.uniform(0.8, 1.2, n)
+    f[:, 2] = rng.uniform(np.log(200), np.log(5000), n); f[:, 3] = rng.uniform(1.3, 1.5, n)
+    f[:, 4] = rng.uniform(-180, 180, n); f[:, 5] = rng.uniform(0, 180, n); f[:, 6] = rng.uniform(-180, 180, n)
+    f[:, 7] = rng.uniform(120, 170, n); f[:, 8] = rng.uniform(0, 360, n)
+    return f
+
+
+def _net(R, seed, max_rows=4096, scale=None):
+    s = R.Surrogate(seed=seed, max_rows=max_rows)
+    s.set_normalization(*NORM)
+    if scale is not None:  # larger output weights, so that the test exercises every layer
+        rng = np.random.default_rng(seed)
+        p = s.get_params()
+        p = p + (p != 0) * rng.normal(0, scale, p.size).astype(np.float32)
+        s.set_params(p)
+    return s
+
+
+def test_forward_matches_reference(R):
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(1)
+    s = _net(R, 11, scale=0.02)
+    f = _feats(rng, 300)  # not a multiple of the 128-row tile
+    say("[surrogate forward] 300 rows vs FP64 reference on BF16 operands")
+    got = s.forward(torch.from_numpy(f).cuda()).cpu().numpy()
+    ref = M.predict(s.get_params(), f, NORM, bf16_ops=True)
+    err = np.abs(got - ref) / (1.0 + np.abs(ref))
+    say(f"   max scaled error {err.max():.3e}")
+    assert err.max() < 2e-2
+
+
+def test_gradients_match_reference(R):
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(2)
+    s = _net(R, 12, scale=0.02)
+    f = _feats(rng, 256)
+    y = rng.normal(8.0, 3.0, size=(256, 2)).astype(np.float32)
+    say("[surrogate gradients] 256 rows vs FP64 reference on BF16 operands")
+    loss = s.grad(torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda()).item()
+    g = s.get_grads()
+    lr, gr = M.loss_and_grad(s.get_params(), f, y, NORM, bf16_ops=True)
+    assert abs(loss - lr) <= 1e-2 * abs(lr)
+    for l, ((Wg, bg), (Wr, br)) in enumerate(zip(M.unpack(g), M.unpack(gr))):
+        for a, b, name in ((Wg, Wr, "W"), (bg, br, "b")):
+            nb = np.linalg.norm(b)
+            if nb == 0:
+                assert np.linalg.norm(a) == 0
+                continue
+            rel = np.linalg.norm(a - b) / nb
+            cos = float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * nb))
+            say(f"   layer {l} {name}: rel {rel:.2e} cos {cos:.6f}")
+            assert rel < 5e-2 and cos > 0.995
+
+
+def test_training_reduces_loss(R):
+    rng = np.random.default_rng(3)
+    s = _net(R, 13)
+    f = _feats(rng, 8192)
+    # smooth synthetic target in ln-intensity units
+    x = (f - FS) / FC
+    y = np.stack([8 + 2 * np.sin(2 * x[:, 7]) + x[:, 2] + 0.5 * x[:, 3],
+                  8 + 2 * np.cos(2 * x[:, 7]) + x[:, 2] - 0.5 * x[:, 0]], axis=1).astype(np.float32)
+    ft, yt = torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda()
+    rmse0 = np.sqrt(np.mean((s.forward(ft).cpu().numpy()[:, :2] - y) ** 2))
+    losses = []
+    for it in range(300):
+        a = (it * 1024) % 8192
+        losses.append(s.train_step(ft[a:a + 1024], yt[a:a + 1024], 2e-3).item())
+    say(f"[surrogate training] loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert np.isfinite(losses).all() and losses[-1] < losses[0] - 1.0
+    pred = s.forward(ft).cpu().numpy()
+    rmse = np.sqrt(np.mean((pred[:, :2] - y) ** 2))
+    say(f"   rmse of ln I: {rmse0:.3f} before, {rmse:.3f} after 300 steps")
+    assert rmse < 0.25 * rmse0
+
+
+def test_query_fallback_extremes(R):
+    th, ph = I.batch_node_grid()
+    rng = np.random.default_rng(4)
+    parts = [I.random_ellipsoid(rng, 15.0, 40.0) for _ in range(5)]
+    sides = [64, 48, 80, 64, 56]
+    cells = R.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
+    inc = R.make_incident(0.6328, 2)
+    opts = R.make_opts(0, 3, 2, R.MIXED)
+    b = R.Batch(parts, sides, inc, opts, th, ph)
+    b()
+    cellI = R.cell_log_intensity(b, cells).cpu().numpy()  # [n_part, 360, 2]
+    feats = R.surrogate_features(parts, inc, cells)
+    n_cells = 360
+    q_part = np.repeat(np.arange(len(parts)), n_cells).astype(np.int32)
+    q_cell = np.tile(np.arange(n_cells), len(parts)).astype(np.int32)
+    s = _net(R, 14)
+    desc = R.Batch(parts, sides, inc, opts, th, ph, allocate=False)
+    ft, qp, qc = (torch.from_numpy(feats).cuda(), torch.from_numpy(q_part).cuda(), torch.from_numpy(q_cell).cuda())
+    say("[surrogate query] tau tiny: every query answered by RTW")
+    ans, pred, used, nrec = s.query(ft, qp, qc, 1e-30, desc, cells)
+    assert nrec == len(parts) and int(used.sum()) == len(q_part)
+    assert np.array_equal(ans.cpu().numpy(), cellI[q_part, q_cell])
+    say("[surrogate query] tau huge: every query answered by the network")
+    ans, pred, used, nrec = s.query(ft, qp, qc, 1e30, desc, cells)
+    assert nrec == 0 and int(used.sum()) == 0
+    assert np.array_equal(ans.cpu().numpy(), pred.cpu().numpy()[:, :2])
