@@ -210,6 +210,168 @@ def bench_batch(args, rtw, inputs):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args, rtw, inputs):
+    """Surrogate of the batched workload: train the BF16 MLP on cell-averaged
+    ln-intensities that rtw_batch computes for seeded particles (cells 5 x 10
+    deg over theta 120-170 deg), calibrate sigma's threshold tau on held-out
+    particles so that accepted answers are within 1% (|d ln I| <= 0.01 for
+    99% of them), then time 1,048,576 queries (128 random cells of each of
+    8192 new particles) answered with RTW fallback, against RTW alone."""
+    import numpy as np
+    import torch
+    rtw.sload()
+    th, ph = inputs.batch_node_grid()
+    cells = rtw.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
+    n_cells = 360
+    inc = rtw.make_incident(inputs.WAVELENGTH, 2)
+    opts = rtw.make_opts(0, 3, 2, rtw.MIXED)
+
+    def traced(seed, n, tune=None):
+        bp = inputs.batch_particles(n, seed=seed)
+        parts = [(p.semi_axes, p.euler_deg, p.m) for p in bp]
+        sides = [p.grid_n for p in bp]
+        b = rtw.Batch(parts, sides, inc, opts, th, ph, tune=tune, incoherent=True)
+        if tune is None:
+            b.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.launch(with_counts=False)
+        cI = rtw.cell_log_intensity(b, cells)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rc, _ = b.status()
+        if rc != rtw.RTW_OK:
+            raise RuntimeError("hit pool overflow in the training batch")
+        tune = b.tune
+        feats = rtw.surrogate_features(parts, inc, cells)
+        del b
+        torch.cuda.empty_cache()
+        return parts, sides, torch.from_numpy(feats).cuda(), cI.reshape(-1, 2), dt, tune
+
+    t0 = time.perf_counter()
+    tune = None
+    F, Y = [], []
+    for seed in (11, 12):
+        _, _, f, y, dt, tune = traced(seed, 4096, tune)
+        F.append(f); Y.append(y)
+        log(f"[surrogate] training data seed {seed}: {y.shape[0]} samples, RTW {dt:.2f} s")
+    F = torch.cat(F); Y = torch.cat(Y)
+    ok = (Y > -50.0).all(dim=1)  # cells no ray reaches hold ln(1e-30): left out of training
+    F, Y = F[ok], Y[ok]
+    fs = np.array([1.0, 1.0, 7.0, 1.4, 0.0, 90.0, 0.0, 145.0, 180.0], np.float32)
+    fc = np.array([0.2, 0.2, 1.0, 0.1, 180.0, 90.0, 180.0, 25.0, 180.0], np.float32)
+    ts = Y.mean(dim=0).cpu().numpy().astype(np.float32)
+    tc = Y.std(dim=0).cpu().numpy().astype(np.float32)
+    net = rtw.Surrogate(seed=0, max_rows=65536)
+    net.set_normalization(fs, fc, ts, tc)
+    n = F.shape[0]
+    bs = 8192
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    perm = torch.randperm(n, device=F.device)
+    for it in range(args.train_steps):
+        a = (it * bs) % (n - bs)
+        if a < bs:
+            perm = torch.randperm(n, device=F.device)
+        idx = perm[a:a + bs]
+        lr = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + np.cos(np.pi * it / args.train_steps))
+        loss = net.train_step(F[idx].contiguous(), Y[idx].contiguous(), lr)
+        if it % 500 == 0 or it == args.train_steps - 1:
+            log(f"[surrogate] step {it}: loss {loss.item():.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"[surrogate] {args.train_steps} steps of {bs} rows in {t_train:.1f} s")
+
+    # calibration of tau on held-out particles
+    _, _, fcal, ycal, _, _ = traced(13, 2048, tune)
+    pred = net.forward(fcal)
+    err = (pred[:, :2] - ycal).abs().max(dim=1).values
+    sig = pred[:, 2:].max(dim=1).values.exp()
+    order = torch.argsort(sig)
+    e_sorted = err[order]
+    ks = torch.arange(1, e_sorted.numel() + 1, device=e_sorted.device)
+
+    def calibrate(err_bar):
+        """Largest prefix (by sigma) in which 99% of the queries are within err_bar."""
+        bad = torch.cumsum((e_sorted > err_bar).int(), 0)
+        okk = bad.float() <= 0.01 * ks.float()
+        k_best = int(torch.nonzero(okk).max().item()) + 1 if okk.any() else 0
+        return (float(sig[order[k_best - 1]].item()) if k_best > 0 else 1e-30), k_best / err.numel()
+
+    tau, acc_cal = calibrate(0.01)
+    others = {f"{b:g}": round(calibrate(b)[1], 4) for b in (0.02, 0.05, 0.1)}
+    log(f"[surrogate] calibration on {err.numel()} held-out queries: median |d ln I| {err.median().item():.4f}; "
+        f"tau {tau:.4g} accepts {acc_cal:.2%} at 1%; accepted fractions at other error bars {others}")
+
+    # timed query set: 8192 new particles x 128 random cells
+    n_qp, k_q = 8192, 128
+    bp = inputs.batch_particles(n_qp, seed=14)
+    parts = [(p.semi_axes, p.euler_deg, p.m) for p in bp]
+    sides = [p.grid_n for p in bp]
+    rng = np.random.default_rng(14)
+    q_cell = rng.integers(0, n_cells, size=(n_qp, k_q)).astype(np.int32)
+    q_part = np.repeat(np.arange(n_qp, dtype=np.int32), k_q)
+    allf = rtw.surrogate_features(parts, inc, cells).reshape(n_qp, n_cells, 9)
+    qf = torch.from_numpy(np.ascontiguousarray(allf[q_part, q_cell.ravel()])).cuda()
+    qp = torch.from_numpy(q_part).cuda()
+    qc = torch.from_numpy(q_cell.ravel().copy()).cuda()
+    n_q = qf.shape[0]
+    # RTW alone: trace every particle the queries touch, then read the queried cells
+    b = rtw.Batch(parts, sides, inc, opts, th, ph, tune=tune, incoherent=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.launch(with_counts=False)
+    cI = rtw.cell_log_intensity(b, cells)
+    truth = cI[qp.long(), qc.long()]
+    torch.cuda.synchronize()
+    t_rtw = time.perf_counter() - t0
+    rc, _ = b.status()
+    if rc != rtw.RTW_OK:
+        raise RuntimeError("hit pool overflow in the query batch")
+    del b, cI
+    torch.cuda.empty_cache()
+    # surrogate with fallback
+    desc = rtw.Batch(parts, sides, inc, opts, th, ph, allocate=False)
+    net.query(qf[:1024], qp[:1024], qc[:1024], 1e30, desc, cells, tune)  # warm-up (allocates the scratch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ans, pred, used, nrec = net.query(qf, qp, qc, tau, desc, cells, tune)
+    torch.cuda.synchronize()
+    t_q = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.forward(qf)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    acc = used == 0
+    e = (ans - truth).abs().max(dim=1).values
+    e_acc = e[acc]
+    frac_acc = float(acc.float().mean().item())
+    p99 = float(torch.quantile(e_acc[:1000000].float(), 0.99).item()) if e_acc.numel() else 0.0
+    frac_bad = float((e_acc > 0.01).float().mean().item()) if e_acc.numel() else 0.0
+    log(f"[surrogate] queries {n_q}: accepted {frac_acc:.2%}, particles re-traced {nrec}/{n_qp}; accepted |d ln I| "
+        f"p99 {p99:.4f}, >1%: {frac_bad:.2%}; time {t_q:.2f} s vs RTW alone {t_rtw:.2f} s; network alone "
+        f"{t_fwd * 1e3:.1f} ms")
+    value = n_q / t_q
+    out = {
+        "metric": "surrogate queries/s at 1% err",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(t_q * 1e3, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": f"{n_q} queries: {k_q} random 5x10 deg cells (theta 120-170) of each of {n_qp} seeded "
+                               f"ellipsoids (batched-workload distribution); MLP 9-512x6-4 trained "
+                               f"{args.train_steps} steps on {n} cell samples of 8192 other ellipsoids",
+                   "tau": tau, "accepted_fraction": frac_acc, "particles_retraced": nrec,
+                   "accepted_err_p99": p99, "accepted_err_gt_1pct": frac_bad,
+                   "rtw_only_queries_per_s": round(n_q / t_rtw, 1), "gain_over_rtw_only": round(t_rtw / t_q, 3),
+                   "network_only_queries_per_s": round(n_q / t_fwd, 1), "train_seconds": round(t_train, 2),
+                   "calibration_accepted_fraction": acc_cal, "calibration_accepted_at_other_bars": others,
+                   "calibration_median_err": float(err.median().item())},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,8 +382,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
-    ap.add_argument("--workload", choices=["ellipsoid", "batch"], default="ellipsoid",
-                    help="ellipsoid: the 2048^2-ray ellipsoid (default); batch: 4096 seeded ellipsoids via rtw_batch")
+    ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate"], default="ellipsoid",
+                    help="ellipsoid: the 2048^2-ray ellipsoid (default); batch: 4096 seeded ellipsoids via rtw_batch; "
+                         "surrogate: train the MLP on rtw_batch data, then time 1M queries with RTW fallback")
+    ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--batch-n", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -249,6 +413,8 @@ def main():
         torch.cuda.empty_cache()
     if args.workload == "batch":
         return bench_batch(args, rtw, inputs)
+    if args.workload == "surrogate":
+        return bench_surrogate(args, rtw, inputs)
     w = inputs.ellipsoid_mixed(args.grid_n)
     n_active, n_tri = count_units(rtw, w, args.grid_n)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "

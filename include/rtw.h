@@ -172,6 +172,9 @@ int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n
  *   out_field  DEVICE [n][n_pol][2][n_theta][n_phi] complex (layout and type as
  *              rtw_farfield), particle i at index i.
  *   ncontrib   DEVICE int32 [n][n_theta*n_phi] or NULL.
+ *   out_incoh  DEVICE [n][n_pol][n_theta*n_phi] (float for RTW_MIXED, double for
+ *              RTW_FP64) or NULL: the incoherent intensity sum_b (|f_b,theta|^2 +
+ *              |f_b,phi|^2) of each node's triangle contributions b.
  *   tune       NULL = defaults (see rtw_tune); rtw_batch_autotune picks one.
  * Synchronises hip_stream once to upload the per-particle metadata (a few
  * hundred bytes per particle) into the workspace, then queues the kernels and
@@ -179,7 +182,7 @@ int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n
  * RTW_ERR_UNSUPPORTED when n_ord grid_n^2 >= 2^30.  Overflow of the hit pool is
  * reported by rtw_farfield_status on the same workspace. */
 int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
-              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib,
+              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* out_incoh,
               const rtw_tune* tune, const rtw_batch_opts* bopts, void* workspace, size_t workspace_bytes,
               void* hip_stream);
 

@@ -4,10 +4,14 @@
  *
  * The paper computes every far field by tracing (section "Strategy of Ray
  * Theory of Waves"); this surrogate is not in the paper.  It learns, from far
- * fields that rtw_batch computes, the log of the cell-averaged intensity
- *     ln I_pol(cell) = ln mean_{nodes in cell} (|F_theta|^2 + |F_phi|^2)
- * of each incident polarisation (x, y) over cells of the (theta, phi) sphere,
- * as a function of nine features of the particle and the cell:
+ * fields that rtw_batch computes, the log of the cell-averaged incoherent
+ * intensity
+ *     ln I_pol(cell) = ln mean_{nodes in cell} sum_b (|f_b,theta|^2 + |f_b,phi|^2)
+ * of each incident polarisation (x, y), b running over the node's triangle
+ * contributions (orders and branches).  Averaged over a cell many fringes
+ * wide, the coherent intensity |sum_b f_b|^2 tends to this value; sampled at
+ * the nodes of a cell it scatters around it by the fringe contrast over the
+ * square root of the node count, too much to learn to 1%.  Features:
  *     (b/a, c/a, ln(k rbar), m, alpha, beta, gamma, theta_cell, phi_cell)
  * with rbar = (abc)^(1/3), Euler angles and cell centres in degrees.
  * Network: 9 -> 512 -> ... (6 hidden layers of width 512, GELU) -> 4 outputs:
@@ -96,10 +100,11 @@ int rtw_surrogate_train_step(rtw_surrogate* h, int n, const float* feats, const 
 int rtw_surrogate_features(int n_part, const rtw_particle* parts, const rtw_incident* inc, int n_cell,
                            const double* cell_theta_deg, const double* cell_phi_deg, float* feats);
 
-/* ln of the cell-averaged intensity of far fields computed by rtw_batch
- * (DEVICE field [n_part][n_pol][2][n_theta][n_phi] complex FP32, grid as
- * passed to rtw_batch) into DEVICE out [n_part][n_cells][n_pol]. */
-int rtw_cell_log_intensity(int n_part, const void* field, int n_pol, const rtw_grid* grid, const rtw_cells* cells,
+/* ln of the cell average of a per-node intensity (DEVICE intensity
+ * [n_part][n_pol][n_theta * n_phi] FP32, e.g. the out_incoh of rtw_batch on
+ * the node grid `grid`) into DEVICE out [n_part][n_cells][n_pol]; cells no
+ * node falls in give 0, cells of zero intensity ln(1e-30). */
+int rtw_cell_log_intensity(int n_part, const float* intensity, int n_pol, const rtw_grid* grid, const rtw_cells* cells,
                            float* out, void* hip_stream);
 
 /* Scratch bytes rtw_surrogate_query needs for these particles (worst case:
@@ -112,7 +117,7 @@ int rtw_surrogate_query_scratch_size(int n_part, const rtw_particle* parts, cons
  * q_cell [n] cell index): the surrogate everywhere (DEVICE pred [n][4]), then
  * every particle with a query whose sigma exceeds tau is traced with rtw_batch
  * (mixed, two polarisations; parts and grid_n are HOST arrays [n_part]) and
- * its queries take the RTW cell values.  DEVICE answer [n][2] = ln I_x, ln I_y;
+ * its queries take the RTW cell values of the incoherent intensity.  DEVICE answer [n][2] = ln I_x, ln I_y;
  * DEVICE used_fallback [n] = 1 where RTW answered; *n_recomputed (host) = the
  * particles traced.  scratch: DEVICE, >= rtw_surrogate_query_scratch_size.
  * Synchronises hip_stream (after the surrogate pass, and before returning). */

@@ -604,8 +604,8 @@ int compute_units() {
 // Queue every kernel of a call on the stream.  With one_meta the single
 // particle's metadata is written by k_setup; otherwise the caller uploaded it.
 template <typename G>
-int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* out, int32_t* ncontrib, char* ws,
-                size_t ws_bytes, hipStream_t st, bool one_meta) {
+int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* out, int32_t* ncontrib, void* incoh,
+                char* ws, size_t ws_bytes, hipStream_t st, bool one_meta) {
   const Shape& S = pl.S;
   const int n_nodes = grid->n_theta * grid->n_phi;
   Layout base = layout(S, 0);
@@ -704,7 +704,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
     hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_heads + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
-                       S.n_pol, (G*)out, ncontrib); }
+                       S.n_pol, (G*)out, ncontrib, (G*)incoh); }
     hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter);
   }
   hipError_t e = hipGetLastError();
@@ -833,8 +833,9 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
   if (rc) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   if (opts->precision == RTW_FP64)
-    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, true);
-  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, true);
+    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)workspace, workspace_bytes, st,
+                               true);
+  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)workspace, workspace_bytes, st, true);
 }
 
 int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
@@ -850,7 +851,7 @@ int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n
 }
 
 int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
-              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib,
+              const rtw_trace_opts* opts, const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* out_incoh,
               const rtw_tune* tune, const rtw_batch_opts* bopts, void* workspace, size_t workspace_bytes,
               void* hip_stream) {
   if (!opts || !inc) return fail(RTW_ERR_INVALID_ARG, "NULL argument struct");
@@ -870,8 +871,10 @@ int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   rc = upload_plan(pl, base, (char*)workspace, st);
   if (rc) return rc;
   if (opts->precision == RTW_FP64)
-    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, false);
-  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, (char*)workspace, workspace_bytes, st, false);
+    return launch_plan<double>(pl, tu, grid, out_field, ncontrib, out_incoh, (char*)workspace, workspace_bytes, st,
+                               false);
+  return launch_plan<float>(pl, tu, grid, out_field, ncontrib, out_incoh, (char*)workspace, workspace_bytes, st,
+                            false);
 }
 
 int rtw_batch_autotune(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
@@ -897,11 +900,11 @@ int rtw_batch_autotune(int n, const rtw_particle* parts, const int* grid_n, cons
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(RTW_ERR_DEVICE, "event creation failed");
   auto trial = [&](const rtw_tune& t, float* ms) -> int {
-    int rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, &t, bopts, workspace,
+    int rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, nullptr, &t, bopts, workspace,
                        workspace_bytes, st);  // warm-up and upload
     if (rc) return rc;
     hipEventRecord(a, st);
-    rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, &t, bopts, workspace,
+    rc = rtw_batch(m, sp.data(), sg.data(), inc, opts, grid, out_field, nullptr, nullptr, &t, bopts, workspace,
                    workspace_bytes, st);
     if (rc) return rc;
     hipEventRecord(b, st);

@@ -67,6 +67,7 @@ enum Epi : int { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_STO
 
 struct GemmArgs {
   int M, N, K;
+  int K_slice;         // K range of one blockIdx.z (split K); = K without splitting
   const bf16* A;
   long lda;
   int transA;
@@ -100,7 +101,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  const int k_begin = blockIdx.z * g.K_slice, k_end = min(g.K, k_begin + g.K_slice);
+  for (int k0 = k_begin; k0 < k_end; k0 += BK) {
     // A tile -> As[m][k]
     if (!g.transA) {
       const int r = t >> 1, kh = (t & 1) * 16;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
         } else if (EPI == EPI_BWD_GELU) {
           g.Gout[o] = (bf16)(v * gelu_grad((float)g.Zin[o]));
         } else {
-          g.Fout[o] = v;
+          g.Fout[(long)blockIdx.z * g.M * g.ldo + o] = v;  // split-K partial
         }
       }
 }
@@ -222,12 +224,33 @@ __global__ void k_sum(const float* partial, int n, float* out) {
   }
 }
 
-// Column sums of a BF16 matrix [rows][cols] (bias gradients), FP32, fixed order.
-__global__ void k_colsum(const bf16* G, int rows, int cols, float* out) {
+// Column sums of a BF16 matrix [rows][cols] (bias gradients), FP32, in a fixed
+// order: blockIdx.y takes a slab of COLSUM_SLAB rows (partial sums), then
+// k_colsum_final adds the slabs in order.
+constexpr int COLSUM_SLAB = 128;
+constexpr int DW_MAX_SPLITS = 32;  // split-K slices of a weight-gradient product
+__global__ void k_colsum(const bf16* G, int rows, int cols, float* partial) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.y * COLSUM_SLAB, r1 = min(rows, r0 + COLSUM_SLAB);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) s += (float)G[(long)r * cols + c];
+  partial[(long)blockIdx.y * cols + c] = s;
+}
+// Sum of split-K partial products [slices][n] in slice order.
+__global__ void k_sum_slices(const float* part, int slices, long n, float* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < slices; ++k) s += part[(long)k * n + i];
+  out[i] = s;
+}
+
+__global__ void k_colsum_final(const float* partial, int slabs, int cols, float* out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += (float)G[(long)r * cols + c];
+  for (int k = 0; k < slabs; ++k) s += partial[(long)k * cols + c];
   out[c] = s;
 }
 
@@ -281,11 +304,11 @@ __device__ __forceinline__ int first_ge(const double* v, int n, double x) {
   return lo;
 }
 
-// ln of the mean of |F_theta|^2 + |F_phi|^2 over the nodes of each cell, per
-// particle and polarisation: out[p][cell][pol].  Cell (tc, pc) holds the nodes
-// with theta in [t0 + tc dt, t0 + (tc + 1) dt) and phi in [p0 + pc dp, ...).
-// One thread per output.
-__global__ void k_cell_log_intensity(int n_part, const float* field, int n_pol, int n_theta, const double* th,
+// ln of the mean over the nodes of each cell of a per-node intensity
+// (inten [p][pol][node]), per particle and polarisation: out[p][cell][pol].
+// Cell (tc, pc) holds the nodes with theta in [t0 + tc dt, t0 + (tc + 1) dt)
+// and phi in [p0 + pc dp, ...).  One thread per output.
+__global__ void k_cell_log_intensity(int n_part, const float* inten, int n_pol, int n_theta, const double* th,
                                      int n_phi, const double* ph, rtw_cells c, float* out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long n_cells = (long)c.n_theta_cells * c.n_phi_cells;
@@ -299,15 +322,12 @@ __global__ void k_cell_log_intensity(int n_part, const float* field, int n_pol, 
   const int it1 = first_ge(th, n_theta, c.theta0_deg + (tc + 1) * c.dtheta_deg);
   const int ip0 = first_ge(ph, n_phi, c.phi0_deg + pc * c.dphi_deg);
   const int ip1 = first_ge(ph, n_phi, c.phi0_deg + (pc + 1) * c.dphi_deg);
-  const long nodes = (long)n_theta * n_phi;
-  const float* F = field + ((p * n_pol + pol) * 2) * nodes * 2;  // [2 comps][nodes][re, im]
+  const float* I = inten + (p * n_pol + pol) * (long)n_theta * n_phi;
   double s = 0.0;
   int cnt = 0;
   for (int it = it0; it < it1; ++it)
     for (int ip = ip0; ip < ip1; ++ip) {
-      const long nd = (long)it * n_phi + ip;
-      const float a = F[nd * 2], b = F[nd * 2 + 1], e = F[(nodes + nd) * 2], d = F[(nodes + nd) * 2 + 1];
-      s += (double)a * a + (double)b * b + (double)e * e + (double)d * d;
+      s += (double)I[(long)it * n_phi + ip];
       ++cnt;
     }
   out[i] = cnt > 0 ? (float)log(fmax(s / cnt, 1e-30)) : 0.f;
@@ -367,6 +387,8 @@ struct rtw_surrogate {
   bf16* dZout;          // [rows][OUT_PAD]
   float* out;           // [rows][OUT_PAD]
   float* partial;       // loss partial sums
+  float* colpart;       // bias-gradient partial sums [slabs][512]
+  float* wpart;         // split-K partial weight gradients [DW_MAX_SPLITS][512][512]
   float* norm;          // feature shift[9], scale[9], target shift[2], scale[2]
   std::vector<void*> allocs;
 };
@@ -379,9 +401,15 @@ int dmalloc(rtw_surrogate* h, void** p, size_t bytes) {
   return RTW_OK;
 }
 
-int gemm(int epi, const GemmArgs& g, hipStream_t st) {
+int gemm(int epi, GemmArgs g, hipStream_t st, int splits = 1, int* used_splits = nullptr) {
   if (g.M % BM || g.N % BN || g.K % BK) return mfail(RTW_ERR_INVALID_ARG, "gemm shape %d x %d x %d", g.M, g.N, g.K);
-  dim3 grid(g.N / BN, g.M / BM);
+  const int steps = g.K / BK;
+  splits = std::max(1, std::min(splits, steps));
+  g.K_slice = (steps + splits - 1) / splits * BK;
+  splits = (g.K + g.K_slice - 1) / g.K_slice;
+  if (splits > 1 && epi != EPI_STORE_F32) return mfail(RTW_ERR_INVALID_ARG, "split K only for weight gradients");
+  if (used_splits) *used_splits = splits;
+  dim3 grid(g.N / BN, g.M / BM, splits);
   switch (epi) {
     case EPI_FWD_GELU: hipLaunchKernelGGL(k_gemm<EPI_FWD_GELU>, grid, dim3(256), 0, st, g); break;
     case EPI_FWD_LINEAR: hipLaunchKernelGGL(k_gemm<EPI_FWD_LINEAR>, grid, dim3(256), 0, st, g); break;
@@ -489,6 +517,8 @@ int rtw_surrogate_create(uint64_t seed, int max_rows, rtw_surrogate** out) {
   A((void**)&h->dZout, 2 * R * OUT_PAD);
   A((void**)&h->out, 4 * R * OUT_PAD);
   A((void**)&h->partial, 4 * (R / 256 + 1));
+  A((void**)&h->colpart, 4 * (size_t)(R / COLSUM_SLAB + 1) * HID);
+  A((void**)&h->wpart, 4 * (size_t)DW_MAX_SPLITS * HID * HID);
   A((void**)&h->norm, 4 * 22);
   if (rc) { rtw_surrogate_destroy(h); return rc; }
   // seeded initialisation: uniform(-b, b) with b = sqrt(6 / fan_in) (He, for GELU),
@@ -650,9 +680,19 @@ int rtw_surrogate_grad(rtw_surrogate* h, int n, const float* feats, const float*
     GemmArgs g = gargs(in, out, n_pad);
     g.A = xin; g.lda = in; g.transA = 1;
     g.B = dz; g.ldb = out; g.transB = 0;
-    g.ldo = out; g.Fout = h->gW[l];
-    if ((rc = gemm(EPI_STORE_F32, g, st))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256), dim3(256), 0, st, dz, n_pad, out, h->gb[l]);
+    g.ldo = out; g.Fout = h->wpart;
+    // split the batch dimension so that the small weight matrix fills the
+    // chip; the slices are added in a fixed order
+    const int tiles = (in / BM) * (out / BN);
+    const int splits = std::max(1, std::min(DW_MAX_SPLITS, 512 / tiles));
+    int used = 1;
+    if ((rc = gemm(EPI_STORE_F32, g, st, splits, &used))) return rc;
+    const long nw = (long)in * out;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, h->wpart, used, nw,
+                       h->gW[l]);
+    const int slabs = (n_pad + COLSUM_SLAB - 1) / COLSUM_SLAB;
+    hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256, slabs), dim3(256), 0, st, dz, n_pad, out, h->colpart);
+    hipLaunchKernelGGL(k_colsum_final, dim3((out + 255) / 256), dim3(256), 0, st, h->colpart, slabs, out, h->gb[l]);
     if (l > 0) {
       // dZ_{l-1} = (dZ W^T) * gelu'(Z_{l-1})
       bf16* dn = bufs[l & 1];
@@ -685,9 +725,9 @@ int rtw_surrogate_get_grads(rtw_surrogate* h, float* host, size_t n) {
   return RTW_OK;
 }
 
-int rtw_cell_log_intensity(int n_part, const void* field, int n_pol, const rtw_grid* grid, const rtw_cells* cells,
+int rtw_cell_log_intensity(int n_part, const float* intensity, int n_pol, const rtw_grid* grid, const rtw_cells* cells,
                            float* out, void* hip_stream) {
-  if (!field || !grid || !cells || !out || n_part < 1 || (n_pol != 1 && n_pol != 2))
+  if (!intensity || !grid || !cells || !out || n_part < 1 || (n_pol != 1 && n_pol != 2))
     return mfail(RTW_ERR_INVALID_ARG, "bad arguments");
   if (grid->n_theta < 1 || grid->n_phi < 1 || !grid->theta_deg || !grid->phi_deg)
     return mfail(RTW_ERR_INVALID_ARG, "empty node grid");
@@ -696,7 +736,7 @@ int rtw_cell_log_intensity(int n_part, const void* field, int n_pol, const rtw_g
   hipStream_t st = (hipStream_t)hip_stream;
   const long n_out = (long)n_part * cells->n_theta_cells * cells->n_phi_cells * n_pol;
   hipLaunchKernelGGL(k_cell_log_intensity, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, n_part,
-                     (const float*)field, n_pol, grid->n_theta, grid->theta_deg, grid->n_phi, grid->phi_deg, *cells,
+                     intensity, n_pol, grid->n_theta, grid->theta_deg, grid->n_phi, grid->phi_deg, *cells,
                      out);
   if (hipGetLastError() != hipSuccess) return mfail(RTW_ERR_DEVICE, "launch failed");
   return RTW_OK;
@@ -742,8 +782,9 @@ int rtw_surrogate_query_scratch_size(int n_part, const rtw_particle* parts, cons
   int rc = rtw_batch_workspace_size(n_part, parts, grid_n, inc, opts, grid, &bo, &ws);
   if (rc) return mfail(rc, "%s", rtw_last_error());
   const size_t n_cells = (size_t)cells->n_theta_cells * cells->n_phi_cells;
+  const size_t nodes = (size_t)grid->n_theta * grid->n_phi;
   *bytes = 256 + a256(8 * (size_t)n_part) + a256(sizeof(float) * n_part * n_cells * 2) + a256(ws) +
-           (size_t)n_part * 2 * 2 * grid->n_theta * grid->n_phi * 2 * sizeof(float);
+           a256((size_t)n_part * 2 * 2 * nodes * 2 * sizeof(float)) + (size_t)n_part * 2 * nodes * sizeof(float);
   return RTW_OK;
 }
 
@@ -797,12 +838,14 @@ int rtw_surrogate_query(rtw_surrogate* h, int n_query, const float* feats, const
     rc = rtw_batch_workspace_size((int)fp.size(), fp.data(), fg.data(), inc, opts, grid, &bo, &wsb);
     if (rc) return mfail(rc, "%s", rtw_last_error());
     wsb = a256(wsb);
+    const size_t nodes = (size_t)grid->n_theta * grid->n_phi;
     char* ff = ws + wsb;
-    rc = rtw_batch((int)fp.size(), fp.data(), fg.data(), inc, opts, grid, ff, nullptr, tune, &bo, ws, wsb,
+    float* incoh = (float*)(ff + a256(fp.size() * 2 * 2 * nodes * 2 * sizeof(float)));
+    rc = rtw_batch((int)fp.size(), fp.data(), fg.data(), inc, opts, grid, ff, nullptr, incoh, tune, &bo, ws, wsb,
                    hip_stream);
     if (!rc) rc = rtw_farfield_status(ws, hip_stream, nullptr);
     if (rc) return mfail(rc, "fallback: %s", rtw_last_error());
-    rc = rtw_cell_log_intensity((int)fp.size(), ff, 2, grid, cells, cellI, hip_stream);
+    rc = rtw_cell_log_intensity((int)fp.size(), incoh, 2, grid, cells, cellI, hip_stream);
     if (rc) return rc;
   }
   // 4. answers (dslot was uploaded synchronously before its first use by hipMemcpyAsync ordering)

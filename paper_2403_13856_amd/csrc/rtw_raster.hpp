@@ -949,10 +949,12 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
 
 // One thread per node of the chunk (particle-major): walk the node's hit list,
 // order the hits by triangle key, sum them in that order and write (F_theta,
-// F_phi) for every polarisation into the particle's output block.
+// F_phi) for every polarisation into the particle's output block; optionally
+// also the incoherent intensity sum_b (|f_b,theta|^2 + |f_b,phi|^2) of the
+// node's contributions per polarisation.
 template <typename G>
 __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPool<G> pool, int n_nodes, int n_pol,
-                                                  G* out, int32_t* ncontrib) {
+                                                  G* out, int32_t* ncontrib, G* incoh) {
   const long gn = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gn >= (long)B.n * n_nodes) return;
   const int pl = (int)(gn / n_nodes);
@@ -970,13 +972,16 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
     }
     ++cnt;
   }
-  G acc[8];
+  G acc[8], inc[2] = {0, 0};
   for (int i = 0; i < 8; ++i) acc[i] = 0;
   const int w = n_pol * 4;
   if (cnt <= NODE_SORT_MAX) {
     for (int i = 0; i < cnt; ++i) {
       const G* c = pool.contrib + (long)idxs[i] * w;
       for (int k = 0; k < w; ++k) acc[k] += c[k];
+      for (int p = 0; p < n_pol; ++p)
+        inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
+                  c[4 * p + 3] * c[4 * p + 3];
     }
   } else {
     // more hits than the register window: repeated minimum search, same order
@@ -991,6 +996,9 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
       last = best;
       const G* c = pool.contrib + (long)bi * w;
       for (int k = 0; k < w; ++k) acc[k] += c[k];
+      for (int p = 0; p < n_pol; ++p)
+        inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
+                  c[4 * p + 3] * c[4 * p + 3];
     }
   }
   G* po = out + ob * ((long)n_pol * 2 * n_nodes * 2);
@@ -1001,6 +1009,8 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
       po[o + 1] = acc[p * 4 + a * 2 + 1];
     }
   if (ncontrib) ncontrib[ob * n_nodes + node] = cnt;
+  if (incoh)
+    for (int p = 0; p < n_pol; ++p) incoh[(ob * n_pol + p) * n_nodes + node] = inc[p];
 }
 
 }  // namespace rtw

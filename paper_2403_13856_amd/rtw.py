@@ -89,8 +89,8 @@ def load():
     L.rtw_batch_workspace_size.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts),
                                            P(Grid), P(BatchOpts), P(ctypes.c_size_t)]
     L.rtw_batch.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts), P(Grid),
-                            ctypes.c_void_p, ctypes.c_void_p, P(Tune), P(BatchOpts), ctypes.c_void_p, ctypes.c_size_t,
-                            ctypes.c_void_p]
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, P(Tune), P(BatchOpts), ctypes.c_void_p,
+                            ctypes.c_size_t, ctypes.c_void_p]
     L.rtw_batch_autotune.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts),
                                      P(Grid), P(BatchOpts), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p, P(Tune)]
@@ -266,6 +266,7 @@ class Batch:
     tune: Optional[Tune] = None
     device: str = "cuda"
     allocate: bool = True  # False: describe the particles only (no workspace or output)
+    incoherent: bool = False  # also return per-node incoherent intensities (self.incoh)
 
     def __post_init__(self):
         import torch
@@ -287,6 +288,8 @@ class Batch:
         self.out = torch.empty((n, self.inc.n_pol, 2, self.theta.numel(), self.phi.numel(), 2), dtype=dt,
                                device=self.device)
         self.ncontrib = torch.empty((n, self.theta.numel(), self.phi.numel()), dtype=torch.int32, device=self.device)
+        self.incoh = torch.empty((n, self.inc.n_pol, self.theta.numel() * self.phi.numel()), dtype=dt,
+                                 device=self.device) if self.incoherent else None
 
     def _alloc(self, nbytes):
         import torch
@@ -297,7 +300,8 @@ class Batch:
     def launch(self, stream=None, with_counts=True):
         _check(load().rtw_batch(self.n, self.parts, self.gn, ctypes.byref(self.inc), ctypes.byref(self.opts),
                                 ctypes.byref(self.grid), _ptr(self.out), _ptr(self.ncontrib) if with_counts else None,
-                                ctypes.byref(self.tune) if self.tune is not None else None, ctypes.byref(self.bopts),
+                                _ptr(self.incoh), ctypes.byref(self.tune) if self.tune is not None else None,
+                                ctypes.byref(self.bopts),
                                 ctypes.c_void_p(self.ws_ptr), ctypes.c_size_t(self.ws_bytes), _stream_ptr(stream)))
 
     def autotune(self, stream=None):
@@ -423,11 +427,14 @@ def surrogate_features(particles, inc, cells):
 
 
 def cell_log_intensity(batch, cells, stream=None):
-    """ln cell-mean intensity [n_part, n_cells, n_pol] of a computed Batch (device tensor)."""
+    """ln cell-mean incoherent intensity [n_part, n_cells, n_pol] of a computed
+    Batch made with incoherent=True (mixed precision)."""
     import torch
+    if batch.incoh is None or batch.incoh.dtype != torch.float32:
+        raise ValueError("needs a mixed-precision Batch with incoherent=True")
     n_cells = cells.n_theta_cells * cells.n_phi_cells
     out = torch.empty((batch.n, n_cells, batch.inc.n_pol), dtype=torch.float32, device=batch.device)
-    _scheck(sload().rtw_cell_log_intensity(batch.n, _ptr(batch.out), batch.inc.n_pol, ctypes.byref(batch.grid),
+    _scheck(sload().rtw_cell_log_intensity(batch.n, _ptr(batch.incoh), batch.inc.n_pol, ctypes.byref(batch.grid),
                                            ctypes.byref(cells), _ptr(out), _stream_ptr(stream)))
     return out
 

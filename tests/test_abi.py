@@ -121,11 +121,11 @@ def test_batch_workspace_and_validation_without_device():
     G = (ctypes.c_int * n)(*sides)
     g = rtw.Grid(361, 1, 180, 1)
     args = (n, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g))
-    assert L.rtw_batch(*args, None, None, None, None, None, 0, None) == rtw.RTW_ERR_INVALID_ARG
-    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, None, None, ctypes.c_void_p(4096 + 8), 1 << 30,
+    assert L.rtw_batch(*args, None, None, None, None, None, None, 0, None) == rtw.RTW_ERR_INVALID_ARG
+    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, None, None, None, ctypes.c_void_p(4096 + 8), 1 << 30,
                        None) == rtw.RTW_ERR_INVALID_ARG
     t = rtw.Tune(300, 8, 32)
-    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, ctypes.byref(t), None, ctypes.c_void_p(4096), 1 << 30,
+    assert L.rtw_batch(*args, ctypes.c_void_p(256), None, None, ctypes.byref(t), None, ctypes.c_void_p(4096), 1 << 30,
                        None) == rtw.RTW_ERR_INVALID_ARG
     assert L.rtw_batch(0, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g), ctypes.c_void_p(256), None,
-                       None, None, ctypes.c_void_p(4096), 1 << 30, None) == rtw.RTW_ERR_INVALID_ARG
+                       None, None, None, ctypes.c_void_p(4096), 1 << 30, None) == rtw.RTW_ERR_INVALID_ARG

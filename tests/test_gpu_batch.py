@@ -152,3 +152,21 @@ def test_batch_argument_errors(R):
     b.tune = R.Tune(300, 8, 32)  # not a multiple of 256
     with pytest.raises(R.RTWError):
         b.launch()
+
+
+def test_batch_incoherent_intensity_matches_oracle(oracle, R):
+    """Per-node incoherent intensity sum_b |f_b|^2 (the surrogate's training
+    quantity) against the oracle's, summed over the two polarisations."""
+    th, ph = I.batch_node_grid()
+    parts, sides = _small_batch(21, 3, [48, 64, 40])
+    for prec, P, tol in (("fp64", R.FP64, 1e-10), ("mixed", R.MIXED, 1e-4)):
+        b = R.Batch(parts, sides, R.make_incident(0.6328, 2), R.make_opts(0, 3, 2, P), th, ph, incoherent=True)
+        b()
+        inc = b.incoh.cpu().numpy().sum(axis=1).reshape(len(parts), th.size, ph.size)
+        for i in range(len(parts)):
+            ref = oracle.farfield(oracle.particle(*parts[i]), oracle.setup(0.6328, 2, 0, 3, sides[i]), th, ph)
+            clean = ref["flags"] == 0
+            rel = np.abs(inc[i] - ref["incoh"])[clean] / np.maximum(ref["incoh"][clean], 1e-300)
+            rel = rel[ref["incoh"][clean] > 0]
+            say(f"[incoherent {prec}] particle {i}: max relative difference {rel.max(initial=0):.2e}")
+            assert rel.max(initial=0) < tol

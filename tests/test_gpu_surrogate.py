@@ -111,14 +111,15 @@ def test_training_reduces_loss(R):
     ft, yt = torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda()
     rmse0 = np.sqrt(np.mean((s.forward(ft).cpu().numpy()[:, :2] - y) ** 2))
     losses = []
-    for it in range(300):
+    for it in range(600):
         a = (it * 1024) % 8192
-        losses.append(s.train_step(ft[a:a + 1024], yt[a:a + 1024], 2e-3).item())
-    say(f"[surrogate training] loss {losses[0]:.3f} -> {losses[-1]:.3f}")
-    assert np.isfinite(losses).all() and losses[-1] < losses[0] - 1.0
+        losses.append(s.train_step(ft[a:a + 1024], yt[a:a + 1024], 1e-3).item())
+    first, last = np.mean(losses[:20]), np.mean(losses[-20:])
+    say(f"[surrogate training] mean minibatch loss {first:.3f} (first 20 steps) -> {last:.3f} (last 20)")
+    assert np.isfinite(losses).all() and last < first - 1.0
     pred = s.forward(ft).cpu().numpy()
     rmse = np.sqrt(np.mean((pred[:, :2] - y) ** 2))
-    say(f"   rmse of ln I: {rmse0:.3f} before, {rmse:.3f} after 300 steps")
+    say(f"   rmse of ln I: {rmse0:.3f} before, {rmse:.3f} after 600 steps")
     assert rmse < 0.25 * rmse0
 
 
@@ -130,7 +131,7 @@ def test_query_fallback_extremes(R):
     cells = R.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
     inc = R.make_incident(0.6328, 2)
     opts = R.make_opts(0, 3, 2, R.MIXED)
-    b = R.Batch(parts, sides, inc, opts, th, ph)
+    b = R.Batch(parts, sides, inc, opts, th, ph, incoherent=True)
     b()
     cellI = R.cell_log_intensity(b, cells).cpu().numpy()  # [n_part, 360, 2]
     feats = R.surrogate_features(parts, inc, cells)
