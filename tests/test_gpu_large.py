@@ -1,0 +1,161 @@
+"""The large-scatterer workload: ellipsoid 1000/950/900 um (size parameter
+~10^4), m = 1.333, p = 0..5, rainbow band theta 120-170 deg at 0.02 deg.
+
+* At its full size (8192^2 rays) the per-ray records of 4096 sampled rays --
+  uniform over the shadow and crowded at the grazing rim -- match the oracle
+  traced at the same entry points, FP64 and mixed.  The FP64 phase reaches
+  1.6e5 rad here: both sides round it in different orders, so the bar is the
+  FP64 rounding of the phase itself (50 eps Phi) where that exceeds 1e-10.
+* The far field on a strip of the rainbow band, with the ray grid reduced to
+  1024^2 so that the oracle finishes, matches the oracle element by element.
+* The full-size far field (mixed) completes without overflow, and its
+  intensity obeys the mirror symmetries of an axis-aligned ellipsoid under
+  x-polarised incidence: I(theta, phi) = I(theta, -phi) = I(theta, 180 - phi).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2403_13856_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_13856_amd import rtw
+    rtw.load()
+    return rtw
+
+
+W = I.large_ellipsoid()
+K = 2 * np.pi / W.wavelength
+PHI_MAX = K * W.m * 2 * (W.p_max + 1) * max(W.semi_axes)
+FP64_PHASE_TOL = max(1e-10, 50 * 2.22e-16 * PHI_MAX)
+
+
+def _sample_rays(oracle, N, n_uniform=3000, n_rim=1096, seed=5):
+    op = oracle.particle(W.semi_axes, W.euler_deg, W.m)
+    L = oracle.grid_halfwidth(op)
+    h = 2 * L / N
+    rng = np.random.default_rng(seed)
+    a, b = W.semi_axes[0], W.semi_axes[1]
+    ids = []
+    while len(ids) < n_uniform:
+        ix, iy = rng.integers(0, N, 2)
+        x, y = -L + (ix + 0.5) * h, -L + (iy + 0.5) * h
+        if (x / a) ** 2 + (y / b) ** 2 < 1:
+            ids.append(iy * N + ix)
+    t = rng.uniform(0, 2 * np.pi, n_rim)
+    r = 1 - rng.uniform(0, 2e-3, n_rim)  # within 0.2% of the rim: grazing incidence
+    ix = np.clip(np.floor((r * a * np.cos(t) + L) / h), 0, N - 1).astype(int)
+    iy = np.clip(np.floor((r * b * np.sin(t) + L) / h), 0, N - 1).astype(int)
+    ids = np.unique(np.concatenate([np.array(ids), iy * N + ix]))
+    xy = np.stack([-L + (ids % N + 0.5) * h, -L + (ids // N + 0.5) * h], axis=1)
+    return op, ids, xy
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_size_sampled_rays(oracle, R, prec):
+    N = W.grid_n
+    P = R.FP64 if prec == "fp64" else R.MIXED
+    op, ids, xy = _sample_rays(oracle, N)
+    say(f"[large {prec}] {N}^2 rays, p={W.p_min}..{W.p_max}, {ids.size} sampled rays; phase bar {FP64_PHASE_TOL:.2e}")
+    rec = R.trace(R.make_particle(W.semi_axes, W.euler_deg, W.m), R.make_incident(W.wavelength, 1),
+                  R.make_opts(W.p_min, W.p_max, N, P))
+    idx = torch.from_numpy(ids).cuda()
+    got = {k: v[..., idx].cpu().numpy() for k, v in rec.items() if k in ("flags", "dir", "rexit", "phase", "amp")}
+    del rec
+    torch.cuda.empty_cache()
+    rays = oracle.trace_rays(op, oracle.setup(W.wavelength, 1, W.p_min, W.p_max, N), xy)
+    n_ord = W.p_max - W.p_min + 1
+    flags_ok = checked = 0
+    worst = dict(dir=0.0, phase=0.0, amp=0.0)
+    for j in range(ids.size):
+        for o in range(n_ord):
+            e = oracle.ray_emit(rays[j], W.p_min + o)
+            f = int(got["flags"][o, j])
+            ref_flag = (1 | (e["nf"] << 1) | (int(e["det_neg"]) << 8)) if e["valid"] else 0
+            flags_ok += f == ref_flag
+            if not e["valid"] or f != ref_flag:
+                continue
+            checked += 1
+            d = got["dir"][o, :, j]
+            worst["dir"] = max(worst["dir"], np.abs(d - e["dir"]).max())
+            if prec == "fp64":
+                dph = abs(got["phase"][o, j] - e["phase"])
+            else:
+                carried = got["phase"][o, j] + K * np.dot(got["rexit"][o, :, j], d - e["dir"])
+                dph = abs(np.angle(np.exp(1j * (carried - e["phase"]))))
+            worst["phase"] = max(worst["phase"], dph)
+            worst["amp"] = max(worst["amp"], abs(got["amp"][o, j] - e["amp"]) / max(e["amp"], 1e-300))
+    frac = flags_ok / (ids.size * n_ord)
+    say(f"   flags agree {frac:.5f}; {checked} emissions compared; worst {worst}")
+    if prec == "fp64":
+        assert frac == 1.0
+        assert worst["dir"] < 1e-12 and worst["phase"] < FP64_PHASE_TOL and worst["amp"] < 1e-9
+    else:
+        assert frac > 0.999
+        assert worst["dir"] < 1e-3 and worst["phase"] < 1e-3 and worst["amp"] < 1e-3
+
+
+def test_reduced_grid_farfield_strip(oracle, R):
+    N = 1024
+    th = I.uniform_angles(120.0, 170.0, 0.02)
+    ph = I.uniform_angles(0.0, 10.0, 0.5)
+    op = oracle.particle(W.semi_axes, W.euler_deg, W.m)
+    ref = oracle.farfield(op, oracle.setup(W.wavelength, 1, W.p_min, W.p_max, N), th, ph)
+    clean = ref["flags"] == 0
+    inc = ref["incoh"]
+    for prec, P in (("fp64", R.FP64), ("mixed", R.MIXED)):
+        ff = R.FarField(R.make_particle(W.semi_axes, W.euler_deg, W.m), R.make_incident(W.wavelength, 1),
+                        R.make_opts(W.p_min, W.p_max, N, P), th, ph)
+        F = ff().cpu().numpy()
+        if prec == "fp64":
+            err = np.abs(F - ref["field"]).max(axis=(0, 1))
+            worst = (err / np.maximum(np.sqrt(inc), 1e-300))[clean & (inc > 0)].max(initial=0.0)
+            say(f"[large strip fp64] {N}^2 rays, {th.size}x{ph.size} nodes: worst relative {worst:.2e} "
+                f"(bar {FP64_PHASE_TOL:.2e})")
+            assert worst < FP64_PHASE_TOL
+        else:
+            unc = np.maximum(ref["uncancelled"], inc)
+            I_ref = (np.abs(ref["field"]) ** 2).sum(axis=(0, 1))
+            I_got = (np.abs(F) ** 2).sum(axis=(0, 1))
+            sel = clean & (inc > 0)
+            rel = (np.abs(I_got - I_ref)[sel] / unc[sel]).max(initial=0.0)
+            big = (np.abs(ref["field"]) >= 0.1 * np.sqrt(inc)[None, None]) & sel[None, None]
+            dph = np.abs(np.angle(F[big] * np.conj(ref["field"][big]))).max(initial=0.0)
+            say(f"[large strip mixed] intensity rel {rel:.2e} phase {dph:.2e}")
+            assert rel < 1e-4 and dph < 1e-3
+
+
+def test_full_size_farfield_mirror_symmetry(R):
+    th, ph = W.theta_deg, W.phi_deg
+    say(f"[large full] mixed far field, {W.grid_n}^2 rays, {th.size}x{ph.size} nodes")
+    ff = R.FarField(R.make_particle(W.semi_axes, W.euler_deg, W.m), R.make_incident(W.wavelength, 1),
+                    R.make_opts(W.p_min, W.p_max, W.grid_n, R.MIXED), th, ph)
+    F = ff()
+    hits, fp64 = ff.stats()
+    I_ = (F.abs() ** 2).sum(dim=(0, 1)).cpu().numpy()  # [n_theta, n_phi]
+    say(f"   hits {hits}, FP64 re-traced rays {fp64}")
+    j = np.arange(ph.size)
+    neg = (ph.size - j) % ph.size                    # -phi
+    sup = np.round(((180.0 - ph) % 360.0) / 0.5).astype(int) % ph.size  # 180 - phi
+    band = (th >= 120.0) & (th <= 170.0) & (th > 0.2) & (th < 179.8)
+    for name, jj in (("phi -> -phi", neg), ("phi -> 180 - phi", sup)):
+        a, b = I_[band][:, j], I_[band][:, jj]
+        scale = np.maximum(a + b, 1e-30)
+        rel = np.abs(a - b) / scale
+        live = (a + b) > 1e-6 * np.median(a + b)
+        say(f"   {name}: median relative difference {np.median(rel[live]):.2e}, 99% {np.quantile(rel[live], 0.99):.2e}")
+        assert np.median(rel[live]) < 1e-3 and np.quantile(rel[live], 0.99) < 5e-2
