@@ -81,6 +81,8 @@ struct GemmArgs {
   float* Fout;         // [M][N] FP32    (forward linear, weight gradients)
   const bf16* Zin;     // [M][N] BF16    (backward: pre-activation of the layer below)
   bf16* Gout;          // [M][N] BF16    (backward: gradient w.r.t. that pre-activation)
+  float* colsum;       // [splits][N] FP32 or null (weight gradients: column sums of B over each K
+                       //                 slice, i.e. the bias gradient when B = dZ)
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678f)); }
@@ -101,6 +103,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  float csum = 0.f;  // column sum of B over this block's K slice (weight-gradient products)
   const int k_begin = blockIdx.z * g.K_slice, k_end = min(g.K, k_begin + g.K_slice);
   for (int k0 = k_begin; k0 < k_end; k0 += BK) {
     // A tile -> As[m][k]
@@ -130,6 +133,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       for (int j = 0; j < 8; ++j) { Bs[nc + j][kk] = v0[j]; Bs[nc + 8 + j][kk] = v1[j]; }
     }
     __syncthreads();
+    if (EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0) {
+      // column sums of this K step of B, in a fixed order (two halves of k per column)
+      const int n = t & 127, kh = (t >> 7) * 16;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) csum += (float)Bs[n][kh + j];
+    }
     bf16x8 af[4], bfr[4];
     const int kq = 8 * (lane >> 4), rr = lane & 15;
 #pragma unroll
@@ -141,6 +150,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     __syncthreads();
+  }
+  if (EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0) {
+    float* red = reinterpret_cast<float*>(&As[0][0]);  // the A tile is free now
+    red[t] = csum;
+    __syncthreads();
+    if (t < 128) g.colsum[(long)blockIdx.z * g.N + n0 + t] = red[t] + red[t + 128];
   }
   // epilogue
 #pragma unroll
@@ -224,19 +239,8 @@ __global__ void k_sum(const float* partial, int n, float* out) {
   }
 }
 
-// Column sums of a BF16 matrix [rows][cols] (bias gradients), FP32, in a fixed
-// order: blockIdx.y takes a slab of COLSUM_SLAB rows (partial sums), then
-// k_colsum_final adds the slabs in order.
-constexpr int COLSUM_SLAB = 128;
 constexpr int DW_MAX_SPLITS = 32;  // split-K slices of a weight-gradient product
-__global__ void k_colsum(const bf16* G, int rows, int cols, float* partial) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  const int r0 = blockIdx.y * COLSUM_SLAB, r1 = min(rows, r0 + COLSUM_SLAB);
-  float s = 0.f;
-  for (int r = r0; r < r1; ++r) s += (float)G[(long)r * cols + c];
-  partial[(long)blockIdx.y * cols + c] = s;
-}
+
 // Sum of split-K partial products [slices][n] in slice order.
 __global__ void k_sum_slices(const float* part, int slices, long n, float* out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,14 +248,6 @@ __global__ void k_sum_slices(const float* part, int slices, long n, float* out) 
   float s = 0.f;
   for (int k = 0; k < slices; ++k) s += part[(long)k * n + i];
   out[i] = s;
-}
-
-__global__ void k_colsum_final(const float* partial, int slabs, int cols, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.f;
-  for (int k = 0; k < slabs; ++k) s += partial[(long)k * cols + c];
-  out[c] = s;
 }
 
 // Adam on FP32 master parameters; refreshes the BF16 copies W[in][out] and
@@ -387,7 +383,7 @@ struct rtw_surrogate {
   bf16* dZout;          // [rows][OUT_PAD]
   float* out;           // [rows][OUT_PAD]
   float* partial;       // loss partial sums
-  float* colpart;       // bias-gradient partial sums [slabs][512]
+  float* colpart;       // split-K partial bias gradients [DW_MAX_SPLITS][512]
   float* wpart;         // split-K partial weight gradients [DW_MAX_SPLITS][512][512]
   float* norm;          // feature shift[9], scale[9], target shift[2], scale[2]
   std::vector<void*> allocs;
@@ -517,7 +513,7 @@ int rtw_surrogate_create(uint64_t seed, int max_rows, rtw_surrogate** out) {
   A((void**)&h->dZout, 2 * R * OUT_PAD);
   A((void**)&h->out, 4 * R * OUT_PAD);
   A((void**)&h->partial, 4 * (R / 256 + 1));
-  A((void**)&h->colpart, 4 * (size_t)(R / COLSUM_SLAB + 1) * HID);
+  A((void**)&h->colpart, 4 * (size_t)DW_MAX_SPLITS * HID);
   A((void**)&h->wpart, 4 * (size_t)DW_MAX_SPLITS * HID * HID);
   A((void**)&h->norm, 4 * 22);
   if (rc) { rtw_surrogate_destroy(h); return rc; }
@@ -680,7 +676,7 @@ int rtw_surrogate_grad(rtw_surrogate* h, int n, const float* feats, const float*
     GemmArgs g = gargs(in, out, n_pad);
     g.A = xin; g.lda = in; g.transA = 1;
     g.B = dz; g.ldb = out; g.transB = 0;
-    g.ldo = out; g.Fout = h->wpart;
+    g.ldo = out; g.Fout = h->wpart; g.colsum = h->colpart;
     // split the batch dimension so that the small weight matrix fills the
     // chip; the slices are added in a fixed order
     const int tiles = (in / BM) * (out / BN);
@@ -690,9 +686,8 @@ int rtw_surrogate_grad(rtw_surrogate* h, int n, const float* feats, const float*
     const long nw = (long)in * out;
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, h->wpart, used, nw,
                        h->gW[l]);
-    const int slabs = (n_pad + COLSUM_SLAB - 1) / COLSUM_SLAB;
-    hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256, slabs), dim3(256), 0, st, dz, n_pad, out, h->colpart);
-    hipLaunchKernelGGL(k_colsum_final, dim3((out + 255) / 256), dim3(256), 0, st, h->colpart, slabs, out, h->gb[l]);
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((out + 255) / 256)), dim3(256), 0, st, h->colpart, used,
+                       (long)out, h->gb[l]);
     if (l > 0) {
       // dZ_{l-1} = (dZ W^T) * gelu'(Z_{l-1})
       bf16* dn = bufs[l & 1];
