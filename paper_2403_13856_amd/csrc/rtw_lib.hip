@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_trace_diag(const ParticleConst P, const
 // call).  With P1 != nullptr the call has one particle, whose metadata is
 // written here from the kernel arguments (no host upload).
 __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg, double* th,
-                        double* ph, double* sth, double* cth, double* sph, double* cph, unsigned* counter,
+                        double* ph, double* sth, double* cth, double* sph, double* cph, float* tf, unsigned* counter,
                         WsHeader* hdr, WsHeader hv, ParticleConst* meta_P, long* meta_off, int* meta_out,
                         ParticleConst P1, int tile, int one) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,12 +306,16 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
     th[i] = t;
     sth[i] = sin(t);
     cth[i] = cos(t);
+    tf[i] = (float)sth[i];
+    tf[n_theta + i] = (float)cth[i];
   }
   if (i < n_phi) {
     double p = phi_deg[i] * D2R;
     ph[i] = p;
     sph[i] = sin(p);
     cph[i] = cos(p);
+    tf[2 * n_theta + i] = (float)sph[i];
+    tf[2 * n_theta + n_phi + i] = (float)cph[i];
   }
   if (i < C_COUNT) counter[i] = 0u;
   if (i == 0) {
@@ -434,8 +438,8 @@ int check_keys(const rtw_trace_opts* o) {
 // Workspace layout (256-byte aligned sections).  Record arrays are sized for
 // the largest chunk; metadata for every particle of the call.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, seg, mP, moff, mout, flags, rr, ang, head, redo, rows, link,
-      contrib, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, head, redo, rows,
+      link, contrib, desc, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -461,20 +465,24 @@ Layout layout(const Shape& S, long cap_total) {
   L.th = take(8 * S.n_theta); L.ph = take(8 * S.n_phi);
   L.sth = take(8 * S.n_theta); L.cth = take(8 * S.n_theta);
   L.sph = take(8 * S.n_phi); L.cph = take(8 * S.n_phi);
+  L.tf = take(4 * 2 * ((size_t)S.n_theta + S.n_phi));  // FP32 sin/cos tables
   L.seg = take(2 * sizeof(AxisSeg));
   L.mP = take(sizeof(ParticleConst) * (size_t)S.n_parts);
   L.moff = take(sizeof(long) * 3 * (size_t)(S.n_parts + 1));
   L.mout = take(sizeof(int) * (size_t)S.n_parts);
   L.flags = take(4 * nrec);
   L.rr = take(rr * nrec);
+  L.dir = take((S.precision == RTW_FP64 ? sizeof(Dir4<double>) : sizeof(Dir4<float>)) * nrec);
   L.ang = take(sizeof(float2) * nrec);
   L.head = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.redo = take(S.precision == RTW_FP64 ? 4 : 4 * (size_t)S.max_chunk_rays);
   L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
   L.fixed = off;
-  L.bytes_per_hit = sizeof(int2) + gs * 4 * S.n_pol;
+  const size_t ds = S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>);
+  L.bytes_per_hit = sizeof(int2) + gs * 4 * S.n_pol + ds;
   L.link = take(sizeof(int2) * (size_t)cap_total);
   L.contrib = take(gs * 4 * S.n_pol * (size_t)cap_total);
+  L.desc = take(ds * (size_t)cap_total);
   L.total = off;
   return L;
 }
@@ -631,10 +639,14 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   ng.sph = (double*)(ws + L.sph); ng.cph = (double*)(ws + L.cph);
   ng.seg_t = (const AxisSeg*)(ws + L.seg);
   ng.seg_p = (const AxisSeg*)(ws + L.seg) + 1;
+  float* tf = (float*)(ws + L.tf);
+  ng.sthf = tf; ng.cthf = tf + grid->n_theta;
+  ng.sphf = tf + 2 * grid->n_theta; ng.cphf = tf + 2 * grid->n_theta + grid->n_phi;
   unsigned* counter = (unsigned*)(ws + L.counter);
   Records<G> rec;
   rec.flags = (int32_t*)(ws + L.flags);
   rec.rr = (RayRec<G>*)(ws + L.rr);
+  rec.dir = (Dir4<G>*)(ws + L.dir);
   rec.ang = (float2*)(ws + L.ang);
   rec.n_pol = S.n_pol;
   rec.n_fp64 = counter + C_REDO;
@@ -643,6 +655,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   pool.head = (int*)(ws + L.head);
   pool.link = (int2*)(ws + L.link);
   pool.contrib = (G*)(ws + L.contrib);
+  pool.desc = (HitDesc<G>*)(ws + L.desc);
   pool.counter = counter;
   pool.cap_part = (int)cap_part;
   pool.rows = (int2*)(ws + L.rows);
@@ -662,7 +675,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   { ProfScope ps("k_setup", st);
   hipLaunchKernelGGL(k_setup, dim3((unsigned)((setup_n + 255) / 256)), dim3(256), 0, st, grid->n_theta,
                      grid->theta_deg, grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth,
-                     (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, counter, (WsHeader*)(ws + L.hdr), hv, mP,
+                     (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, tf, counter, (WsHeader*)(ws + L.hdr), hv, mP,
                      moff, mout, pl.P[0], pl.tile, one_meta ? 1 : 0);
   hipLaunchKernelGGL(k_axis_segments, dim3(2), dim3(256), 0, st, ng.th, ng.n_theta, ng.ph, ng.n_phi,
                      (AxisSeg*)(ws + L.seg), (AxisSeg*)(ws + L.seg) + 1); }
@@ -702,6 +715,9 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
                        pool, BOX_MARGIN, tu.cand_inline); }
     { ProfScope ps(fp64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
     hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
+    { ProfScope ps(fp64 ? "k_store_hits_fp64" : "k_store_hits_mixed", st);
+    const long slots = (long)NPART * cap_part;
+    hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, rec, ng, pool); }
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
     hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_heads + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
                        S.n_pol, (G*)out, ncontrib, (G*)incoh); }

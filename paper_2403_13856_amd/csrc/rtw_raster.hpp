@@ -11,10 +11,11 @@
 // barycentric weights of the central projection, each ray field carried to n
 // with the stationary-phase gradient dPhi/d(dir) = -k r_exit.
 //
-// Membership is watertight: the edge function of an edge is always evaluated
-// from its lower ray index to its higher one with contraction disabled, so the
-// two triangles sharing an edge see the same value and exactly one of them
-// claims a node on it (the one on the edge's positive side on an exact tie).
+// Membership is watertight: the edge normal of an edge is always formed from
+// its lower ray index to its higher one, and its product with a node
+// direction is a fixed sequence of correctly rounded operations, so the two
+// triangles sharing an edge see the same value and exactly one of them claims
+// a node on it (the one on the edge's positive side on an exact tie).
 //
 // Hits are appended to a pool with one atomic per wave per step (wave ballot)
 // on one of NPART counters; each hit is pushed on its node's list with an
@@ -46,17 +47,27 @@ struct NodeGrid {
   const double* cth;
   const double* sph;
   const double* cph;
+  const float* sthf;  // FP32 copies of the four tables
+  const float* cthf;
+  const float* sphf;
+  const float* cphf;
   const AxisSeg* seg_t;
   const AxisSeg* seg_p;
 };
 
-// One ray's emission record for one order, contiguous so that a triangle's
-// vertices are a few cache lines each (the rasteriser gathers them at random).
+// One ray's emission record for one order, contiguous so that the three
+// vertices of a hit are a few cache lines each (gathered at random).  The
+// exit direction lives in its own array of 4-vectors (Records::dir), read
+// coalesced by the rasteriser's per-quad pass.
 template <typename G>
 struct alignas(16) RayRec {
-  G dir[3];   // lab exit direction
   G kr[3];    // k r_exit (lab)
   G f[12];    // [pol][xyz][re|im] lab field amp e^{i phase} (J_perp e_perp + J_par e_par)
+};
+
+template <typename G>
+struct alignas(4 * sizeof(G)) Dir4 {
+  G x, y, z, pad;
 };
 
 // Emission records of the particles of one chunk: particle p owns the index
@@ -66,6 +77,7 @@ template <typename G>
 struct Records {
   int32_t* flags;  // bit0 valid, bits 1..7 nf, bit 8 det_neg
   RayRec<G>* rr;
+  Dir4<G>* dir;    // exit direction
   float2* ang;     // (theta, phi) of the exit direction (rad), phi in [0, 2 pi)
   int n_pol;
   unsigned* n_fp64;  // rays listed for the FP64 re-trace (mixed path)
@@ -97,11 +109,26 @@ __device__ __forceinline__ int find_part(const long* off, int n, long base, long
   return lo;
 }
 
+// A node hit found by the rasteriser, waiting for k_store_hits: which
+// triangle (record base, corner ray, grid side, half, key), which node, and
+// the barycentric weights.
+template <typename G>
+struct HitDesc {
+  int key;
+  int rb;     // record index of (particle, slot, ray 0)
+  int v00;    // corner ray of the quad
+  int nt;     // N << 1 | t
+  int itip;   // node row | node column << 16
+  int node;   // node index within the chunk (particle-major)
+  G lam[3];
+};
+
 template <typename G>
 struct HitPool {
   int* head;          // [n_nodes] first hit of each node, -1 = none
   int2* link;         // [cap] (key, next)
   G* contrib;         // [cap][n_pol * 4]: (pol, theta|phi, re|im)
+  HitDesc<G>* desc;   // [cap] hits found, stored by k_store_hits
   unsigned* counter;  // [NPART]
   int cap_part;       // capacity of each partition
   int2* rows;         // [rows_cap] (triangle key, theta row) of triangles rasterised row by row
@@ -132,7 +159,8 @@ struct RecordSink {
     const long at = base + e.slot * NN + id;
     rec.flags[at] = 1 | (e.nf << 1) | (e.det_neg << 8);
     RayRec<G> r;
-    r.dir[0] = (G)e.dir.x; r.dir[1] = (G)e.dir.y; r.dir[2] = (G)e.dir.z;
+    Dir4<G> dv;
+    dv.x = (G)e.dir.x; dv.y = (G)e.dir.y; dv.z = (G)e.dir.z; dv.pad = (G)0;
     r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
     // The field's phase contains -k dir.r_exit and the rasteriser carries it
     // with k r_exit.(dir - n) using the stored direction, so the two must use
@@ -141,8 +169,8 @@ struct RecordSink {
     // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
     double cre = 1.0, cim = 0.0;
     if (sizeof(E) > sizeof(G)) {
-      const double dpx = (double)e.dir.x - (double)r.dir[0], dpy = (double)e.dir.y - (double)r.dir[1],
-                   dpz = (double)e.dir.z - (double)r.dir[2];
+      const double dpx = (double)e.dir.x - (double)dv.x, dpy = (double)e.dir.y - (double)dv.y,
+                   dpz = (double)e.dir.z - (double)dv.z;
       const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz);
       sincos(dphi, &cim, &cre);
     }
@@ -153,6 +181,7 @@ struct RecordSink {
         r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)(fr * cim + fi * cre) : (G)0;
       }
     rec.rr[at] = r;
+    rec.dir[at] = dv;
     const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
     float phi = atan2f(dy, dx);
     if (phi < 0.0f) phi += 6.28318531f;
@@ -167,15 +196,6 @@ __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, 
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
 __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
-
-// (a x b) . n evaluated as a fixed sequence of correctly rounded operations.
-template <typename T>
-__device__ __forceinline__ T edge_fn(const v3<T>& a, const v3<T>& b, const v3<T>& n) {
-  T cx_ = sub_rn(mul_rn(a.y, b.z), mul_rn(a.z, b.y));
-  T cy_ = sub_rn(mul_rn(a.z, b.x), mul_rn(a.x, b.z));
-  T cz_ = sub_rn(mul_rn(a.x, b.y), mul_rn(a.y, b.x));
-  return add_rn(add_rn(mul_rn(cx_, n.x), mul_rn(cy_, n.y)), mul_rn(cz_, n.z));
-}
 
 __host__ __device__ __forceinline__ int lower_idx(const double* v, int n, double x) {
   int lo = 0, hi = n;
@@ -254,8 +274,8 @@ __device__ inline int phi_ranges(const NodeGrid& ng, double lo, double hi, int* 
 
 template <typename G>
 __device__ __forceinline__ v3<G> load_dir(const Records<G>& rec, long at) {
-  const G* p = rec.rr[at].dir;
-  return mk3<G>(p[0], p[1], p[2]);
+  const Dir4<G> d = rec.dir[at];
+  return mk3<G>(d.x, d.y, d.z);
 }
 
 // One triangle of one order of one particle, as the rasteriser needs it.
@@ -265,6 +285,7 @@ struct Tri {
   v3<G> dv[3];  // stored exit directions
   int sig[3];   // +1 if edge e (cyclic, opposite vertex e) runs from the lower ray id
   int orient;   // sign of the triple product of the directions
+  v3<G> m[3];   // canonical edge normals d_lo x d_hi of the edges opposite each vertex
   long rb;      // record index of (particle, order slot, ray 0)
   int part;     // particle within the chunk (selects its node lists)
   int N;        // rays per side of the particle
@@ -532,26 +553,35 @@ __device__ inline bool row_window(const Tri<G>& T, const Box& bx, double theta_r
   return true;
 }
 
-// Membership of node direction n (watertight canonical-edge rule) and its
-// barycentric weights; dl receives d_v - n.
+// Canonical edge normals: for the edge opposite vertex k, m_k = d_lo x d_hi
+// with lo/hi its endpoint of lower/higher ray id, formed in FP64 from the
+// stored directions and rounded to G.  The neighbouring triangle across the
+// edge forms the same vector bit for bit, so both evaluate the same edge
+// function m_k . n at every node: membership is watertight.
 template <typename G>
-__device__ __forceinline__ G canon_edge(const v3<G>& a, const v3<G>& b, int sig, const v3<G>& n) {
-  // canonical edge function (lower ray index first), shared bit-for-bit with
-  // the neighbouring triangle across this edge; returned in cyclic order
-  const v3<G> lo = sig > 0 ? a : b, hi = sig > 0 ? b : a;
-  const G ev = edge_fn(lo, hi, n);
-  return ev;
-}
-template <typename G>
-__device__ __forceinline__ bool tri_member(const Tri<G>& T, const v3<double>& n, G lam[3], v3<G> dl[3]) {
+__device__ __forceinline__ void edge_normals(Tri<G>& T) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-    dl[k] = mk3<G>((G)((double)T.dv[k].x - n.x), (G)((double)T.dv[k].y - n.y), (G)((double)T.dv[k].z - n.z));
-  const v3<G> nG = cvt<G>(n);
+  for (int k = 0; k < 3; ++k) {
+    const v3<G>& a = T.dv[(k + 1) % 3];
+    const v3<G>& b = T.dv[(k + 2) % 3];
+    const v3<double> lo = cvt<double>(T.sig[k] > 0 ? a : b), hi = cvt<double>(T.sig[k] > 0 ? b : a);
+    T.m[k] = cvt<G>(cross(lo, hi));
+  }
+}
+
+// m . n as a fixed sequence of correctly rounded operations.
+template <typename T>
+__device__ __forceinline__ T dot_rn(const v3<T>& m, const v3<T>& n) {
+  return add_rn(add_rn(mul_rn(m.x, n.x), mul_rn(m.y, n.y)), mul_rn(m.z, n.z));
+}
+
+// Membership of node direction n (watertight canonical-edge rule) and its
+// barycentric weights: the central-projection weights are proportional to
+// the triple products (d_a x d_b) . n of the cyclic edges.
+template <typename G>
+__device__ __forceinline__ bool tri_member(const Tri<G>& T, const v3<G>& n, G lam[3]) {
   const int o = T.orient;
-  const G e0 = canon_edge(dl[1], dl[2], T.sig[0], nG);
-  const G e1 = canon_edge(dl[2], dl[0], T.sig[1], nG);
-  const G e2 = canon_edge(dl[0], dl[1], T.sig[2], nG);
+  const G e0 = dot_rn(T.m[0], n), e1 = dot_rn(T.m[1], n), e2 = dot_rn(T.m[2], n);
   const G w0 = T.sig[0] > 0 ? e0 : -e0, w1 = T.sig[1] > 0 ? e1 : -e1, w2 = T.sig[2] > 0 ? e2 : -e2;
   const bool ok0 = (o > 0 ? w0 > 0 : w0 < 0) || (e0 == 0 && T.sig[0] * o > 0);
   const bool ok1 = (o > 0 ? w1 > 0 : w1 < 0) || (e1 == 0 && T.sig[1] * o > 0);
@@ -562,16 +592,34 @@ __device__ __forceinline__ bool tri_member(const Tri<G>& T, const v3<double>& n,
   return true;
 }
 
-// Unit direction of node (it, ip).
+// Unit direction of node (it, ip), FP64, and in the rasteriser's precision
+// (the FP32 tables give the mixed path's membership tests).
 __device__ __forceinline__ v3<double> node_dir(const NodeGrid& ng, int it, int ip) {
   return mk3<double>(ng.sth[it] * ng.cph[ip], ng.sth[it] * ng.sph[ip], ng.cth[it]);
 }
-
-// Contribution of triangle T at node (it, ip), stored at pool slot idx and
-// pushed on the node's list.
 template <typename G>
-__device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, const Tri<G>& T,
-                                     int it, int ip, const G lam[3], const v3<G> dl[3], long idx) {
+__device__ __forceinline__ v3<G> node_dir_g(const NodeGrid& ng, int it, int ip);
+template <>
+__device__ __forceinline__ v3<double> node_dir_g<double>(const NodeGrid& ng, int it, int ip) {
+  return node_dir(ng, it, ip);
+}
+template <>
+__device__ __forceinline__ v3<float> node_dir_g<float>(const NodeGrid& ng, int it, int ip) {
+  const float st = ng.sthf[it];
+  return mk3<float>(st * ng.cphf[ip], st * ng.sphf[ip], ng.cthf[it]);
+}
+
+// Contribution of the hit in pool slot idx (its descriptor), stored in the
+// same slot and pushed on the node's list.  The list exchange is issued first
+// so that its latency overlaps the record gathers.
+template <typename G>
+__device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, long idx) {
+  const HitDesc<G> d = pool.desc[idx];
+  const int prev = atomicExch(&pool.head[d.node], (int)idx);
+  const int it = d.itip & 0xffff, ip = (int)((unsigned)d.itip >> 16);
+  const int N = d.nt >> 1, t = d.nt & 1;
+  const long v00 = d.v00;
+  const long vid[3] = {v00, t == 0 ? v00 + 1 : v00 + N + 1, t == 0 ? v00 + N + 1 : v00 + N};
   const G st = (G)ng.sth[it], ct = (G)ng.cth[it], sp = (G)ng.sph[ip], cp = (G)ng.cph[ip];
   const v3<G> eth = mk3<G>(ct * cp, ct * sp, -st);
   const v3<G> eph = mk3<G>(-sp, cp, (G)0);
@@ -580,15 +628,16 @@ __device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, 
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
   const v3<double> n = node_dir(ng, it, ip);
   for (int k = 0; k < 3; ++k) {
-    const RayRec<G>& vr = rec.rr[T.rb + T.vid[k]];
+    const RayRec<G>& vr = rec.rr[d.rb + vid[k]];
+    const Dir4<G> dk = rec.dir[d.rb + vid[k]];
     // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
-    const double psi = (double)vr.kr[0] * ((double)T.dv[k].x - n.x) + (double)vr.kr[1] * ((double)T.dv[k].y - n.y) +
-                       (double)vr.kr[2] * ((double)T.dv[k].z - n.z);
+    const double psi = (double)vr.kr[0] * ((double)dk.x - n.x) + (double)vr.kr[1] * ((double)dk.y - n.y) +
+                       (double)vr.kr[2] * ((double)dk.z - n.z);
     G s_, c_;
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
     else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
-    const G lr = lam[k] * c_, li = lam[k] * s_;
+    const G lr = d.lam[k] * c_, li = d.lam[k] * s_;
     const G* fp = vr.f;
     for (int p = 0; p < rec.n_pol; ++p) {
       G fxr = fp[p * 6 + 0], fxi = fp[p * 6 + 1];
@@ -605,9 +654,19 @@ __device__ inline void tri_store_hit(const Records<G>& rec, const NodeGrid& ng, 
     out[p * 4 + 0] = acc[p][0][0]; out[p * 4 + 1] = acc[p][0][1];
     out[p * 4 + 2] = acc[p][1][0]; out[p * 4 + 3] = acc[p][1][1];
   }
-  const long node = ((long)T.part * ng.n_theta + it) * ng.n_phi + ip;
-  int prev = atomicExch(&pool.head[node], (int)idx);
-  pool.link[idx] = make_int2(T.key, prev);
+  pool.link[idx] = make_int2(d.key, prev);
+}
+
+// One thread per pool slot: contributions and node lists of every hit the
+// rasterisers found (slots past a partition's fill are idle).
+template <typename G>
+__global__ void __launch_bounds__(256) k_store_hits(const Records<G> rec, const NodeGrid ng, const HitPool<G> pool) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long part = i / pool.cap_part;
+  if (part >= NPART) return;
+  const unsigned pos = (unsigned)(i - part * pool.cap_part);
+  if (pos >= min(pool.counter[part], (unsigned)pool.cap_part)) return;
+  store_hit(rec, ng, pool, i);
 }
 
 // Wave-aggregated append: every lane with hit == true receives a pool slot
@@ -636,7 +695,7 @@ __device__ inline int wave_partition() {
 // 2^16 (checked on the host), so index pairs share a word.
 template <typename G>
 struct TriSlot {
-  G dv[9];   // stored exit directions of the three vertices
+  G m[9];    // canonical edge normals (edge_normals)
   int v00;   // ray id of the quad's (ix, iy) corner
   int meta;  // bit 0: t (which half of the quad), bit 1: orient > 0, bits 2..16: N
   int key;   // per-node summation order
@@ -647,10 +706,11 @@ struct TriSlot {
 };
 
 template <typename G>
-__device__ __forceinline__ void slot_put(TriSlot<G>& S, const Tri<G>& T, const Cand& cd) {
+__device__ __forceinline__ void slot_put(TriSlot<G>& S, Tri<G>& T, const Cand& cd) {
+  edge_normals(T);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    S.dv[3 * k] = T.dv[k].x; S.dv[3 * k + 1] = T.dv[k].y; S.dv[3 * k + 2] = T.dv[k].z;
+    S.m[3 * k] = T.m[k].x; S.m[3 * k + 1] = T.m[k].y; S.m[3 * k + 2] = T.m[k].z;
   }
   S.v00 = (int)T.vid[0];
   S.meta = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.orient > 0 ? 2 : 0) | (T.N << 2);
@@ -664,7 +724,7 @@ __device__ __forceinline__ void slot_put(TriSlot<G>& S, const Tri<G>& T, const C
 template <typename G>
 __device__ __forceinline__ void slot_get(const TriSlot<G>& S, Tri<G>& T) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) T.dv[k] = mk3<G>(S.dv[3 * k], S.dv[3 * k + 1], S.dv[3 * k + 2]);
+  for (int k = 0; k < 3; ++k) T.m[k] = mk3<G>(S.m[3 * k], S.m[3 * k + 1], S.m[3 * k + 2]);
   const int t = S.meta & 1;
   const int N = (S.meta >> 2) & 0x7fff;
   const long v00 = S.v00;
@@ -702,15 +762,18 @@ __device__ __forceinline__ void locate(const WaveStage<G>& W, int g, Tri<G>& T, 
   if (c >= n0) c -= n0;
   const int i0 = S.pk0 & 0xffff, len = (int)((unsigned)S.pk0 >> 16);
   const int ja0 = S.pk1 & 0xffff, la = (int)((unsigned)S.pk1 >> 16), jb0 = S.pk2 & 0xffff;
-  const int row = c / len;
+  int row = (int)((float)c * __frcp_rn((float)len));  // c / len, then corrected
+  if (row * len > c) --row;
+  else if ((row + 1) * len <= c) ++row;
   const int jj = c - row * len;
   it = i0 + row;
   ip = jj < la ? ja0 + jj : jb0 + (jj - la);
   slot_get(S, T);
 }
 
-// Take pool slots for the nh buffered hits with one atomic, then store each
-// hit's contribution (its membership weights are recomputed, bit for bit).
+// Take pool slots for the nh buffered hits with one atomic, then write each
+// hit's descriptor (its membership weights are recomputed, bit for bit);
+// k_store_hits computes the contributions.
 template <typename G>
 __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
                            const WaveStage<G>& W, int nh, int part) {
@@ -725,11 +788,19 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
       int it, ip;
       locate(W, W.hits[h], T, it, ip);
       G lam[3];
-      v3<G> dl[3];
-      tri_member(T, node_dir(ng, it, ip), lam, dl);
+      tri_member(T, node_dir_g<G>(ng, it, ip), lam);
       const unsigned pos = first + (unsigned)h;
-      if (pos < (unsigned)pool.cap_part)  // beyond: overflow, reported by the status call
-        tri_store_hit(rec, ng, pool, T, it, ip, lam, dl, (long)part * pool.cap_part + pos);
+      if (pos < (unsigned)pool.cap_part) {  // beyond: overflow, reported by the status call
+        HitDesc<G> d;
+        d.key = T.key;
+        d.rb = (int)T.rb;
+        d.v00 = (int)T.vid[0];
+        d.nt = (T.N << 1) | (T.vid[1] == T.vid[0] + 1 ? 0 : 1);
+        d.itip = it | (ip << 16);
+        d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
+        d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
+        pool.desc[(long)part * pool.cap_part + pos] = d;
+      }
     }
   }
 }
@@ -755,8 +826,7 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
       int it, ip;
       locate(W, g, T, it, ip);
       G lam[3];
-      v3<G> dl[3];
-      hit = tri_member(T, node_dir(ng, it, ip), lam, dl);
+      hit = tri_member(T, node_dir_g<G>(ng, it, ip), lam);
     }
     const unsigned long long mask = __ballot(hit);
     if (hit) W.hits[nh + __popcll(mask & below)] = g;
