@@ -144,10 +144,11 @@ enum : int {
   C_NEED,          // fullest hit-pool partition over the chunks of the call
   C_FP64_TOTAL,    // rays re-traced in FP64 over the call
   C_PAD,
-  C_HITS,          // node hits over the call (64-bit, two slots)
+  C_HITS,          // node hits over the call (64-bit, two slots: must be 8-byte aligned)
   C_HITS_HI,
   C_COUNT
 };
+static_assert(C_HITS % 2 == 0, "the 64-bit hit total needs an 8-byte aligned slot");
 
 // Particle constants of a wave-uniform particle index, kept in scalar
 // registers (each 32-bit word is made uniform explicitly: the compiler cannot
