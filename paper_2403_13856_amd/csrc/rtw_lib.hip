@@ -333,9 +333,9 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
 }
 
 // Reset of the per-chunk state: node lists and per-chunk counters.
-__global__ void k_chunk_reset(int* head, long n_heads, unsigned* counter) {
+__global__ void k_chunk_reset(int* count, long n_heads, unsigned* counter) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_heads) head[i] = -1;
+  if (i < n_heads) count[i] = 0;
   if (i <= C_QUEUE) counter[i] = 0u;
 }
 
@@ -439,8 +439,8 @@ int check_keys(const rtw_trace_opts* o) {
 // Workspace layout (256-byte aligned sections).  Record arrays are sized for
 // the largest chunk; metadata for every particle of the call.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, head, redo, rows,
-      link, contrib, desc, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, head, cursor,
+      bsum, redo, rows, link, contrib, desc, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -476,12 +476,14 @@ Layout layout(const Shape& S, long cap_total) {
   L.dir = take((S.precision == RTW_FP64 ? sizeof(Dir4<double>) : sizeof(Dir4<float>)) * nrec);
   L.ang = take(sizeof(float2) * nrec);
   L.head = take(4 * (size_t)S.max_chunk_parts * n_nodes);
+  L.cursor = take(4 * (size_t)S.max_chunk_parts * n_nodes);
+  L.bsum = take(4 * ((size_t)S.max_chunk_parts * n_nodes / SCAN_BLOCK + 1));
   L.redo = take(S.precision == RTW_FP64 ? 4 : 4 * (size_t)S.max_chunk_rays);
   L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
   L.fixed = off;
   const size_t ds = S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>);
-  L.bytes_per_hit = sizeof(int2) + gs * 4 * S.n_pol + ds;
-  L.link = take(sizeof(int2) * (size_t)cap_total);
+  L.bytes_per_hit = sizeof(int) + gs * 4 * S.n_pol + ds;
+  L.link = take(sizeof(int) * (size_t)cap_total);
   L.contrib = take(gs * 4 * S.n_pol * (size_t)cap_total);
   L.desc = take(ds * (size_t)cap_total);
   L.total = off;
@@ -653,8 +655,9 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   rec.n_fp64 = counter + C_REDO;
   rec.redo_list = (int*)(ws + L.redo);
   HitPool<G> pool;
-  pool.head = (int*)(ws + L.head);
-  pool.link = (int2*)(ws + L.link);
+  pool.count = (int*)(ws + L.head);
+  pool.cursor = (int*)(ws + L.cursor);
+  pool.key = (int*)(ws + L.link);
   pool.contrib = (G*)(ws + L.contrib);
   pool.desc = (HitDesc<G>*)(ws + L.desc);
   pool.counter = counter;
@@ -702,7 +705,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     const long items = pl.tile_off[c1] - pl.tile_off[c0];
     const long n_heads = (long)nc * n_nodes;
     hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_heads, C_COUNT) + 255) / 256)), dim3(256),
-                       0, st, pool.head, n_heads, counter);
+                       0, st, pool.count, n_heads, counter);
     { ProfScope ps(fp64 ? "k_trace_fp64" : "k_trace_mixed", st);
     const long grid_t = std::min<long>(items, (long)cu * tu.blocks_per_cu);
     hipLaunchKernelGGL(k_trace_tiles<G>, dim3((unsigned)grid_t), dim3(256), 0, st, B, rec, counter + C_QUEUE); }
@@ -716,6 +719,12 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
                        pool, BOX_MARGIN, tu.cand_inline); }
     { ProfScope ps(fp64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
     hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
+    { ProfScope ps("k_scan", st);
+    const long nsb = (n_heads + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    int* bsum = (int*)(ws + L.bsum);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_heads, pool.cursor, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_heads, bsum); }
     { ProfScope ps(fp64 ? "k_store_hits_fp64" : "k_store_hits_mixed", st);
     const long slots = (long)NPART * cap_part;
     hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, rec, ng, pool); }

@@ -125,9 +125,10 @@ struct HitDesc {
 
 template <typename G>
 struct HitPool {
-  int* head;          // [n_nodes] first hit of each node, -1 = none
-  int2* link;         // [cap] (key, next)
-  G* contrib;         // [cap][n_pol * 4]: (pol, theta|phi, re|im)
+  int* count;         // [n_nodes] hits of each node (counted by the rasterisers)
+  int* cursor;        // [n_nodes] exclusive prefix of count, advanced by k_store_hits to the node's end
+  int* key;           // [cap] triangle key of each stored contribution (node-major order)
+  G* contrib;         // [cap][n_pol * 4]: (pol, theta|phi, re|im), node-major order
   HitDesc<G>* desc;   // [cap] hits found, stored by k_store_hits
   unsigned* counter;  // [NPART]
   int cap_part;       // capacity of each partition
@@ -609,13 +610,13 @@ __device__ __forceinline__ v3<float> node_dir_g<float>(const NodeGrid& ng, int i
   return mk3<float>(st * ng.cphf[ip], st * ng.sphf[ip], ng.cthf[it]);
 }
 
-// Contribution of the hit in pool slot idx (its descriptor), stored in the
-// same slot and pushed on the node's list.  The list exchange is issued first
-// so that its latency overlaps the record gathers.
+// Contribution of the hit in pool slot idx (its descriptor), stored at the
+// next free place of its node's range (node-major order).  The place is taken
+// first so that the atomic's latency overlaps the record gathers.
 template <typename G>
 __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, long idx) {
   const HitDesc<G> d = pool.desc[idx];
-  const int prev = atomicExch(&pool.head[d.node], (int)idx);
+  const long at = atomicAdd(&pool.cursor[d.node], 1);
   const int it = d.itip & 0xffff, ip = (int)((unsigned)d.itip >> 16);
   const int N = d.nt >> 1, t = d.nt & 1;
   const long v00 = d.v00;
@@ -649,16 +650,16 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
       acc[p][1][0] += lr * pr - li * pi_; acc[p][1][1] += lr * pi_ + li * pr;
     }
   }
-  G* out = pool.contrib + idx * (rec.n_pol * 4);
+  G* out = pool.contrib + at * (rec.n_pol * 4);
   for (int p = 0; p < rec.n_pol; ++p) {
     out[p * 4 + 0] = acc[p][0][0]; out[p * 4 + 1] = acc[p][0][1];
     out[p * 4 + 2] = acc[p][1][0]; out[p * 4 + 3] = acc[p][1][1];
   }
-  pool.link[idx] = make_int2(d.key, prev);
+  pool.key[at] = d.key;
 }
 
-// One thread per pool slot: contributions and node lists of every hit the
-// rasterisers found (slots past a partition's fill are idle).
+// One thread per pool slot: contributions of every hit the rasterisers found,
+// placed node by node (slots past a partition's fill are idle).
 template <typename G>
 __global__ void __launch_bounds__(256) k_store_hits(const Records<G> rec, const NodeGrid ng, const HitPool<G> pool) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -800,6 +801,7 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
         d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
         d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
         pool.desc[(long)part * pool.cap_part + pos] = d;
+        atomicAdd(&pool.count[d.node], 1);
       }
     }
   }
@@ -1017,11 +1019,73 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
   }
 }
 
-// One thread per node of the chunk (particle-major): walk the node's hit list,
-// order the hits by triangle key, sum them in that order and write (F_theta,
-// F_phi) for every polarisation into the particle's output block; optionally
-// also the incoherent intensity sum_b (|f_b,theta|^2 + |f_b,phi|^2) of the
-// node's contributions per polarisation.
+// Exclusive prefix of the node counts (three phases: per-block scans of
+// SCAN_BLOCK counts, a scan of the block sums, their addition).
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_BLOCK = 256 * SCAN_PER_THREAD;
+
+__device__ __forceinline__ int block_excl_scan(int v, int* total, int* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int wt;
+  const int ex = wave_excl_scan(v, &wt);
+  if (lane == 0) lds[wave] = wt;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) before += lds[w];
+    all += lds[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + ex;
+}
+
+__global__ void __launch_bounds__(256) k_scan_local(const int* count, long n, int* out, int* bsum) {
+  __shared__ int lds[4];
+  const long base = (long)blockIdx.x * SCAN_BLOCK + (long)threadIdx.x * SCAN_PER_THREAD;
+  int v[SCAN_PER_THREAD], s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER_THREAD; ++j) {
+    v[j] = base + j < n ? count[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int run = block_excl_scan(s, &total, lds);
+#pragma unroll
+  for (int j = 0; j < SCAN_PER_THREAD; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the nb block sums in place.
+__global__ void __launch_bounds__(1024) k_scan_sums(int* bsum, int nb) {
+  __shared__ int lds[16];
+  const int per = (nb + blockDim.x - 1) / blockDim.x;
+  const int b0 = threadIdx.x * per;
+  int s = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) s += bsum[b0 + j];
+  int total;
+  int run = block_excl_scan(s, &total, lds);
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) { const int x = bsum[b0 + j]; bsum[b0 + j] = run; run += x; }
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(int* out, long n, const int* bsum) {
+  const long base = (long)blockIdx.x * SCAN_BLOCK;
+  const int add = bsum[blockIdx.x];
+  for (int j = threadIdx.x; j < SCAN_BLOCK; j += blockDim.x)
+    if (base + j < n) out[base + j] += add;
+}
+
+// One thread per node of the chunk (particle-major): order the node's
+// contributions (a contiguous range after k_store_hits) by triangle key, sum
+// them in that order and write (F_theta, F_phi) for every polarisation into
+// the particle's output block; optionally also the incoherent intensity
+// sum_b (|f_b,theta|^2 + |f_b,phi|^2) of the node's contributions per
+// polarisation.
 template <typename G>
 __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPool<G> pool, int n_nodes, int n_pol,
                                                   G* out, int32_t* ncontrib, G* incoh) {
@@ -1030,45 +1094,39 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
   const int pl = (int)(gn / n_nodes);
   const int node = (int)(gn - (long)pl * n_nodes);
   const long ob = (long)B.out_index[pl];
+  const int cnt = pool.count[gn];
+  const long s0 = (long)pool.cursor[gn] - cnt;
   int keys[NODE_SORT_MAX], idxs[NODE_SORT_MAX];
-  int cnt = 0;
-  for (int h = pool.head[gn]; h >= 0; h = pool.link[h].y) {
-    int2 l = pool.link[h];
-    if (cnt < NODE_SORT_MAX) {
-      // insertion into the sorted prefix
-      int j = cnt;
-      while (j > 0 && keys[j - 1] > l.x) { keys[j] = keys[j - 1]; idxs[j] = idxs[j - 1]; --j; }
-      keys[j] = l.x; idxs[j] = h;
-    }
-    ++cnt;
-  }
+  const int w = n_pol * 4;
   G acc[8], inc[2] = {0, 0};
   for (int i = 0; i < 8; ++i) acc[i] = 0;
-  const int w = n_pol * 4;
+  auto add = [&](long at) {
+    const G* c = pool.contrib + at * w;
+    for (int k = 0; k < w; ++k) acc[k] += c[k];
+    for (int p = 0; p < n_pol; ++p)
+      inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
+                c[4 * p + 3] * c[4 * p + 3];
+  };
   if (cnt <= NODE_SORT_MAX) {
-    for (int i = 0; i < cnt; ++i) {
-      const G* c = pool.contrib + (long)idxs[i] * w;
-      for (int k = 0; k < w; ++k) acc[k] += c[k];
-      for (int p = 0; p < n_pol; ++p)
-        inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
-                  c[4 * p + 3] * c[4 * p + 3];
+    for (int h = 0; h < cnt; ++h) {  // insertion into the sorted prefix
+      const int kk = pool.key[s0 + h];
+      int j = h;
+      while (j > 0 && keys[j - 1] > kk) { keys[j] = keys[j - 1]; idxs[j] = idxs[j - 1]; --j; }
+      keys[j] = kk; idxs[j] = h;
     }
+    for (int i = 0; i < cnt; ++i) add(s0 + idxs[i]);
   } else {
     // more hits than the register window: repeated minimum search, same order
     long last = -1;
     for (int r = 0; r < cnt; ++r) {
       long best = 0x7fffffffffffL;
-      int bi = -1;
-      for (int h = pool.head[gn]; h >= 0; h = pool.link[h].y) {
-        long kk = pool.link[h].x;
+      int bi = 0;
+      for (int h = 0; h < cnt; ++h) {
+        const long kk = pool.key[s0 + h];
         if (kk > last && kk < best) { best = kk; bi = h; }
       }
       last = best;
-      const G* c = pool.contrib + (long)bi * w;
-      for (int k = 0; k < w; ++k) acc[k] += c[k];
-      for (int p = 0; p < n_pol; ++p)
-        inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
-                  c[4 * p + 3] * c[4 * p + 3];
+      add(s0 + bi);
     }
   }
   G* po = out + ob * ((long)n_pol * 2 * n_nodes * 2);
