@@ -24,14 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic floating-point work of the rasteriser (adds, multiplies,
-# divides and square roots counted once each, an FMA as two, an elementary
-# function as one), per unit of the method:
-#   per valid triangle: orientation triple product (20) and angular bounds (40)
-#   per node hit: membership and barycentric weights (58) + carrying and
-#   projecting the three vertex fields for two polarisations (180)
+# Algorithmic floating-point work (adds, multiplies, divides and square roots
+# counted once each, an FMA as two, an elementary function as one), per unit
+# of the method:
+#   rasteriser: per valid triangle, orientation triple product (20) and
+#   angular bounds (40); per node hit, membership and barycentric weights (58)
+#   hit store: per node hit, carrying and projecting the three vertex fields
+#   for two polarisations (180)
+#   node sum: per hit, 8 accumulations
 FLOP_RASTER_PER_TRIANGLE = 60
-FLOP_RASTER_PER_HIT = 238
+FLOP_RASTER_PER_HIT = 58
+FLOP_STORE_PER_HIT = 180
 # per active ray, p = 0..3: four interactions (both branches), three
 # propagations, four emissions
 FLOP_TRACE_PER_RAY = 4 * 300 + 3 * 60 + 4 * 200
@@ -444,6 +447,8 @@ def main():
         flops = FLOP_RASTER_PER_HIT * hits  # share of hits unknown per kernel: upper bound
     elif dom.startswith("k_raster"):
         flops = FLOP_RASTER_PER_TRIANGLE * n_tri + FLOP_RASTER_PER_HIT * hits
+    elif dom.startswith("k_store_hits"):
+        flops = FLOP_STORE_PER_HIT * hits
     else:
         flops = 8 * hits
     achieved = flops / avg_s / 1e12
