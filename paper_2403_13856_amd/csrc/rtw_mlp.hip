@@ -90,10 +90,58 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678f)) + z * 0.39894228f * __expf(-0.5f * z * z);
 }
 
+// Global -> register staging of one K step of the A and B tiles (16 BF16 of
+// each per thread), and register -> LDS placement in the [row][k] layout.
+struct Stage {
+  bf16x8 a0, a1, b0, b1;
+};
+
+__device__ __forceinline__ void stage_load(const GemmArgs& g, long m0, long n0, int k0, int t, Stage& r) {
+  if (!g.transA) {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (m0 + (t >> 1)) * g.lda + k0 + (t & 1) * 16);
+    r.a0 = src[0]; r.a1 = src[1];
+  } else {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (long)(k0 + (t >> 3)) * g.lda + m0 + (t & 7) * 16);
+    r.a0 = src[0]; r.a1 = src[1];
+  }
+  if (g.transB) {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (n0 + (t >> 1)) * g.ldb + k0 + (t & 1) * 16);
+    r.b0 = src[0]; r.b1 = src[1];
+  } else {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (long)(k0 + (t >> 3)) * g.ldb + n0 + (t & 7) * 16);
+    r.b0 = src[0]; r.b1 = src[1];
+  }
+}
+
+__device__ __forceinline__ void stage_store(const GemmArgs& g, int t, const Stage& r, bf16 (*As)[LDK],
+                                            bf16 (*Bs)[LDK]) {
+  if (!g.transA) {
+    const int row = t >> 1, kh = (t & 1) * 16;
+    *reinterpret_cast<bf16x8*>(&As[row][kh]) = r.a0;
+    *reinterpret_cast<bf16x8*>(&As[row][kh + 8]) = r.a1;
+  } else {
+    const int kk = t >> 3, mc = (t & 7) * 16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) { As[mc + j][kk] = r.a0[j]; As[mc + 8 + j][kk] = r.a1[j]; }
+  }
+  if (g.transB) {
+    const int row = t >> 1, kh = (t & 1) * 16;
+    *reinterpret_cast<bf16x8*>(&Bs[row][kh]) = r.b0;
+    *reinterpret_cast<bf16x8*>(&Bs[row][kh + 8]) = r.b1;
+  } else {
+    const int kk = t >> 3, nc = (t & 7) * 16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) { Bs[nc + j][kk] = r.b0[j]; Bs[nc + 8 + j][kk] = r.b1[j]; }
+  }
+}
+
+// Software-pipelined main loop: the next K step's tiles are loaded into
+// registers while the matrix cores work on the current one from LDS, then
+// placed into the other LDS buffer; one barrier per K step.
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
-  __shared__ bf16 As[BM][LDK];
-  __shared__ bf16 Bs[BN][LDK];
+  __shared__ bf16 As[2][BM][LDK];
+  __shared__ bf16 Bs[2][BN][LDK];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const long m0 = (long)blockIdx.y * BM, n0 = (long)blockIdx.x * BN;
@@ -104,55 +152,38 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   float csum = 0.f;  // column sum of B over this block's K slice (weight-gradient products)
+  const bool do_csum = EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0;
   const int k_begin = blockIdx.z * g.K_slice, k_end = min(g.K, k_begin + g.K_slice);
+  Stage r;
+  stage_load(g, m0, n0, k_begin, t, r);
+  stage_store(g, t, r, As[0], Bs[0]);
+  __syncthreads();
+  int cur = 0;
   for (int k0 = k_begin; k0 < k_end; k0 += BK) {
-    // A tile -> As[m][k]
-    if (!g.transA) {
-      const int r = t >> 1, kh = (t & 1) * 16;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (m0 + r) * g.lda + k0 + kh);
-      *reinterpret_cast<bf16x8*>(&As[r][kh]) = src[0];
-      *reinterpret_cast<bf16x8*>(&As[r][kh + 8]) = src[1];
-    } else {
-      const int kk = t >> 3, mc = (t & 7) * 16;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (long)(k0 + kk) * g.lda + m0 + mc);
-      const bf16x8 v0 = src[0], v1 = src[1];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) { As[mc + j][kk] = v0[j]; As[mc + 8 + j][kk] = v1[j]; }
-    }
-    // B tile -> Bs[n][k]
-    if (g.transB) {
-      const int r = t >> 1, kh = (t & 1) * 16;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (n0 + r) * g.ldb + k0 + kh);
-      *reinterpret_cast<bf16x8*>(&Bs[r][kh]) = src[0];
-      *reinterpret_cast<bf16x8*>(&Bs[r][kh + 8]) = src[1];
-    } else {
-      const int kk = t >> 3, nc = (t & 7) * 16;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (long)(k0 + kk) * g.ldb + n0 + nc);
-      const bf16x8 v0 = src[0], v1 = src[1];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) { Bs[nc + j][kk] = v0[j]; Bs[nc + 8 + j][kk] = v1[j]; }
-    }
-    __syncthreads();
-    if (EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0) {
+    const bool more = k0 + BK < k_end;
+    if (more) stage_load(g, m0, n0, k0 + BK, t, r);
+    if (do_csum) {
       // column sums of this K step of B, in a fixed order (two halves of k per column)
       const int n = t & 127, kh = (t >> 7) * 16;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) csum += (float)Bs[n][kh + j];
+      for (int j = 0; j < 16; ++j) csum += (float)Bs[cur][n][kh + j];
     }
     bf16x8 af[4], bfr[4];
     const int kq = 8 * (lane >> 4), rr = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + i * 16 + rr][kq]);
+    for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm * 64 + i * 16 + rr][kq]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + j * 16 + rr][kq]);
+    for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn * 64 + j * 16 + rr][kq]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (more) stage_store(g, t, r, As[cur ^ 1], Bs[cur ^ 1]);
     __syncthreads();
+    cur ^= 1;
   }
-  if (EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0) {
-    float* red = reinterpret_cast<float*>(&As[0][0]);  // the A tile is free now
+  if (do_csum) {
+    float* red = reinterpret_cast<float*>(&As[cur][0][0]);  // no longer read
     red[t] = csum;
     __syncthreads();
     if (t < 128) g.colsum[(long)blockIdx.z * g.N + n0 + t] = red[t] + red[t + 128];
@@ -163,11 +194,11 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+      for (int rr2 = 0; rr2 < 4; ++rr2) {
+        const long row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + rr2;
         const long col = n0 + wn * 64 + j * 16 + (lane & 15);
         const long o = row * g.ldo + col;
-        const float v = acc[i][j][r];
+        const float v = acc[i][j][rr2];
         if (EPI == EPI_FWD_GELU) {
           const float z = v + g.bias[col];
           g.Zout[o] = (bf16)z;
