@@ -740,27 +740,37 @@ __device__ __forceinline__ void slot_get(const TriSlot<G>& S, Tri<G>& T) {
   for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
 }
 
-// Per-wave LDS area of the flattened loop: up to two staged triangles per lane.
+// A triangle of the wave that needs its directions loaded: its quad, particle,
+// half (bit 0), whether the vertex-angle box applies (bit 1) and that box.
+struct TriQueued {
+  int quad, part, tf;
+  int i0, i1, ja0, ja1, jb0, jb1;
+};
+
+// Per-wave LDS area of the flattened loop: up to 128 staged triangles (two per
+// lane's quad at most).  The queue of triangles to load shares the slot
+// storage: entry k is read by the lane that then writes slot k.
 constexpr int HITBUF = 128;  // node hits buffered per wave before their pool slots are taken
+constexpr int WAVE_SLOTS = 128;
 template <typename G>
 struct WaveStage {
-  TriSlot<G> tri[128];  // [2 * lane + which]
-  int excl[64];         // exclusive prefix of the lanes' candidate counts
-  int n0[64];           // candidates of each lane's first triangle
-  int hits[HITBUF];     // wave candidate numbers of buffered hits
+  union {
+    TriSlot<G> tri[WAVE_SLOTS];
+    TriQueued queued[WAVE_SLOTS];
+  };
+  int excl[WAVE_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the wave total)
+  int hits[HITBUF];      // wave candidate numbers of buffered hits
 };
 
 // Candidate g of the wave: its triangle and node (row it, column ip).
 template <typename G>
 __device__ __forceinline__ void locate(const WaveStage<G>& W, int g, Tri<G>& T, int& it, int& ip) {
-  int L = 0;  // last lane whose prefix is <= g
+  int L = 0;  // last slot whose prefix is <= g
 #pragma unroll
-  for (int step = 32; step > 0; step >>= 1)
+  for (int step = WAVE_SLOTS / 2; step > 0; step >>= 1)
     if (W.excl[L + step] <= g) L += step;
-  int c = g - W.excl[L];
-  const int n0 = W.n0[L];
-  const TriSlot<G>& S = W.tri[2 * L + (c < n0 ? 0 : 1)];
-  if (c >= n0) c -= n0;
+  const int c = g - W.excl[L];
+  const TriSlot<G>& S = W.tri[L];
   const int i0 = S.pk0 & 0xffff, len = (int)((unsigned)S.pk0 >> 16);
   const int ja0 = S.pk1 & 0xffff, la = (int)((unsigned)S.pk1 >> 16), jb0 = S.pk2 & 0xffff;
   int row = (int)((float)c * __frcp_rn((float)len));  // c / len, then corrected
@@ -811,8 +821,8 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
 // wave goes to lane g mod 64 whatever triangle owns it, so one large triangle
 // costs its size / 64 iterations instead of its size.  Hits are buffered in
 // LDS and stored in batches, so the membership loop never waits on an atomic.
-// The lanes must have written their slots, n0 and prefix before the call, and
-// the block must have passed a barrier since.
+// The lanes must have written their slots and the prefix of all WAVE_SLOTS
+// slots before the call, and the block must have passed a barrier since.
 template <typename G>
 __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
                              WaveStage<G>& W, int wave_total, int part) {
@@ -876,15 +886,18 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
   __syncthreads();
   const long gq = gq0 + threadIdx.x;
 
-  Tri<G> T0, T1;
+  // Phase one, every quad: validity from the flags, then the box of each valid
+  // triangle from its vertex angles where fast_box applies.  Triangles with
+  // candidate nodes, or whose box needs the directions, are queued in LDS.
   Cand c0, c1;
-  int n0 = 0, n1 = 0, r0 = 0, r1 = 0;  // inline candidates, rows to list
+  bool need0 = false, need1 = false, fast0 = false, fast1 = false;
+  int p = s_p0;
+  long quad = 0;
   if (gq < n_quads) {
-    int p = s_p0;  // a block spans few particles: walk forward from the block's first
-    while (B.quad_off[p + 1] - B.quad_base <= gq) ++p;
+    while (B.quad_off[p + 1] - B.quad_base <= gq) ++p;  // a block spans few particles
     const int N = B.P[p].N;
     const long qoff = B.quad_off[p] - B.quad_base;
-    const long quad = gq - qoff;
+    quad = gq - qoff;
     const int Nq = N - 1;
     const long NN = (long)N * N;
     const long rb = B.n_ord * (B.ray_off[p] - B.ray_base) + (long)slot * NN;
@@ -898,60 +911,94 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
     if (tv0 || tv1) {
       const float2* an = rec.ang + rb;
       const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + N], a11 = an[v00 + N + 1];
-      // box of one triangle: from the vertex angles when fast_box applies, else
-      // from the directions; the directions (and orientation) are loaded only
-      // for triangles with candidate nodes
-      auto setup = [&](int t, bool tv, float2 b, float2 c, Tri<G>& T, Cand& cd, int& n, int& r) {
-        if (!tv) return;
-        const int key = tri_key(B.n_ord, qoff, slot, (long)Nq * Nq, quad, t);
-        bool loaded = false;
-        if (!fast_box(ng, a00, b, c, (float)margin, cd)) {
-          tri_load(rec, rb, N, quad, t, key, p, T);
-          loaded = true;
-          if (T.orient == 0) return;
-          cd = box_cand(ng, tri_box(T, (float)margin));
-        }
-        const int cnt = cd.count();
-        if (cnt == 0) return;
-        if (!loaded) {
-          tri_load(rec, rb, N, quad, t, key, p, T);
-          if (T.orient == 0) return;
-        }
-        if (cnt <= cand_inline) n = cnt; else r = cd.i1 - cd.i0;
-      };
-      setup(0, tv0, a01, a11, T0, c0, n0, r0);
-      setup(1, tv1, a11, a10, T1, c1, n1, r1);
+      if (tv0) {
+        fast0 = fast_box(ng, a00, a01, a11, (float)margin, c0);
+        need0 = !fast0 || c0.count() > 0;
+      }
+      if (tv1) {
+        fast1 = fast_box(ng, a00, a11, a10, (float)margin, c1);
+        need1 = !fast1 || c1.count() > 0;
+      }
     }
   }
-  // rows of large triangles: wave-level exclusive scan, one atomic per wave
-  {
-    const int mine = r0 + r1;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const unsigned long long q0 = __ballot(need0), q1 = __ballot(need1);
+  const int nq0 = __popcll(q0), nq = nq0 + __popcll(q1);
+  auto enqueue = [&](int at, int t, bool fast, const Cand& c) {
+    TriQueued& e = W.queued[at];
+    e.quad = (int)quad; e.part = p; e.tf = t | (fast ? 2 : 0);
+    e.i0 = c.i0; e.i1 = c.i1; e.ja0 = c.ja0; e.ja1 = c.ja1; e.jb0 = c.jb0; e.jb1 = c.jb1;
+  };
+  if (need0) enqueue(__popcll(q0 & below), 0, fast0, c0);
+  if (need1) enqueue(nq0 + __popcll(q1 & below), 1, fast1, c1);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // Phase two, 64 queued triangles at a time: directions and orientation, the
+  // direction box where the angle box did not apply; boxes of at most
+  // cand_inline nodes are staged in slot k, larger ones listed by row.  The
+  // queue shares the slots' storage with a different element size, so every
+  // entry is read into registers before the first slot is written.
+  TriQueued mine[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (64 * h + lane < nq) mine[h] = W.queued[64 * h + lane];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  int wave_total = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = 64 * h + lane;
+    if (64 * h >= nq) {  // wave-uniform: no more queued triangles
+      W.excl[k] = wave_total;
+      continue;
+    }
+    Tri<G> T;
+    Cand c;
+    int n = 0, r = 0;
+    if (k < nq) {
+      const TriQueued& e = mine[h];
+      const int t = e.tf & 1, pp = e.part;
+      const int N = B.P[pp].N;
+      const long qoff = B.quad_off[pp] - B.quad_base;
+      const long nq2 = (long)(N - 1) * (N - 1);
+      const long rb = B.n_ord * (B.ray_off[pp] - B.ray_base) + (long)slot * N * N;
+      tri_load(rec, rb, N, (long)e.quad, t, tri_key(B.n_ord, qoff, slot, nq2, (long)e.quad, t), pp, T);
+      if (T.orient != 0) {
+        if (e.tf & 2) {
+          c.i0 = e.i0; c.i1 = e.i1; c.ja0 = e.ja0; c.ja1 = e.ja1; c.jb0 = e.jb0; c.jb1 = e.jb1;
+        } else {
+          c = box_cand(ng, tri_box(T, (float)margin));
+        }
+        const int cnt = c.count();
+        if (cnt > 0) {
+          if (cnt <= cand_inline) n = cnt; else r = c.i1 - c.i0;
+        }
+      }
+    }
+    // rows of large triangles: wave-level exclusive scan, one atomic per wave
     int wave_rows;
-    const int before = wave_excl_scan(mine, &wave_rows);
+    const int before = wave_excl_scan(r, &wave_rows);
     if (wave_rows > 0) {
-      unsigned base = 0;
-      if (lane == 63) base = atomicAdd(pool.n_rows, (unsigned)wave_rows);
-      base = __shfl(base, 63);
-      const unsigned at = base + (unsigned)before;
-      const bool fits = (unsigned long long)base + (unsigned)wave_rows <= (unsigned long long)pool.rows_cap;
-      for (int k = 0; k < mine; ++k) {
-        const unsigned pos = at + k;
-        const int key = k < r0 ? T0.key : T1.key;
-        const int row = k < r0 ? c0.i0 + k : c1.i0 + (k - r0);
-        if (fits) pool.rows[pos] = make_int2(key, row);
+      unsigned rbase = 0;
+      if (lane == 63) rbase = atomicAdd(pool.n_rows, (unsigned)wave_rows);
+      rbase = __shfl(rbase, 63);
+      const unsigned at = rbase + (unsigned)before;
+      const bool fits = (unsigned long long)rbase + (unsigned)wave_rows <= (unsigned long long)pool.rows_cap;
+      for (int j = 0; j < r; ++j) {
+        const unsigned pos = at + j;
+        if (fits) pool.rows[pos] = make_int2(T.key, c.i0 + j);
         else if (pos < (unsigned)pool.rows_cap) pool.rows[pos] = make_int2(-1, 0);  // unused slot
       }
-      if (!fits) {  // list full: rasterise the whole box in this kernel (slow but exact)
-        if (r0 > 0) n0 = c0.count();
-        if (r1 > 0) n1 = c1.count();
-      }
+      if (!fits && r > 0) n = c.count();  // list full: rasterise the whole box here (slow but exact)
     }
+    if (n > 0) slot_put(W.tri[k], T, c);
+    int it_total;
+    W.excl[k] = wave_total + wave_excl_scan(n, &it_total);
+    wave_total += it_total;
   }
-  if (n0 > 0) slot_put(W.tri[2 * lane], T0, c0);
-  if (n1 > 0) slot_put(W.tri[2 * lane + 1], T1, c1);
-  int wave_total;
-  W.excl[lane] = wave_excl_scan(n0 + n1, &wave_total);
-  W.n0[lane] = n0;
   __syncthreads();
   raster_drain(rec, ng, pool, W, wave_total, wave_partition());
 }
@@ -1006,13 +1053,13 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
           cd.jb0 = nr > 1 ? j0[1] : 0;
           cd.jb1 = nr > 1 ? j1[1] : 0;
           n = cd.count();
-          if (n > 0) slot_put(W.tri[2 * lane], T, cd);
+          if (n > 0) slot_put(W.tri[lane], T, cd);
         }
       }
     }
     int wave_total;
     W.excl[lane] = wave_excl_scan(n, &wave_total);
-    W.n0[lane] = n;
+    W.excl[64 + lane] = wave_total;
     __syncthreads();
     raster_drain(rec, ng, pool, W, wave_total, part);
     __syncthreads();  // the stage is rewritten by the next block of items
