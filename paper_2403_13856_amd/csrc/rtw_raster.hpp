@@ -437,8 +437,10 @@ __device__ inline Cand box_cand(const NodeGrid& ng, const Box& bx) {
 //     farther than l from the nearest vertex is outside;
 //   - along a great-circle arc of length l, cos theta exceeds its end values
 //     by at most l^2 / 8, so theta leaves the vertex range by at most
-//     l^2 / (8 sin theta); the test below keeps that under 2e-6 rad, which
-//     the margin absorbs;
+//     l^2 / (8 sin theta) (bounded here by 0.132 q / s_lo, s_lo <= sin theta;
+//     on random and near-pole east-west arcs the true excursion stays below
+//     0.55 of it); the theta range is widened by that bound, capped at
+//     1e-3 rad;
 //   - longitude is monotonic along pole-free arcs: the phi extent is the
 //     shortest circular interval holding the three vertex longitudes.
 __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c, float margin, Cand& cd) {
@@ -456,9 +458,10 @@ __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c
   const float pole_gap = fminf(tmin, PI_F - tmax) - l;  // lower bound of the pole distance of any point
   if (!(pole_gap > 2.0f * margin + 1e-3f)) return false;
   const float s_lo = 0.63661977f * pole_gap;  // sin x >= 2x / pi on [0, pi/2]
-  if (!(0.132f * q <= 2e-6f * s_lo)) return false;
+  const float bulge = 0.132f * q / s_lo;
+  if (!(bulge <= 1e-3f)) return false;
   const float m = margin + 2e-6f;
-  const float tlo = tmin - m, thi = tmax + m;
+  const float tlo = tmin - m - bulge, thi = tmax + m + bulge;
   cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
   cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
   cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
@@ -488,7 +491,8 @@ __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c
   return true;
 }
 
-// Longitude window of the triangle on one node row (colatitude theta_r): the
+// Longitude window of the triangle on one node row (colatitude theta_r, given
+// as sr = sin theta_r, cr = cos theta_r; sm = sin margin): the
 // box window with every part removed that lies more than `margin` outside one
 // of the three edge hemispheres o (d_a x d_b).x >= 0.  On the row circle, the
 // points outside an edge form one arc (a "hole") centred opposite the edge
@@ -496,13 +500,12 @@ __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c
 // window a single interval holding the triangle's part of the row.  FP64,
 // because near-tangent rows make the hole ends ill-conditioned.
 template <typename G>
-__device__ inline bool row_window(const Tri<G>& T, const Box& bx, double theta_r, double margin, double& lo,
+__device__ inline bool row_window(const Tri<G>& T, const Box& bx, double sr, double cr, double sm, double& lo,
                                   double& hi) {
   const double TWO_PI = 6.283185307179586, PI = 3.141592653589793;
   lo = bx.plo;
   hi = bx.phi;
   bool full = bx.full;
-  const double sr = sin(theta_r), cr = cos(theta_r), sm = sin(margin);
   double hc[3], hw[3];
   bool has[3];
 #pragma unroll
@@ -1014,6 +1017,7 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
   const int lane = threadIdx.x & 63;
   const unsigned n_items = min(*pool.n_rows, (unsigned)pool.rows_cap);
   const int part = wave_partition();
+  const double sin_margin = sin(margin);
   for (unsigned first = blockIdx.x * blockDim.x; first < n_items; first += gridDim.x * blockDim.x) {
     const unsigned item = first + threadIdx.x;
     int n = 0;
@@ -1042,7 +1046,7 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
       if (T.orient != 0) {
         const Box bx = tri_box(T, (float)margin);
         double lo_phi, hi_phi;
-        if (row_window(T, bx, ng.th[it], margin, lo_phi, hi_phi)) {
+        if (row_window(T, bx, ng.sth[it], ng.cth[it], sin_margin, lo_phi, hi_phi)) {
           int j0[2], j1[2];
           const int nr = phi_ranges(ng, lo_phi, hi_phi, j0, j1);
           Cand cd;
