@@ -13,13 +13,20 @@
  * the nodes of a cell it scatters around it by the fringe contrast over the
  * square root of the node count, too much to learn to 1%.  Features:
  *     (b/a, c/a, ln(k rbar), m, alpha, beta, gamma, theta_cell, phi_cell)
- * with rbar = (abc)^(1/3), Euler angles and cell centres in degrees.
- * Network: 9 -> 512 -> ... (6 hidden layers of width 512, GELU) -> 4 outputs:
+ * with rbar = (abc)^(1/3), Euler angles and cell centres in degrees.  The
+ * network first maps them to a fixed 23-wide embedding: the 9 normalised
+ * features; the particle-frame unit vectors of the incident direction, both
+ * polarisations and the cell direction (ZYZ Euler angles, lab = Rz(alpha)
+ * Ry(beta) Rz(gamma) body); cos and sin of phi.
+ * Network: embedding -> 512 -> ... (6 hidden layers of width 512, GELU) -> 4 outputs:
  * the two means and ln(sigma) of each, sigma being the predicted standard
  * deviation of ln I.  BF16 weights and activations, FP32 accumulation on the
- * matrix cores; FP32 master weights; trained with the Gaussian negative
- * log-likelihood  0.5 (y - mu)^2 / sigma^2 + ln sigma  and Adam (b1 = 0.9,
- * b2 = 0.999, eps = 1e-8).  Inputs and targets are normalised inside with the
+ * matrix cores; FP32 master weights; trained with Adam (b1 = 0.9, b2 =
+ * 0.999, eps = 1e-8) on the beta-NLL with beta = 1 (Seitzer et al., ICLR
+ * 2022): the Gaussian negative log-likelihood 0.5 (y - mu)^2 / sigma^2 +
+ * ln sigma of each output, weighted by sigma^2 held constant, so that the
+ * means get the squared-error gradient and sigma^2 tends to the expected
+ * squared error; ln sigma is floored at ln 1e-4 (normalised units) in it.  Inputs and targets are normalised inside with the
  * shifts and scales set by rtw_surrogate_set_normalization.
  *
  * Queries whose predicted sigma exceeds a threshold tau (either polarisation)
@@ -43,6 +50,7 @@ extern "C" {
 #endif
 
 #define RTW_SURROGATE_INPUTS 9
+#define RTW_SURROGATE_EMBED 23
 #define RTW_SURROGATE_WIDTH 512
 #define RTW_SURROGATE_DEPTH 6
 
@@ -62,8 +70,9 @@ typedef struct {
 const char* rtw_surrogate_last_error(void);
 
 /* Number of FP32 parameters in the order of get/set_params: for each layer
- * l = 0..6, W[in][out] then bias[out], with in = 128 for layer 0 (rows >= 9
- * are zero and stay zero) and out = 128 for the last layer (columns >= 4). */
+ * l = 0..6, W[in][out] then bias[out], with in = 128 for layer 0 (rows >= 23,
+ * past the embedding, are zero and stay zero) and out = 128 for the last
+ * layer (columns >= 4). */
 int rtw_surrogate_param_count(size_t* n);
 
 /* New surrogate with seeded uniform He initialisation (SplitMix64 stream),
@@ -84,7 +93,7 @@ int rtw_surrogate_set_params(rtw_surrogate* h, const float* host, size_t n);
  * [n][4] FP32: ln I_x, ln I_y, ln sigma_x, ln sigma_y.  n <= max_rows. */
 int rtw_surrogate_forward(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream);
 
-/* Loss and gradients of the mean Gaussian NLL over n rows (DEVICE feats
+/* Loss and gradients of the mean beta-NLL over n rows (DEVICE feats
  * [n][9], DEVICE targets [n][2] = ln I_x, ln I_y); *loss (DEVICE float)
  * receives the loss in normalised units.  rtw_surrogate_get_grads reads the
  * gradients (synchronous, parameter order).  train_step also applies one Adam

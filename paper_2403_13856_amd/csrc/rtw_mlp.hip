@@ -1,14 +1,15 @@
 // rtw_mlp.hip -- the learned surrogate of the RTW far field on gfx950: an MLP
-// 9 -> 512 (x6, GELU) -> 2 means + 2 log-sigmas, BF16 weights and activations
+// 9 features -> fixed 23-wide embedding -> 512 (x6, GELU) -> 2 means + 2
+// log-sigmas, BF16 weights and activations
 // with FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16),
 // trained with a Gaussian negative log-likelihood and Adam, queried with an
 // RTW fallback wherever the predicted sigma exceeds the caller's threshold.
 //
 // Layouts (row-major): activations [rows][512] BF16; each layer keeps FP32
 // master weights W[in][out], Adam moments, and two BF16 copies W[in][out]
-// (for dX = dZ W^T) and W^T[out][in] (for Y = X W).  The 9 inputs are padded
-// to 128 and the 4 outputs to 128 columns (zero weights), so every product is
-// a multiple of the 128 x 128 block tile.
+// (for dX = dZ W^T) and W^T[out][in] (for Y = X W).  The 23 embedded inputs
+// are padded to 128 and the 4 outputs to 128 columns (zero weights), so every
+// product is a multiple of the 128 x 128 block tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rtw_surrogate.h"
@@ -40,11 +42,14 @@ int mfail(int code, const char* fmt, ...) {
 }
 
 constexpr int IN_RAW = RTW_SURROGATE_INPUTS;  // 9 features
+constexpr int IN_EMB = RTW_SURROGATE_EMBED;   // fixed embedding of the features (first-layer inputs)
 constexpr int IN_PAD = 128;
+static_assert(IN_EMB <= IN_PAD, "embedding wider than the padded input");
 constexpr int HID = RTW_SURROGATE_WIDTH;      // 512
 constexpr int N_HIDDEN = RTW_SURROGATE_DEPTH; // 6 hidden layers
 constexpr int N_LAYERS = N_HIDDEN + 1;
 constexpr int OUT_RAW = 4;                    // mean x, mean y, log sigma x, log sigma y
+constexpr float S_MIN = -9.2103404f;          // ln 1e-4: floor of the normalised log-sigma in the loss
 constexpr int OUT_PAD = 128;
 
 constexpr int layer_in(int l) { return l == 0 ? IN_PAD : HID; }
@@ -217,21 +222,66 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 // element-wise kernels
 // ---------------------------------------------------------------------------
 
-// Normalised, padded BF16 inputs from FP32 features [n][9].
+// The fixed embedding of one feature row x = (b/a, c/a, ln k rbar, m, alpha,
+// beta, gamma, theta, phi), angles in degrees, ZYZ Euler angles of the
+// particle (lab = Rz(alpha) Ry(beta) Rz(gamma) body):
+//   [0, 9)   (x - shift) / scale
+//   [9, 21)  particle-frame unit vectors of the incident direction z, the two
+//            polarisations x and y and the cell-centre direction s
+//   [21, 23) cos phi, sin phi
+// then BF16 and zero up to IN_PAD.  One thread per row.
 __global__ void k_inputs(int n, int n_pad, const float* feats, const float* shift, const float* scale, bf16* X) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)n_pad * IN_PAD) return;
-  const long r = i / IN_PAD;
-  const int c = (int)(i - r * IN_PAD);
-  float v = 0.f;
-  if (r < n && c < IN_RAW) v = (feats[r * IN_RAW + c] - shift[c]) / scale[c];
-  X[i] = (bf16)v;
+  const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_pad) return;
+  constexpr int E8 = (IN_EMB + 7) / 8 * 8;
+  float e[E8];
+#pragma unroll
+  for (int c = 0; c < E8; ++c) e[c] = 0.0f;
+  if (r < n) {
+    const float* x = feats + r * IN_RAW;
+#pragma unroll
+    for (int c = 0; c < IN_RAW; ++c) e[c] = (x[c] - shift[c]) / scale[c];
+    const float D2R = 0.017453292519943295f;
+    float sa, ca, sb, cb, sg, cg, st, ct, sp, cp;
+    sincosf(x[4] * D2R, &sa, &ca);
+    sincosf(x[5] * D2R, &sb, &cb);
+    sincosf(x[6] * D2R, &sg, &cg);
+    sincosf(x[7] * D2R, &st, &ct);
+    sincosf(x[8] * D2R, &sp, &cp);
+    // rows of R: the particle-frame components of the lab axes
+    const float R0[3] = {ca * cb * cg - sa * sg, -ca * cb * sg - sa * cg, ca * sb};
+    const float R1[3] = {sa * cb * cg + ca * sg, -sa * cb * sg + ca * cg, sa * sb};
+    const float R2[3] = {-sb * cg, sb * sg, cb};
+    const float s0 = st * cp, s1 = st * sp, s2 = ct;
+    float vz[3], vx[3], vy[3], vs[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      vz[i] = R2[i]; vx[i] = R0[i]; vy[i] = R1[i];
+      vs[i] = s0 * R0[i] + s1 * R1[i] + s2 * R2[i];
+      e[9 + i] = vz[i]; e[12 + i] = vx[i]; e[15 + i] = vy[i]; e[18 + i] = vs[i];
+    }
+    e[21] = cp; e[22] = sp;
+  }
+  bf16x8* dst = reinterpret_cast<bf16x8*>(X + r * IN_PAD);
+#pragma unroll
+  for (int c8 = 0; c8 < IN_PAD / 8; ++c8) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = 8 * c8 + j < E8 ? (bf16)e[8 * c8 + j] : (bf16)0.0f;
+    dst[c8] = v;
+  }
 }
 
-// Gaussian negative log-likelihood of normalised targets y under N(mu, e^{2s})
-// per output pair, mean over rows < n and the two outputs; gradient w.r.t. the
-// output pre-activations (zero in padded rows and columns) and per-block
-// partial sums of the loss.
+// Loss of normalised targets y under N(mu, e^{2s}) per output pair, mean over
+// rows < n and the two outputs: the beta-NLL of Seitzer et al. (ICLR 2022)
+// with beta = 1, i.e. each element's Gaussian NLL 0.5 d^2 e^{-2s} + s
+// (d = y - mu) weighted by w = e^{2s} held constant.  Its value is
+// 0.5 d^2 + s w; its gradient is -d for mu (that of the squared error, so no
+// small sigma can blow up the mean's step) and w - d^2 for s (stationary at
+// sigma^2 = E d^2).  Writes the gradient w.r.t. the output pre-activations
+// (zero in padded rows and columns) and per-block partial sums of the loss.
+// The log-sigma enters as max(s, S_MIN) (sigma = 1e-4 in normalised units,
+// far below the error bars of use); below the floor its gradient is zero.
 __global__ void __launch_bounds__(256) k_nll(int n, int n_pad, const float* out, const float* targets,
                                              const float* t_shift, const float* t_scale, bf16* dZ, float* partial) {
   __shared__ float red[256];
@@ -243,11 +293,12 @@ __global__ void __launch_bounds__(256) k_nll(int n, int n_pad, const float* out,
       const float inv = 1.0f / (2.0f * (float)n);
       for (int o = 0; o < 2; ++o) {
         const float y = (targets[r * 2 + o] - t_shift[o]) / t_scale[o];
-        const float mu = out[r * OUT_PAD + o], s = out[r * OUT_PAD + 2 + o];
-        const float e = __expf(-2.0f * s), d = y - mu;
-        l += (0.5f * d * d * e + s) * inv;
-        g[o] = -d * e * inv;
-        g[2 + o] = (1.0f - d * d * e) * inv;
+        const float mu = out[r * OUT_PAD + o], s_raw = out[r * OUT_PAD + 2 + o];
+        const float s = fmaxf(s_raw, S_MIN);
+        const float w = __expf(2.0f * s), d = y - mu;
+        l += (0.5f * d * d + s * w) * inv;
+        g[o] = -d * inv;
+        g[2 + o] = s_raw > S_MIN ? (w - d * d) * inv : 0.0f;
       }
     }
     for (int c = 0; c < OUT_PAD; ++c) dZ[r * OUT_PAD + c] = (bf16)(c < OUT_RAW ? g[c] : 0.f);
@@ -477,8 +528,7 @@ int forward(rtw_surrogate* h, int n_pad, hipStream_t st) {
 }
 
 int upload_inputs(rtw_surrogate* h, int n, int n_pad, const float* feats, hipStream_t st) {
-  const long tot = (long)n_pad * IN_PAD;
-  hipLaunchKernelGGL(k_inputs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, n_pad, feats, h->norm,
+  hipLaunchKernelGGL(k_inputs, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, st, n, n_pad, feats, h->norm,
                      h->norm + IN_RAW, h->X0);
   return RTW_OK;
 }
@@ -553,13 +603,13 @@ int rtw_surrogate_create(uint64_t seed, int max_rows, rtw_surrogate** out) {
   Mix mx{seed};
   std::vector<float> w, z;
   for (int l = 0; l < N_LAYERS; ++l) {
-    const int fi = l == 0 ? IN_RAW : HID;
+    const int fi = l == 0 ? IN_EMB : HID;
     const double b = std::sqrt(6.0 / fi) * (l == N_LAYERS - 1 ? 0.1 : 1.0);
     w.assign((size_t)layer_in(l) * layer_out(l), 0.f);
     for (int i = 0; i < layer_in(l); ++i)
       for (int o = 0; o < layer_out(l); ++o) {
         const double u = (2.0 * mx.uniform() - 1.0) * b;
-        const bool live = (l > 0 || i < IN_RAW) && (l < N_LAYERS - 1 || o < OUT_RAW);
+        const bool live = (l > 0 || i < IN_EMB) && (l < N_LAYERS - 1 || o < OUT_RAW);
         w[(size_t)i * layer_out(l) + o] = live ? (float)u : 0.f;
       }
     z.assign(w.size(), 0.f);
@@ -611,7 +661,7 @@ int rtw_surrogate_set_normalization(rtw_surrogate* h, const float* feat_shift, c
 }
 
 // Parameters in a fixed order, FP32: for each layer l = 0..6, W[in][out] then
-// bias[out], with in = 128 for layer 0 (rows >= 9 unused) and out = 128 for
+// bias[out], with in = 128 for layer 0 (rows >= 23 unused) and out = 128 for
 // the last layer (columns >= 4 unused).
 int rtw_surrogate_get_params(rtw_surrogate* h, float* host, size_t n) {
   size_t need = 0;
@@ -857,21 +907,37 @@ int rtw_surrogate_query(rtw_surrogate* h, int n_query, const float* feats, const
     if (hneed[p]) { slot[p] = (int)fp.size(); fp.push_back(parts[p]); fg.push_back(grid_n[p]); }
   if (n_recomputed) *n_recomputed = (int)fp.size();
   hipMemcpyAsync(dslot, slot.data(), sizeof(int) * (size_t)n_part, hipMemcpyHostToDevice, st);
-  // 3. RTW for those particles
-  if (!fp.empty()) {
+  // 3. RTW for those particles.  The batch workspace is not monotone in the
+  // particle set (a subset can group into chunks that need more than the whole
+  // set), so each batch is checked against the scratch left after the cell
+  // values and split in halves until it fits; one particle always fits, its
+  // workspace being at most that of the whole set the scratch was sized for.
+  const size_t avail = scratch_bytes - (size_t)(ws - (char*)scratch);
+  const size_t nodes = (size_t)grid->n_theta * grid->n_phi;
+  const rtw_batch_opts bo{0, FALLBACK_HITS_PER_NODE};
+  std::vector<std::pair<int, int>> todo;  // [first, count) ranges of fp
+  if (!fp.empty()) todo.push_back({0, (int)fp.size()});
+  while (!todo.empty()) {
+    const int f0 = todo.back().first, nf = todo.back().second;
+    todo.pop_back();
     size_t wsb = 0;
-    const rtw_batch_opts bo{0, FALLBACK_HITS_PER_NODE};
-    rc = rtw_batch_workspace_size((int)fp.size(), fp.data(), fg.data(), inc, opts, grid, &bo, &wsb);
+    rc = rtw_batch_workspace_size(nf, fp.data() + f0, fg.data() + f0, inc, opts, grid, &bo, &wsb);
     if (rc) return mfail(rc, "%s", rtw_last_error());
     wsb = a256(wsb);
-    const size_t nodes = (size_t)grid->n_theta * grid->n_phi;
+    const size_t ffb = a256((size_t)nf * 2 * 2 * nodes * 2 * sizeof(float));
+    if (wsb + ffb + (size_t)nf * 2 * nodes * sizeof(float) > avail) {
+      if (nf == 1) return mfail(RTW_ERR_WORKSPACE, "fallback particle does not fit the query scratch");
+      todo.push_back({f0 + nf / 2, nf - nf / 2});
+      todo.push_back({f0, nf / 2});
+      continue;
+    }
     char* ff = ws + wsb;
-    float* incoh = (float*)(ff + a256(fp.size() * 2 * 2 * nodes * 2 * sizeof(float)));
-    rc = rtw_batch((int)fp.size(), fp.data(), fg.data(), inc, opts, grid, ff, nullptr, incoh, tune, &bo, ws, wsb,
+    float* incoh = (float*)(ff + ffb);
+    rc = rtw_batch(nf, fp.data() + f0, fg.data() + f0, inc, opts, grid, ff, nullptr, incoh, tune, &bo, ws, wsb,
                    hip_stream);
     if (!rc) rc = rtw_farfield_status(ws, hip_stream, nullptr);
     if (rc) return mfail(rc, "fallback: %s", rtw_last_error());
-    rc = rtw_cell_log_intensity((int)fp.size(), incoh, 2, grid, cells, cellI, hip_stream);
+    rc = rtw_cell_log_intensity(nf, incoh, 2, grid, cells, cellI + (size_t)f0 * n_cells * 2, hip_stream);
     if (rc) return rc;
   }
   // 4. answers (dslot was uploaded synchronously before its first use by hipMemcpyAsync ordering)

@@ -5,7 +5,8 @@
   predictions within 2e-2 (1 + |value|), per-layer weight gradients within
   5e-2 relative L2 with cosine > 0.995.  The reference's own gradients are
   pinned against central differences by tests/test_oracle_mlp.py.
-* Training reduces the loss of a smooth synthetic target.
+* Training fits the means of a smooth synthetic target, and the sigma head
+  tracks the squared error.
 * The query path: with tau below every sigma all answers are RTW cell values
   (bitwise those of rtw_batch + rtw_cell_log_intensity); with tau above every
   sigma all answers are the surrogate's predictions.
@@ -100,7 +101,7 @@ def test_gradients_match_reference(R):
             assert rel < 5e-2 and cos > 0.995
 
 
-def test_training_reduces_loss(R):
+def test_training_fits_means_and_sigma(R):
     rng = np.random.default_rng(3)
     s = _net(R, 13)
     f = _feats(rng, 8192)
@@ -111,16 +112,20 @@ def test_training_reduces_loss(R):
     ft, yt = torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda()
     rmse0 = np.sqrt(np.mean((s.forward(ft).cpu().numpy()[:, :2] - y) ** 2))
     losses = []
-    for it in range(600):
+    for it in range(1200):
         a = (it * 1024) % 8192
         losses.append(s.train_step(ft[a:a + 1024], yt[a:a + 1024], 1e-3).item())
-    first, last = np.mean(losses[:20]), np.mean(losses[-20:])
-    say(f"[surrogate training] mean minibatch loss {first:.3f} (first 20 steps) -> {last:.3f} (last 20)")
-    assert np.isfinite(losses).all() and last < first - 1.0
+    assert np.isfinite(losses).all()
     pred = s.forward(ft).cpu().numpy()
-    rmse = np.sqrt(np.mean((pred[:, :2] - y) ** 2))
-    say(f"   rmse of ln I: {rmse0:.3f} before, {rmse:.3f} after 600 steps")
+    err2 = (pred[:, :2] - y) ** 2
+    rmse = np.sqrt(np.mean(err2))
+    sig2 = np.exp(2.0 * pred[:, 2:])
+    ratio = np.mean(sig2) / np.mean(err2)
+    say(f"[surrogate training] rmse of ln I {rmse0:.3f} -> {rmse:.3f} after 1200 steps; "
+        f"mean sigma^2 / mean squared error {ratio:.2f}")
     assert rmse < 0.25 * rmse0
+    # the sigma head estimates the squared error (beta-NLL: stationary at sigma^2 = E d^2)
+    assert 0.25 < ratio < 4.0
 
 
 def test_query_fallback_extremes(R):
@@ -149,3 +154,60 @@ def test_query_fallback_extremes(R):
     ans, pred, used, nrec = s.query(ft, qp, qc, 1e30, desc, cells)
     assert nrec == 0 and int(used.sum()) == 0
     assert np.array_equal(ans.cpu().numpy(), pred.cpu().numpy()[:, :2])
+
+
+def _batch_ws(R, parts, sides, inc, opts, n_theta, n_phi):
+    import ctypes
+    n = len(parts)
+    P = (R.Particle * n)(*[R.make_particle(*p) for p in parts])
+    G = (ctypes.c_int * n)(*sides)
+    g = R.Grid(n_theta, 1, n_phi, 1)  # pointers are not read by the size query
+    bo = R.BatchOpts(0, 12.0)
+    out = ctypes.c_size_t(0)
+    assert R.load().rtw_batch_workspace_size(n, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g),
+                                             ctypes.byref(bo), ctypes.byref(out)) == 0
+    return out.value
+
+
+def test_query_partial_fallback_larger_than_whole_set(R):
+    # A subset of the particles can group into chunks that need more workspace
+    # than the whole set the query scratch is sized for; the query must split
+    # its fallback batch instead of overrunning the scratch.
+    import itertools
+    th, ph = I.batch_node_grid()
+    inc = R.make_incident(0.6328, 2)
+    opts = R.make_opts(0, 3, 2, R.MIXED)
+    rng = np.random.default_rng(4)
+    found = None
+    for _ in range(200):
+        sides = [int(v) for v in rng.choice([1024, 2048, 3072, 4096], size=6)]
+        parts = [I.random_ellipsoid(rng, 15.0, 40.0) for _ in range(6)]
+        full = _batch_ws(R, parts, sides, inc, opts, th.size, ph.size)
+        for k in range(5, 0, -1):
+            for S in itertools.combinations(range(6), k):
+                if _batch_ws(R, [parts[i] for i in S], [sides[i] for i in S], inc, opts, th.size, ph.size) > full:
+                    found = (parts, sides, list(S))
+                    break
+            if found:
+                break
+        if found:
+            break
+    assert found is not None
+    parts, sides, S = found
+    say(f"[surrogate query] sides {sides}, fallback subset {S} needs more workspace than all six")
+    cells = R.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
+    b = R.Batch(parts, sides, inc, opts, th, ph, incoherent=True)
+    b()
+    cellI = R.cell_log_intensity(b, cells).cpu().numpy()
+    del b
+    torch.cuda.empty_cache()
+    feats = R.surrogate_features(parts, inc, cells).reshape(6, 360, 9)
+    q_part = np.repeat(np.array(S, np.int32), 360)
+    q_cell = np.tile(np.arange(360, dtype=np.int32), len(S))
+    ft = torch.from_numpy(np.ascontiguousarray(feats[q_part, q_cell])).cuda()
+    s = _net(R, 15)
+    desc = R.Batch(parts, sides, inc, opts, th, ph, allocate=False)
+    ans, pred, used, nrec = s.query(ft, torch.from_numpy(q_part).cuda(), torch.from_numpy(q_cell).cuda(), 1e-30,
+                                    desc, cells)
+    assert nrec == len(S) and int(used.sum()) == q_part.size
+    assert np.array_equal(ans.cpu().numpy(), cellI[q_part, q_cell])
