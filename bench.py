@@ -39,8 +39,11 @@ FLOP_STORE_PER_HIT = 180
 # propagations, four emissions
 FLOP_TRACE_PER_RAY = 4 * 300 + 3 * 60 + 4 * 200
 PEAK_VALU_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, one per 4 cycles
+TRAIN_SEEDS = (11, 12, 15, 16)  # surrogate training particles: 4 x 4096 seeded ellipsoids
+LR_PEAK = 1e-3                  # surrogate Adam learning rate at the start of the cosine schedule
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_raster_mixed_c2_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_raster_mixed_c2_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_13856_amd", "csrc", f)
                   for f in ("rtw_lib.hip", "rtw_device.hpp", "rtw_raster.hpp")]
 
@@ -54,13 +57,15 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the rasteriser from the committed PMC summary,
-    or None if the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_counters():
+    """PMC figures of the rasteriser from the committed rocprofv3 summary (HBM
+    bytes per launch after the copy calibration, VALU busy share and lane
+    utilisation, VALU wave instructions), or None if the kernel sources
+    changed since the counters were taken."""
+    if not os.path.exists(COUNTERS_FILE):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(COUNTERS_FILE) as fh:
         for line in fh:
             if ":" in line and not line.startswith((" ", "#", "\t")):
                 k, v = line.split(":", 1)
@@ -68,7 +73,9 @@ def measured_traffic():
     if kv.get("source_hash") != source_hash():
         return None
     try:
-        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+        return dict(traffic=float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]),
+                    valu_busy_pct=float(kv["valu_busy_pct"]), valu_utilization_pct=float(kv["valu_utilization_pct"]),
+                    valu_insts=float(kv["valu_insts_per_launch"]))
     except (KeyError, ValueError):
         return None
 
@@ -219,7 +226,10 @@ def bench_surrogate(args, rtw, inputs):
     deg over theta 120-170 deg), calibrate sigma's threshold tau on held-out
     particles so that accepted answers are within 1% (|d ln I| <= 0.01 for
     99% of them), then time 1,048,576 queries (128 random cells of each of
-    8192 new particles) answered with RTW fallback, against RTW alone."""
+    8192 new particles) answered with RTW fallback, against RTW alone; the
+    same queries are also timed at the 2%, 5% and 10% bars.  A particle with
+    any rejected query is traced whole, so the gain follows the fraction of
+    particles whose queries are all accepted."""
     import numpy as np
     import torch
     rtw.sload()
@@ -254,7 +264,7 @@ def bench_surrogate(args, rtw, inputs):
     t0 = time.perf_counter()
     tune = None
     F, Y = [], []
-    for seed in (11, 12):
+    for seed in TRAIN_SEEDS:
         _, _, f, y, dt, tune = traced(seed, 4096, tune)
         F.append(f); Y.append(y)
         log(f"[surrogate] training data seed {seed}: {y.shape[0]} samples, RTW {dt:.2f} s")
@@ -271,13 +281,15 @@ def bench_surrogate(args, rtw, inputs):
     bs = 8192
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    perm = torch.randperm(n, device=F.device)
+    gen = torch.Generator(device=F.device)
+    gen.manual_seed(0)  # seeded minibatch order: the training is reproducible
+    perm = torch.randperm(n, device=F.device, generator=gen)
     for it in range(args.train_steps):
         a = (it * bs) % (n - bs)
         if a < bs:
-            perm = torch.randperm(n, device=F.device)
+            perm = torch.randperm(n, device=F.device, generator=gen)
         idx = perm[a:a + bs]
-        lr = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + np.cos(np.pi * it / args.train_steps))
+        lr = 1e-5 + 0.5 * (LR_PEAK - 1e-5) * (1 + np.cos(np.pi * it / args.train_steps))
         loss = net.train_step(F[idx].contiguous(), Y[idx].contiguous(), lr)
         if it % 500 == 0 or it == args.train_steps - 1:
             log(f"[surrogate] step {it}: loss {loss.item():.4f}")
@@ -302,7 +314,8 @@ def bench_surrogate(args, rtw, inputs):
         return (float(sig[order[k_best - 1]].item()) if k_best > 0 else 1e-30), k_best / err.numel()
 
     tau, acc_cal = calibrate(0.01)
-    others = {f"{b:g}": round(calibrate(b)[1], 4) for b in (0.02, 0.05, 0.1)}
+    taus = {b: calibrate(b) for b in (0.02, 0.05, 0.1)}
+    others = {f"{b:g}": round(t[1], 4) for b, t in taus.items()}
     log(f"[surrogate] calibration on {err.numel()} held-out queries: median |d ln I| {err.median().item():.4f}; "
         f"tau {tau:.4g} accepts {acc_cal:.2%} at 1%; accepted fractions at other error bars {others}")
 
@@ -331,16 +344,57 @@ def bench_surrogate(args, rtw, inputs):
     rc, _ = b.status()
     if rc != rtw.RTW_OK:
         raise RuntimeError("hit pool overflow in the query batch")
-    del b, cI
+    cI_all = cI
+    del b
     torch.cuda.empty_cache()
     # surrogate with fallback
     desc = rtw.Batch(parts, sides, inc, opts, th, ph, allocate=False)
     net.query(qf[:1024], qp[:1024], qc[:1024], 1e30, desc, cells, tune)  # warm-up (allocates the scratch)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ans, pred, used, nrec = net.query(qf, qp, qc, tau, desc, cells, tune)
-    torch.cuda.synchronize()
-    t_q = time.perf_counter() - t0
+
+    def timed_query(t):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = net.query(qf, qp, qc, t, desc, cells, tune)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    # context: every bar, on this query set and on a sparse one (8 random cells
+    # of each of the same particles; RTW alone costs the same trace)
+    k_s = 8
+    qc_s = rng.integers(0, n_cells, size=(n_qp, k_s)).astype(np.int32)
+    qp_s = np.repeat(np.arange(n_qp, dtype=np.int32), k_s)
+    sparse = (torch.from_numpy(np.ascontiguousarray(allf[qp_s, qc_s.ravel()])).cuda(), torch.from_numpy(qp_s).cuda(),
+              torch.from_numpy(qc_s.ravel().copy()).cuda())
+    truth_s = cI_all[sparse[1].long(), sparse[2].long()]
+
+    def timed_query(t, qs=None):
+        f_, p_, c_ = qs if qs is not None else (qf, qp, qc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = net.query(f_, p_, c_, t, desc, cells, tune)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    at_bars = {}
+    for b, tb in [(0.01, tau)] + [(b, t[0]) for b, t in taus.items()]:
+        row = dict(tau=tb)
+        for name, qs, tr, nq_ in (("dense", None, truth, n_q), ("sparse", sparse, truth_s, n_qp * k_s)):
+            if name == "dense" and b == 0.01:
+                continue  # the headline run below
+            (ans_b, _, used_b, nrec_b), t_b = timed_query(tb, qs)
+            acc_b = used_b == 0
+            e_b = (ans_b - tr).abs().max(dim=1).values[acc_b]
+            row[name] = dict(queries=nq_, accepted_fraction=round(float(acc_b.float().mean().item()), 4),
+                             particles_retraced=nrec_b, queries_per_s=round(nq_ / t_b, 1),
+                             gain_over_rtw_only=round(t_rtw / t_b, 3),
+                             accepted_err_p99=round(float(torch.quantile(e_b[:1000000].float(), 0.99).item()), 4)
+                             if e_b.numel() else 0.0)
+            log(f"[surrogate] bar {b:g} {name} ({nq_} queries): tau {tb:.4g}, accepted "
+                f"{row[name]['accepted_fraction']:.2%}, particles re-traced {nrec_b}/{n_qp}, "
+                f"{nq_ / t_b:.0f} queries/s (gain {t_rtw / t_b:.2f})")
+            del ans_b, used_b, e_b
+        at_bars[f"{b:g}"] = row
+    (ans, pred, used, nrec), t_q = timed_query(tau)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.forward(qf)
@@ -363,13 +417,14 @@ def bench_surrogate(args, rtw, inputs):
         "dtype": "bf16+f32", "data": "synthetic",
         "config": {"workload": f"{n_q} queries: {k_q} random 5x10 deg cells (theta 120-170) of each of {n_qp} seeded "
                                f"ellipsoids (batched-workload distribution); MLP 9-512x6-4 trained "
-                               f"{args.train_steps} steps on {n} cell samples of 8192 other ellipsoids",
+                               f"{args.train_steps} steps on {n} cell samples of {4096 * len(TRAIN_SEEDS)} other ellipsoids",
                    "tau": tau, "accepted_fraction": frac_acc, "particles_retraced": nrec,
                    "accepted_err_p99": p99, "accepted_err_gt_1pct": frac_bad,
                    "rtw_only_queries_per_s": round(n_q / t_rtw, 1), "gain_over_rtw_only": round(t_rtw / t_q, 3),
                    "network_only_queries_per_s": round(n_q / t_fwd, 1), "train_seconds": round(t_train, 2),
                    "calibration_accepted_fraction": acc_cal, "calibration_accepted_at_other_bars": others,
-                   "calibration_median_err": float(err.median().item())},
+                   "calibration_median_err": float(err.median().item()), "by_bar": at_bars,
+                   "lr_peak": LR_PEAK, "train_particles": 4096 * len(TRAIN_SEEDS)},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -388,7 +443,7 @@ def main():
     ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate"], default="ellipsoid",
                     help="ellipsoid: the 2048^2-ray ellipsoid (default); batch: 4096 seeded ellipsoids via rtw_batch; "
                          "surrogate: train the MLP on rtw_batch data, then time 1M queries with RTW fallback")
-    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--train-steps", type=int, default=40000)
     ap.add_argument("--batch-n", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -452,12 +507,16 @@ def main():
     else:
         flops = 8 * hits
     achieved = flops / avg_s / 1e12
-    traffic = measured_traffic() if dom == "k_raster_mixed" else None
+    ctr = measured_counters() if dom == "k_raster_mixed" else None
+    traffic = ctr["traffic"] if ctr else None
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
                     traffic=round(traffic) if traffic is not None else None, kernel=dom,
                     kernel_ms=round(avg_s * 1e3, 4), flop_per_launch=flops,
-                    traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic is not None else None)
+                    traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic is not None else None,
+                    valu_busy_pct=ctr["valu_busy_pct"] if ctr else None,
+                    valu_utilization_pct=ctr["valu_utilization_pct"] if ctr else None,
+                    valu_issue_frac=round(ctr["valu_insts"] / avg_s / VALU_ISSUE_PEAK, 4) if ctr else None)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1,5 +1,5 @@
 """Host-side logic of bench.py (no GPU): the one-GPU contract and the
-traffic summary lookup."""
+lookup of the committed PMC counter summary."""
 import os
 import subprocess
 import sys
@@ -16,22 +16,29 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_summary_matches_or_is_dropped(tmp_path, monkeypatch):
+COUNTER_LINES = ("fetch_bytes_per_launch: 100\nwrite_bytes_per_launch: 23\nvalu_busy_pct: 55.5\n"
+                 "valu_utilization_pct: 40.25\nvalu_insts_per_launch: 7\ncounted_flops_fp32_per_launch: 1000\n"
+                 "counted_flops_fp64_per_launch: 24\n")
+
+
+def test_counter_summary_matches_or_is_dropped(tmp_path, monkeypatch):
     f = tmp_path / "t.txt"
-    f.write_text(f"kernel: k\nsource_hash: {bench.source_hash()}\nfetch_bytes_per_launch: 100\n"
-                 f"write_bytes_per_launch: 23\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic() == 123.0
-    f.write_text("source_hash: 0000\nfetch_bytes_per_launch: 100\nwrite_bytes_per_launch: 23\n")
-    assert bench.measured_traffic() is None  # kernel changed since the counters were taken
+    f.write_text(f"kernel: k\nsource_hash: {bench.source_hash()}\n" + COUNTER_LINES)
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
+    c = bench.measured_counters()
+    assert c == dict(traffic=123.0, valu_busy_pct=55.5, valu_utilization_pct=40.25, valu_insts=7.0)
+    f.write_text("source_hash: 0000\n" + COUNTER_LINES)
+    assert bench.measured_counters() is None  # kernel changed since the counters were taken
 
 
-def test_committed_traffic_summary_is_parseable():
+def test_committed_counter_summary_is_parseable():
     kv = {}
-    with open(bench.TRAFFIC_FILE) as fh:
+    with open(bench.COUNTERS_FILE) as fh:
         for line in fh:
             if ":" in line and not line.startswith((" ", "#")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     assert float(kv["fetch_bytes_per_launch"]) > 0 and float(kv["write_bytes_per_launch"]) > 0
+    assert 0 < float(kv["valu_busy_pct"]) <= 100 and 0 < float(kv["valu_utilization_pct"]) <= 100
+    assert float(kv["valu_insts_per_launch"]) > 0
     assert len(kv["source_hash"]) == 16
