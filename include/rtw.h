@@ -153,7 +153,7 @@ typedef struct {
   int tile_rays;     /* incident rays per trace work item, multiple of 256 (0 = 1024) */
   int blocks_per_cu; /* persistent trace blocks per compute unit (0 = 8) */
   int cand_inline;   /* triangles whose bounding box holds more nodes are rasterised
-                        row by row (0 = 32) */
+                        row by row (0 = 4096, the largest allowed) */
 } rtw_tune;
 
 typedef struct {

@@ -944,7 +944,7 @@ int rtw_batch_autotune(int n, const rtw_particle* parts, const int* grid_n, cons
   int rc = trial(cur, &best_ms);
   const int tiles[] = {256, 512, 1024, 2048, 4096};
   const int bpcs[] = {4, 8, 16};
-  const int cands[] = {8, 16, 32, 64, 128};
+  const int cands[] = {64, 256, 1024, 4096};
   for (int t : tiles)
     for (int bp : bpcs) {
       if (rc) break;

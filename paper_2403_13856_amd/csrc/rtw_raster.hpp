@@ -137,7 +137,9 @@ struct HitPool {
   int rows_cap;
 };
 
-constexpr int CAND_INLINE = 32;  // default: triangles with more box candidates go to the row list
+constexpr int CAND_INLINE = 4096;  // default: triangles with more box candidates go to the row list
+// (draining large boxes inline spreads them over the rasteriser's many waves;
+// the row kernel only serves boxes beyond this, e.g. triangles holding a pole)
 // Angular margin (rad) of the FP32 bounding box: well above its rounding error,
 // so the box never excludes a node that the exact membership test accepts.
 constexpr double BOX_MARGIN = 4e-6;
