@@ -58,12 +58,33 @@ struct NodeGrid {
 // One ray's emission record for one order, contiguous so that the three
 // vertices of a hit are a few cache lines each (gathered at random).  The
 // exit direction lives in its own array of 4-vectors (Records::dir), read
-// coalesced by the rasteriser's per-quad pass.
+// coalesced by the rasteriser's per-quad pass.  The field is transverse to
+// the direction, so it is stored as its two components on the direction's
+// own (e_theta, e_phi) basis (dir_basis of the stored direction): 48 B per
+// record in FP32 instead of 64 B for three Cartesian components.
 template <typename G>
 struct alignas(16) RayRec {
-  G kr[3];    // k r_exit (lab)
-  G f[12];    // [pol][xyz][re|im] lab field amp e^{i phase} (J_perp e_perp + J_par e_par)
+  G kr[3];  // k r_exit (lab)
+  G f[8];   // [pol][e_theta|e_phi][re|im]: field amp e^{i phase} (J_perp e_perp + J_par e_par)
+  G pad;
 };
+
+// (e_theta, e_phi) of a direction d (not necessarily of unit length, as
+// stored): with rho = |(dx, dy)|, cos phi = dx / rho, sin phi = dy / rho
+// (phi = 0 on the axis), e_theta = (dz cos phi, dz sin phi, -rho) and
+// e_phi = (-sin phi, cos phi, 0).  Both the writer and the reader of a record
+// evaluate it in FP64 from the same stored direction, so they agree exactly.
+__device__ __forceinline__ void dir_basis(double dx, double dy, double dz, v3<double>& et, v3<double>& ep) {
+  const double rho = sqrt(dx * dx + dy * dy);
+  double cp = 1.0, sp = 0.0;
+  if (rho > 0.0) {
+    const double r = 1.0 / rho;
+    cp = dx * r;
+    sp = dy * r;
+  }
+  et = mk3<double>(dz * cp, dz * sp, -rho);
+  ep = mk3<double>(-sp, cp, 0.0);
+}
 
 template <typename G>
 struct alignas(4 * sizeof(G)) Dir4 {
@@ -112,6 +133,12 @@ __device__ __forceinline__ int find_part(const long* off, int n, long base, long
 // A node hit found by the rasteriser, waiting for k_store_hits: which
 // triangle (record base, corner ray, grid side, half, key), which node, and
 // the barycentric weights.
+// Four values loaded or stored at once (the alignment makes it one vector access).
+template <typename G>
+struct alignas(4 * sizeof(G)) V4 {
+  G x, y, z, w;
+};
+
 template <typename G>
 struct HitDesc {
   int key;
@@ -177,12 +204,20 @@ struct RecordSink {
       const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz);
       sincos(dphi, &cim, &cre);
     }
-    for (int p = 0; p < 2; ++p)
-      for (int x = 0; x < 3; ++x) {
-        const double fr = (double)e.f[p][x].re, fi = (double)e.f[p][x].im;
-        r.f[(p * 3 + x) * 2 + 0] = p < rec.n_pol ? (G)(fr * cre - fi * cim) : (G)0;
-        r.f[(p * 3 + x) * 2 + 1] = p < rec.n_pol ? (G)(fr * cim + fi * cre) : (G)0;
-      }
+    v3<double> et, ep;
+    dir_basis((double)dv.x, (double)dv.y, (double)dv.z, et, ep);
+    for (int p = 0; p < 2; ++p) {
+      const double ar = (double)e.f[p][0].re * et.x + (double)e.f[p][1].re * et.y + (double)e.f[p][2].re * et.z;
+      const double ai = (double)e.f[p][0].im * et.x + (double)e.f[p][1].im * et.y + (double)e.f[p][2].im * et.z;
+      const double br = (double)e.f[p][0].re * ep.x + (double)e.f[p][1].re * ep.y;
+      const double bi = (double)e.f[p][0].im * ep.x + (double)e.f[p][1].im * ep.y;
+      const bool live = p < rec.n_pol;
+      r.f[p * 4 + 0] = live ? (G)(ar * cre - ai * cim) : (G)0;
+      r.f[p * 4 + 1] = live ? (G)(ar * cim + ai * cre) : (G)0;
+      r.f[p * 4 + 2] = live ? (G)(br * cre - bi * cim) : (G)0;
+      r.f[p * 4 + 3] = live ? (G)(br * cim + bi * cre) : (G)0;
+    }
+    r.pad = (G)0;
     rec.rr[at] = r;
     rec.dir[at] = dv;
     const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
@@ -626,9 +661,9 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
   const int N = d.nt >> 1, t = d.nt & 1;
   const long v00 = d.v00;
   const long vid[3] = {v00, t == 0 ? v00 + 1 : v00 + N + 1, t == 0 ? v00 + N + 1 : v00 + N};
-  const G st = (G)ng.sth[it], ct = (G)ng.cth[it], sp = (G)ng.sph[ip], cp = (G)ng.cph[ip];
-  const v3<G> eth = mk3<G>(ct * cp, ct * sp, -st);
-  const v3<G> eph = mk3<G>(-sp, cp, (G)0);
+  const double st = ng.sth[it], ct = ng.cth[it], sp = ng.sph[ip], cp = ng.cph[ip];
+  const v3<double> eth = mk3<double>(ct * cp, ct * sp, -st);
+  const v3<double> eph = mk3<double>(-sp, cp, 0.0);
   G acc[2][2][2];
   for (int p = 0; p < 2; ++p)
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
@@ -644,21 +679,25 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
     else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
     const G lr = d.lam[k] * c_, li = d.lam[k] * s_;
+    // the vertex field is stored on its direction's (e_theta, e_phi); turn it
+    // onto the node's
+    v3<double> et, ep;
+    dir_basis((double)dk.x, (double)dk.y, (double)dk.z, et, ep);
+    const G ctt = (G)dot(et, eth), cpt = (G)dot(ep, eth), ctp = (G)dot(et, eph), cpp = (G)dot(ep, eph);
     const G* fp = vr.f;
     for (int p = 0; p < rec.n_pol; ++p) {
-      G fxr = fp[p * 6 + 0], fxi = fp[p * 6 + 1];
-      G fyr = fp[p * 6 + 2], fyi = fp[p * 6 + 3];
-      G fzr = fp[p * 6 + 4], fzi = fp[p * 6 + 5];
-      G tr = fxr * eth.x + fyr * eth.y + fzr * eth.z, ti = fxi * eth.x + fyi * eth.y + fzi * eth.z;
-      G pr = fxr * eph.x + fyr * eph.y, pi_ = fxi * eph.x + fyi * eph.y;
+      const G ar = fp[p * 4 + 0], ai = fp[p * 4 + 1], br = fp[p * 4 + 2], bi = fp[p * 4 + 3];
+      const G tr = ar * ctt + br * cpt, ti = ai * ctt + bi * cpt;
+      const G pr = ar * ctp + br * cpp, pi_ = ai * ctp + bi * cpp;
       acc[p][0][0] += lr * tr - li * ti;  acc[p][0][1] += lr * ti + li * tr;
       acc[p][1][0] += lr * pr - li * pi_; acc[p][1][1] += lr * pi_ + li * pr;
     }
   }
-  G* out = pool.contrib + at * (rec.n_pol * 4);
+  V4<G>* out = reinterpret_cast<V4<G>*>(pool.contrib + at * (rec.n_pol * 4));
   for (int p = 0; p < rec.n_pol; ++p) {
-    out[p * 4 + 0] = acc[p][0][0]; out[p * 4 + 1] = acc[p][0][1];
-    out[p * 4 + 2] = acc[p][1][0]; out[p * 4 + 3] = acc[p][1][1];
+    V4<G> v;
+    v.x = acc[p][0][0]; v.y = acc[p][0][1]; v.z = acc[p][1][0]; v.w = acc[p][1][1];
+    out[p] = v;
   }
   pool.key[at] = d.key;
 }
@@ -1154,11 +1193,12 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
   G acc[8], inc[2] = {0, 0};
   for (int i = 0; i < 8; ++i) acc[i] = 0;
   auto add = [&](long at) {
-    const G* c = pool.contrib + at * w;
-    for (int k = 0; k < w; ++k) acc[k] += c[k];
-    for (int p = 0; p < n_pol; ++p)
-      inc[p] += c[4 * p] * c[4 * p] + c[4 * p + 1] * c[4 * p + 1] + c[4 * p + 2] * c[4 * p + 2] +
-                c[4 * p + 3] * c[4 * p + 3];
+    // one polarisation's contribution is 4 values (16 B / 32 B, aligned): vector loads
+    for (int p = 0; p < n_pol; ++p) {
+      const V4<G> c = *reinterpret_cast<const V4<G>*>(pool.contrib + at * w + 4 * p);
+      acc[4 * p] += c.x; acc[4 * p + 1] += c.y; acc[4 * p + 2] += c.z; acc[4 * p + 3] += c.w;
+      inc[p] += c.x * c.x + c.y * c.y + c.z * c.z + c.w * c.w;
+    }
   };
   if (cnt <= NODE_SORT_MAX) {
     for (int h = 0; h < cnt; ++h) {  // insertion into the sorted prefix
