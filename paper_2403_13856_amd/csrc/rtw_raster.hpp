@@ -58,15 +58,17 @@ struct NodeGrid {
 // One ray's emission record for one order, contiguous so that the three
 // vertices of a hit are a few cache lines each (gathered at random).  The
 // exit direction lives in its own array of 4-vectors (Records::dir), read
-// coalesced by the rasteriser's per-quad pass.  The field is transverse to
-// the direction, so it is stored as its two components on the direction's
-// own (e_theta, e_phi) basis (dir_basis of the stored direction): 48 B per
-// record in FP32 instead of 64 B for three Cartesian components.
+// coalesced by the rasteriser's per-quad pass; the record holds a copy, so
+// that the hit store reads one aligned 64 B record (FP32) per vertex.  The
+// field is transverse to the direction, so it is stored as its two
+// components on the direction's own (e_theta, e_phi) basis (dir_basis of the
+// stored direction), which leaves room for the copy.
 template <typename G>
-struct alignas(16) RayRec {
-  G kr[3];  // k r_exit (lab)
-  G f[8];   // [pol][e_theta|e_phi][re|im]: field amp e^{i phase} (J_perp e_perp + J_par e_par)
-  G pad;
+struct alignas(16 * sizeof(G)) RayRec {
+  G kr[3];   // k r_exit (lab)
+  G dir[3];  // the stored exit direction (as in Records::dir)
+  G f[8];    // [pol][e_theta|e_phi][re|im]: field amp e^{i phase} (J_perp e_perp + J_par e_par)
+  G pad[2];
 };
 
 // (e_theta, e_phi) of a direction d (not necessarily of unit length, as
@@ -217,7 +219,8 @@ struct RecordSink {
       r.f[p * 4 + 2] = live ? (G)(br * cre - bi * cim) : (G)0;
       r.f[p * 4 + 3] = live ? (G)(br * cim + bi * cre) : (G)0;
     }
-    r.pad = (G)0;
+    r.dir[0] = dv.x; r.dir[1] = dv.y; r.dir[2] = dv.z;
+    r.pad[0] = r.pad[1] = (G)0;
     rec.rr[at] = r;
     rec.dir[at] = dv;
     const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
@@ -670,7 +673,7 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
   const v3<double> n = node_dir(ng, it, ip);
   for (int k = 0; k < 3; ++k) {
     const RayRec<G>& vr = rec.rr[d.rb + vid[k]];
-    const Dir4<G> dk = rec.dir[d.rb + vid[k]];
+    const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
     // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
     const double psi = (double)vr.kr[0] * ((double)dk.x - n.x) + (double)vr.kr[1] * ((double)dk.y - n.y) +
