@@ -912,30 +912,57 @@ int rtw_surrogate_query(rtw_surrogate* h, int n_query, const float* feats, const
   // set), so each batch is checked against the scratch left after the cell
   // values and split in halves until it fits; one particle always fits, its
   // workspace being at most that of the whole set the scratch was sized for.
+  // A batch whose hit pool overflows is run again with twice the pool per
+  // node where that fits the scratch, else split.
   const size_t avail = scratch_bytes - (size_t)(ws - (char*)scratch);
   const size_t nodes = (size_t)grid->n_theta * grid->n_phi;
-  const rtw_batch_opts bo{0, FALLBACK_HITS_PER_NODE};
-  std::vector<std::pair<int, int>> todo;  // [first, count) ranges of fp
-  if (!fp.empty()) todo.push_back({0, (int)fp.size()});
-  while (!todo.empty()) {
-    const int f0 = todo.back().first, nf = todo.back().second;
-    todo.pop_back();
+  struct Piece {
+    int first, count;
+    double hits_per_node;
+  };
+  std::vector<Piece> todo;  // ranges of fp
+  if (!fp.empty()) todo.push_back({0, (int)fp.size(), FALLBACK_HITS_PER_NODE});
+  auto fits = [&](int f0, int nf, double hpn, size_t* wsb_out) -> int {
+    const rtw_batch_opts b{0, hpn};
     size_t wsb = 0;
-    rc = rtw_batch_workspace_size(nf, fp.data() + f0, fg.data() + f0, inc, opts, grid, &bo, &wsb);
-    if (rc) return mfail(rc, "%s", rtw_last_error());
-    wsb = a256(wsb);
+    const int r = rtw_batch_workspace_size(nf, fp.data() + f0, fg.data() + f0, inc, opts, grid, &b, &wsb);
+    if (r) return -1;
+    *wsb_out = a256(wsb);
     const size_t ffb = a256((size_t)nf * 2 * 2 * nodes * 2 * sizeof(float));
-    if (wsb + ffb + (size_t)nf * 2 * nodes * sizeof(float) > avail) {
+    return *wsb_out + ffb + (size_t)nf * 2 * nodes * sizeof(float) <= avail ? 1 : 0;
+  };
+  while (!todo.empty()) {
+    const Piece pc = todo.back();
+    todo.pop_back();
+    const int f0 = pc.first, nf = pc.count;
+    size_t wsb = 0;
+    const int fit = fits(f0, nf, pc.hits_per_node, &wsb);
+    if (fit < 0) return mfail(RTW_ERR_INVALID_ARG, "%s", rtw_last_error());
+    if (!fit) {
       if (nf == 1) return mfail(RTW_ERR_WORKSPACE, "fallback particle does not fit the query scratch");
-      todo.push_back({f0 + nf / 2, nf - nf / 2});
-      todo.push_back({f0, nf / 2});
+      todo.push_back({f0 + nf / 2, nf - nf / 2, pc.hits_per_node});
+      todo.push_back({f0, nf / 2, pc.hits_per_node});
       continue;
     }
+    const rtw_batch_opts bo{0, pc.hits_per_node};
+    const size_t ffb = a256((size_t)nf * 2 * 2 * nodes * 2 * sizeof(float));
     char* ff = ws + wsb;
     float* incoh = (float*)(ff + ffb);
     rc = rtw_batch(nf, fp.data() + f0, fg.data() + f0, inc, opts, grid, ff, nullptr, incoh, tune, &bo, ws, wsb,
                    hip_stream);
     if (!rc) rc = rtw_farfield_status(ws, hip_stream, nullptr);
+    if (rc == RTW_ERR_WORKSPACE) {  // hit pool overflow: a larger pool, or halves
+      size_t w2 = 0;
+      if (pc.hits_per_node < 1e4 && fits(f0, nf, 2.0 * pc.hits_per_node, &w2) == 1) {
+        todo.push_back({f0, nf, 2.0 * pc.hits_per_node});
+        continue;
+      }
+      if (nf > 1) {
+        todo.push_back({f0 + nf / 2, nf - nf / 2, pc.hits_per_node});
+        todo.push_back({f0, nf / 2, pc.hits_per_node});
+        continue;
+      }
+    }
     if (rc) return mfail(rc, "fallback: %s", rtw_last_error());
     rc = rtw_cell_log_intensity(nf, incoh, 2, grid, cells, cellI + (size_t)f0 * n_cells * 2, hip_stream);
     if (rc) return rc;

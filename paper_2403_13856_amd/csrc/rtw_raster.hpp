@@ -809,12 +809,46 @@ struct WaveStage {
   int hits[HITBUF];      // wave candidate numbers of buffered hits
 };
 
-// Candidate g of the wave: its triangle and node (row it, column ip).
+// Per-block LDS area of the rasteriser: the triangles of the block's 256 quads
+// that have candidates (at most two per quad), shared by its four waves; the
+// queue of triangles to load shares the slot storage.
+constexpr int BLOCK_SLOTS = 512;
 template <typename G>
-__device__ __forceinline__ void locate(const WaveStage<G>& W, int g, Tri<G>& T, int& it, int& ip) {
+struct BlockStage {
+  union {
+    TriSlot<G> tri[BLOCK_SLOTS];
+    TriQueued queued[BLOCK_SLOTS];
+  };
+  int excl[BLOCK_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the block total)
+  int hits[4][HITBUF];    // per-wave buffers of hit candidate numbers
+  int wave_q[4];          // queued triangles of each wave
+};
+
+// What the candidate loop needs of a stage: 2^log_slots slots with their
+// exclusive candidate prefix, and this wave's hit buffer.
+template <typename G>
+struct StageView {
+  const TriSlot<G>* tri;
+  const int* excl;
+  int log_slots;
+  int* hits;
+};
+
+template <typename G>
+__device__ __forceinline__ StageView<G> view(WaveStage<G>& W) {
+  return StageView<G>{W.tri, W.excl, 7, W.hits};
+}
+
+template <typename G>
+__device__ __forceinline__ StageView<G> view(BlockStage<G>& S) {
+  return StageView<G>{S.tri, S.excl, 9, S.hits[threadIdx.x >> 6]};
+}
+
+// Candidate g of the stage: its triangle and node (row it, column ip).
+template <typename G>
+__device__ __forceinline__ void locate(const StageView<G>& W, int g, Tri<G>& T, int& it, int& ip) {
   int L = 0;  // last slot whose prefix is <= g
-#pragma unroll
-  for (int step = WAVE_SLOTS / 2; step > 0; step >>= 1)
+  for (int step = 1 << (W.log_slots - 1); step > 0; step >>= 1)
     if (W.excl[L + step] <= g) L += step;
   const int c = g - W.excl[L];
   const TriSlot<G>& S = W.tri[L];
@@ -834,7 +868,7 @@ __device__ __forceinline__ void locate(const WaveStage<G>& W, int g, Tri<G>& T, 
 // k_store_hits computes the contributions.
 template <typename G>
 __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
-                           const WaveStage<G>& W, int nh, int part) {
+                           const StageView<G>& W, int nh, int part) {
   const int lane = threadIdx.x & 63;
   unsigned first = 0;
   if (lane == 0) first = atomicAdd(&pool.counter[part], (unsigned)nh);
@@ -864,23 +898,25 @@ __device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitP
   }
 }
 
-// Test every staged candidate of the wave, 64 at a time: candidate g of the
-// wave goes to lane g mod 64 whatever triangle owns it, so one large triangle
-// costs its size / 64 iterations instead of its size.  Hits are buffered in
-// LDS and stored in batches, so the membership loop never waits on an atomic.
-// The lanes must have written their slots and the prefix of all WAVE_SLOTS
-// slots before the call, and the block must have passed a barrier since.
+// Test every staged candidate, 64 per wave at a time: candidate g goes to a
+// lane whatever triangle owns it, so one large triangle costs its size / 64
+// iterations instead of its size.  Wave w of a group of n_waves takes g =
+// base + 64 w + lane for base = 0, 64 n_waves, ...  Hits are buffered in the
+// wave's LDS buffer and stored in batches, so the membership loop never
+// waits on an atomic.  The slots and the prefix must be written, and a
+// barrier passed, before the call; the loop bound is uniform over the group.
 template <typename G>
 __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
-                             WaveStage<G>& W, int wave_total, int part) {
+                             const StageView<G>& W, int total, int wave_in_group, int n_waves, int part) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
   int nh = 0;      // buffered hits (wave-uniform)
   int flushes = 0; // successive batches go to different pool partitions (97 is odd: every partition is reached)
-  for (int base = 0; base < wave_total; base += 64) {
-    const int g = base + lane;
+  const int stride = 64 * n_waves;
+  for (int base = 0; base < total; base += stride) {
+    const int g = base + 64 * wave_in_group + lane;
     bool hit = false;
-    if (g < wave_total) {
+    if (g < total) {
       Tri<G> T;
       int it, ip;
       locate(W, g, T, it, ip);
@@ -890,7 +926,7 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
     const unsigned long long mask = __ballot(hit);
     if (hit) W.hits[nh + __popcll(mask & below)] = g;
     nh += __popcll(mask);
-    if (nh > HITBUF - 64 || (base + 64 >= wave_total && nh > 0)) {
+    if (nh > HITBUF - 64 || (base + stride >= total && nh > 0)) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -915,16 +951,35 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
   return incl - v;
 }
 
+// Exclusive block prefix of v (256 threads); *total receives the block's sum.
+// lds: 4 ints of scratch; the call holds two block barriers.
+__device__ __forceinline__ int block_excl_scan(int v, int* total, int* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int wt;
+  const int ex = wave_excl_scan(v, &wt);
+  if (lane == 0) lds[wave] = wt;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) before += lds[w];
+    all += lds[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + ex;
+}
+
 // One thread per (order slot, quad) of the chunk: blockIdx.y is the slot,
 // blockIdx.x * 256 + threadIdx.x the chunk quad.  Triangles whose bounding box
-// holds at most cand_inline nodes are staged for the wave's flattened
-// candidate loop; larger ones are listed row by row for k_raster_rows.
+// holds at most cand_inline nodes are staged for the block's flattened
+// candidate loop (queue, slots and candidates shared by the block's four
+// waves, so that sparse work fills whole waves); larger ones are listed row
+// by row for k_raster_rows.
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<G> rec, const NodeGrid ng,
                                                 const HitPool<G> pool, const double margin, const int cand_inline) {
-  __shared__ WaveStage<G> stage[4];
+  __shared__ BlockStage<G> S;
   __shared__ int s_p0;
-  WaveStage<G>& W = stage[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const int slot = blockIdx.y;
   const long n_quads = B.quad_off[B.n] - B.quad_base;
@@ -968,40 +1023,44 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
       }
     }
   }
+  // block-wide queue: wave w's entries follow those of waves < w
+  const int wave = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
   const unsigned long long q0 = __ballot(need0), q1 = __ballot(need1);
-  const int nq0 = __popcll(q0), nq = nq0 + __popcll(q1);
+  const int nq0 = __popcll(q0), nqw = nq0 + __popcll(q1);
+  if (lane == 0) S.wave_q[wave] = nqw;
+  __syncthreads();
+  int qbase = 0, nq = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    qbase += w < wave ? S.wave_q[w] : 0;
+    nq += S.wave_q[w];
+  }
   auto enqueue = [&](int at, int t, bool fast, const Cand& c) {
-    TriQueued& e = W.queued[at];
+    TriQueued& e = S.queued[at];
     e.quad = (int)quad; e.part = p; e.tf = t | (fast ? 2 : 0);
     e.i0 = c.i0; e.i1 = c.i1; e.ja0 = c.ja0; e.ja1 = c.ja1; e.jb0 = c.jb0; e.jb1 = c.jb1;
   };
-  if (need0) enqueue(__popcll(q0 & below), 0, fast0, c0);
-  if (need1) enqueue(nq0 + __popcll(q1 & below), 1, fast1, c1);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (need0) enqueue(qbase + __popcll(q0 & below), 0, fast0, c0);
+  if (need1) enqueue(qbase + nq0 + __popcll(q1 & below), 1, fast1, c1);
+  __syncthreads();
 
-  // Phase two, 64 queued triangles at a time: directions and orientation, the
-  // direction box where the angle box did not apply; boxes of at most
-  // cand_inline nodes are staged in slot k, larger ones listed by row.  The
-  // queue shares the slots' storage with a different element size, so every
-  // entry is read into registers before the first slot is written.
+  // Phase two, 256 queued triangles at a time over the block: directions and
+  // orientation, the direction box where the angle box did not apply; boxes
+  // of at most cand_inline nodes are staged in slot k, larger ones listed by
+  // row.  The queue shares the slots' storage with a different element size,
+  // so every entry is read into registers before the first slot is written.
   TriQueued mine[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
-    if (64 * h + lane < nq) mine[h] = W.queued[64 * h + lane];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  int wave_total = 0;
+    if (256 * h + (int)threadIdx.x < nq) mine[h] = S.queued[256 * h + threadIdx.x];
+  __syncthreads();
+  int block_total = 0;
+  const int n_iter = nq > 256 ? 2 : 1;  // block-uniform
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int k = 64 * h + lane;
-    if (64 * h >= nq) {  // wave-uniform: no more queued triangles
-      W.excl[k] = wave_total;
-      continue;
-    }
+    if (h >= n_iter) break;
+    const int k = 256 * h + (int)threadIdx.x;
     Tri<G> T;
     Cand c;
     int n = 0, r = 0;
@@ -1041,13 +1100,14 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
       }
       if (!fits && r > 0) n = c.count();  // list full: rasterise the whole box here (slow but exact)
     }
-    if (n > 0) slot_put(W.tri[k], T, c);
+    if (n > 0) slot_put(S.tri[k], T, c);
     int it_total;
-    W.excl[k] = wave_total + wave_excl_scan(n, &it_total);
-    wave_total += it_total;
+    S.excl[k] = block_total + block_excl_scan(n, &it_total, S.wave_q);
+    block_total += it_total;
   }
+  if (n_iter == 1) S.excl[256 + threadIdx.x] = block_total;
   __syncthreads();
-  raster_drain(rec, ng, pool, W, wave_total, wave_partition());
+  raster_drain(rec, ng, pool, view(S), block_total, wave, 4, wave_partition());
 }
 
 // One thread per listed (triangle, theta row); the block walks the list in
@@ -1109,7 +1169,7 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
     W.excl[lane] = wave_excl_scan(n, &wave_total);
     W.excl[64 + lane] = wave_total;
     __syncthreads();
-    raster_drain(rec, ng, pool, W, wave_total, part);
+    raster_drain(rec, ng, pool, view(W), wave_total, 0, 1, part);
     __syncthreads();  // the stage is rewritten by the next block of items
   }
 }
@@ -1119,21 +1179,6 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_BLOCK = 256 * SCAN_PER_THREAD;
 
-__device__ __forceinline__ int block_excl_scan(int v, int* total, int* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int wt;
-  const int ex = wave_excl_scan(v, &wt);
-  if (lane == 0) lds[wave] = wt;
-  __syncthreads();
-  int before = 0, all = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    if (w < wave) before += lds[w];
-    all += lds[w];
-  }
-  __syncthreads();
-  *total = all;
-  return before + ex;
-}
 
 __global__ void __launch_bounds__(256) k_scan_local(const int* count, long n, int* out, int* bsum) {
   __shared__ int lds[4];
