@@ -281,6 +281,39 @@ __host__ __device__ __forceinline__ int seg_upper(const AxisSeg* sg, const doubl
   return n;
 }
 
+// One uniformly spaced axis (a single run) in FP32 registers: the index of the
+// first node >= x is ceil((x - v0) / step), of the last node <= x plus one
+// floor((x - v0) / step) + 1, clamped to [0, n].  FP32 misplaces a bound by
+// at most ~4e-7 rad on the finest grids used here (0.02 deg), a tenth of the
+// box margin, so a node it adds or drops lies outside the triangle anyway;
+// 1e-3 index units of slack are added on both sides regardless.
+struct AxisFast {
+  int uni;  // the axis is one uniform run (else the segment tables are used)
+  int n;
+  float v0, inv_step;
+};
+
+__device__ __forceinline__ AxisFast axis_fast(const AxisSeg* sg, int n) {
+  AxisFast a;
+  a.uni = sg->nseg == 1 && sg->start[0] == 0 && sg->end[0] == n - 1;
+  a.n = n;
+  a.v0 = (float)sg->v0[0];
+  a.inv_step = (float)sg->inv_step[0];
+  return a;
+}
+
+__device__ __forceinline__ int fast_lower(const AxisFast& a, float x) {
+  const float f = (x - a.v0) * a.inv_step;
+  const int i = f <= 0.0f ? 0 : (int)ceilf(f - 1e-3f);
+  return min(i, a.n);
+}
+
+__device__ __forceinline__ int fast_upper(const AxisFast& a, float x) {
+  const float f = (x - a.v0) * a.inv_step;
+  const int i = f < 0.0f ? 0 : (int)floorf(f + 1e-3f) + 1;
+  return min(i, a.n);
+}
+
 // Candidate node set of one triangle: rows [i0, i1) x (phi segment a  U  segment b).
 struct Cand {
   int i0, i1, ja0, ja1, jb0, jb1;
@@ -483,7 +516,8 @@ __device__ inline Cand box_cand(const NodeGrid& ng, const Box& bx) {
 //     1e-3 rad;
 //   - longitude is monotonic along pole-free arcs: the phi extent is the
 //     shortest circular interval holding the three vertex longitudes.
-__device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c, float margin, Cand& cd) {
+__device__ inline bool fast_box(const NodeGrid& ng, const AxisFast& at, const AxisFast& ap, float2 a, float2 b,
+                                float2 c, float margin, Cand& cd) {
   const float PI_F = 3.14159265f, TWO_PI_F = 6.2831853f;
   const float tmin = fminf(a.x, fminf(b.x, c.x)), tmax = fmaxf(a.x, fmaxf(b.x, c.x));
   const float s_hi = fminf(1.0f, fminf(tmax, PI_F - tmin));
@@ -503,8 +537,13 @@ __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c
   const float m = margin + 2e-6f;
   const float tlo = tmin - m - bulge, thi = tmax + m + bulge;
   cd.ja0 = cd.ja1 = cd.jb0 = cd.jb1 = 0;
-  cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
-  cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
+  if (at.uni) {
+    cd.i0 = fast_lower(at, tlo);
+    cd.i1 = fast_upper(at, thi);
+  } else {
+    cd.i0 = seg_lower(ng.seg_t, ng.th, ng.n_theta, (double)tlo);
+    cd.i1 = seg_upper(ng.seg_t, ng.th, ng.n_theta, (double)thi);
+  }
   if (cd.i1 <= cd.i0) return true;  // no node row crosses the triangle: nothing else to do
   float a0 = a.y, a1 = b.y, a2 = c.y, t;
   if (a0 > a1) { t = a0; a0 = a1; a1 = t; }
@@ -521,12 +560,14 @@ __device__ inline bool fast_box(const NodeGrid& ng, float2 a, float2 b, float2 c
   const double lo = (double)lo_f - (double)pm, hi = (double)hi_f + (double)pm;
   if (hi - lo >= TWO_PI) return false;
   const double plo = lo < 0.0 ? lo + TWO_PI : lo, phi = plo + (hi - lo);
+  auto lower = [&](double x) { return ap.uni ? fast_lower(ap, (float)x) : seg_lower(ng.seg_p, ng.ph, ng.n_phi, x); };
+  auto upper = [&](double x) { return ap.uni ? fast_upper(ap, (float)x) : seg_upper(ng.seg_p, ng.ph, ng.n_phi, x); };
   if (phi < TWO_PI) {
-    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo);
-    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi);
+    cd.ja0 = lower(plo);
+    cd.ja1 = upper(phi);
   } else {
-    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo); cd.ja1 = ng.n_phi;
-    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi - TWO_PI);
+    cd.ja0 = lower(plo); cd.ja1 = ng.n_phi;
+    cd.jb0 = 0; cd.jb1 = upper(phi - TWO_PI);
   }
   return true;
 }
@@ -985,6 +1026,7 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
   const long n_quads = B.quad_off[B.n] - B.quad_base;
   const long gq0 = (long)blockIdx.x * blockDim.x;
   if (threadIdx.x == 0) s_p0 = find_part(B.quad_off, B.n, B.quad_base, gq0);
+  const AxisFast axt = axis_fast(ng.seg_t, ng.n_theta), axp = axis_fast(ng.seg_p, ng.n_phi);
   __syncthreads();
   const long gq = gq0 + threadIdx.x;
 
@@ -1014,11 +1056,11 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
       const float2* an = rec.ang + rb;
       const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + N], a11 = an[v00 + N + 1];
       if (tv0) {
-        fast0 = fast_box(ng, a00, a01, a11, (float)margin, c0);
+        fast0 = fast_box(ng, axt, axp, a00, a01, a11, (float)margin, c0);
         need0 = !fast0 || c0.count() > 0;
       }
       if (tv1) {
-        fast1 = fast_box(ng, a00, a11, a10, (float)margin, c1);
+        fast1 = fast_box(ng, axt, axp, a00, a11, a10, (float)margin, c1);
         need1 = !fast1 || c1.count() > 0;
       }
     }
