@@ -838,7 +838,6 @@ struct TriQueued {
 // Per-wave LDS area of the flattened loop: up to 128 staged triangles (two per
 // lane's quad at most).  The queue of triangles to load shares the slot
 // storage: entry k is read by the lane that then writes slot k.
-constexpr int HITBUF = 128;  // node hits buffered per wave before their pool slots are taken
 constexpr int WAVE_SLOTS = 128;
 template <typename G>
 struct WaveStage {
@@ -847,7 +846,6 @@ struct WaveStage {
     TriQueued queued[WAVE_SLOTS];
   };
   int excl[WAVE_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the wave total)
-  int hits[HITBUF];      // wave candidate numbers of buffered hits
 };
 
 // Per-block LDS area of the rasteriser: the triangles of the block's 256 quads
@@ -861,28 +859,26 @@ struct BlockStage {
     TriQueued queued[BLOCK_SLOTS];
   };
   int excl[BLOCK_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the block total)
-  int hits[4][HITBUF];    // per-wave buffers of hit candidate numbers
   int wave_q[4];          // queued triangles of each wave
 };
 
 // What the candidate loop needs of a stage: 2^log_slots slots with their
-// exclusive candidate prefix, and this wave's hit buffer.
+// exclusive candidate prefix.
 template <typename G>
 struct StageView {
   const TriSlot<G>* tri;
   const int* excl;
   int log_slots;
-  int* hits;
 };
 
 template <typename G>
 __device__ __forceinline__ StageView<G> view(WaveStage<G>& W) {
-  return StageView<G>{W.tri, W.excl, 7, W.hits};
+  return StageView<G>{W.tri, W.excl, 7};
 }
 
 template <typename G>
 __device__ __forceinline__ StageView<G> view(BlockStage<G>& S) {
-  return StageView<G>{S.tri, S.excl, 9, S.hits[threadIdx.x >> 6]};
+  return StageView<G>{S.tri, S.excl, 9};
 }
 
 // Candidate g of the stage: its triangle and node (row it, column ip).
@@ -904,77 +900,54 @@ __device__ __forceinline__ void locate(const StageView<G>& W, int g, Tri<G>& T, 
   slot_get(S, T);
 }
 
-// Take pool slots for the nh buffered hits with one atomic, then write each
-// hit's descriptor (its membership weights are recomputed, bit for bit);
-// k_store_hits computes the contributions.
-template <typename G>
-__device__ void flush_hits(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
-                           const StageView<G>& W, int nh, int part) {
-  const int lane = threadIdx.x & 63;
-  unsigned first = 0;
-  if (lane == 0) first = atomicAdd(&pool.counter[part], (unsigned)nh);
-  first = __shfl(first, 0);
-  for (int h0 = 0; h0 < nh; h0 += 64) {
-    const int h = h0 + lane;
-    if (h < nh) {
-      Tri<G> T;
-      int it, ip;
-      locate(W, W.hits[h], T, it, ip);
-      G lam[3];
-      tri_member(T, node_dir_g<G>(ng, it, ip), lam);
-      const unsigned pos = first + (unsigned)h;
-      if (pos < (unsigned)pool.cap_part) {  // beyond: overflow, reported by the status call
-        HitDesc<G> d;
-        d.key = T.key;
-        d.rb = (int)T.rb;
-        d.v00 = (int)T.vid[0];
-        d.nt = (T.N << 1) | (T.vid[1] == T.vid[0] + 1 ? 0 : 1);
-        d.itip = it | (ip << 16);
-        d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
-        d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
-        pool.desc[(long)part * pool.cap_part + pos] = d;
-        atomicAdd(&pool.count[d.node], 1);
-      }
-    }
-  }
-}
-
 // Test every staged candidate, 64 per wave at a time: candidate g goes to a
 // lane whatever triangle owns it, so one large triangle costs its size / 64
 // iterations instead of its size.  Wave w of a group of n_waves takes g =
-// base + 64 w + lane for base = 0, 64 n_waves, ...  Hits are buffered in the
-// wave's LDS buffer and stored in batches, so the membership loop never
-// waits on an atomic.  The slots and the prefix must be written, and a
-// barrier passed, before the call; the loop bound is uniform over the group.
+// base + 64 w + lane for base = 0, 64 n_waves, ...  The hits of one pass take
+// their pool slots with one atomic and are written from registers: a
+// descriptor each (triangle, node, barycentric weights; k_store_hits computes
+// the contributions) and one count for the node.  Successive passes of a
+// wave go to different pool partitions (97 is odd: every partition is
+// reached).  The slots and the prefix must be written, and a barrier passed,
+// before the call; the loop bound is uniform over the group.
 template <typename G>
 __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
                              const StageView<G>& W, int total, int wave_in_group, int n_waves, int part) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
-  int nh = 0;      // buffered hits (wave-uniform)
-  int flushes = 0; // successive batches go to different pool partitions (97 is odd: every partition is reached)
+  int flushes = 0;
   const int stride = 64 * n_waves;
   for (int base = 0; base < total; base += stride) {
     const int g = base + 64 * wave_in_group + lane;
     bool hit = false;
+    Tri<G> T;
+    int it = 0, ip = 0;
+    G lam[3];
     if (g < total) {
-      Tri<G> T;
-      int it, ip;
       locate(W, g, T, it, ip);
-      G lam[3];
       hit = tri_member(T, node_dir_g<G>(ng, it, ip), lam);
     }
     const unsigned long long mask = __ballot(hit);
-    if (hit) W.hits[nh + __popcll(mask & below)] = g;
-    nh += __popcll(mask);
-    if (nh > HITBUF - 64 || (base + stride >= total && nh > 0)) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      flush_hits(rec, ng, pool, W, nh, (part + 97 * flushes) % NPART);
-      ++flushes;
-      nh = 0;
-      __builtin_amdgcn_wave_barrier();
+    if (mask == 0ull) continue;  // wave-uniform
+    const int pt = (part + 97 * flushes) % NPART;
+    ++flushes;
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned first = 0;
+    if (lane == leader) first = atomicAdd(&pool.counter[pt], (unsigned)__popcll(mask));
+    first = __shfl(first, leader);
+    if (!hit) continue;
+    const unsigned pos = first + (unsigned)__popcll(mask & below);
+    if (pos < (unsigned)pool.cap_part) {  // beyond: overflow, reported by the status call
+      HitDesc<G> d;
+      d.key = T.key;
+      d.rb = (int)T.rb;
+      d.v00 = (int)T.vid[0];
+      d.nt = (T.N << 1) | (T.vid[1] == T.vid[0] + 1 ? 0 : 1);
+      d.itip = it | (ip << 16);
+      d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
+      d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
+      pool.desc[(long)pt * pool.cap_part + pos] = d;
+      atomicAdd(&pool.count[d.node], 1);
     }
   }
 }

@@ -230,11 +230,15 @@ def test_farfield_edge_cases(oracle, R):
 
 def test_workspace_overflow_is_reported_and_recovered(oracle, R):
     w = I.sphere_fp64()
-    say("[overflow] sphere N=128 with a deliberately small hit pool")
+    # a 0.25 deg node grid (1 M nodes, 1.7 M hits) against the smallest pool
+    # (256 slots in each of the 1024 partitions): the pool must overflow
+    th = I.uniform_angles(0.0, 180.0, 0.25)
+    ph = I.uniform_angles(0.0, 359.75, 0.25)
+    say(f"[overflow] sphere N=128, {th.size}x{ph.size} nodes, with a deliberately small hit pool")
     gp = R.make_particle(w.semi_axes, w.euler_deg, w.m)
     gi = R.make_incident(w.wavelength, 1)
     go = R.make_opts(0, 2, 128, R.FP64)
-    ff = R.FarField(gp, gi, go, w.theta_deg, w.phi_deg, hits_per_node=0.01)
+    ff = R.FarField(gp, gi, go, th, ph, hits_per_node=0.01)
     small = ff.ws_bytes
     ff.launch()
     rc, need = ff.status()
@@ -242,5 +246,5 @@ def test_workspace_overflow_is_reported_and_recovered(oracle, R):
     F = ff().cpu().numpy()  # grows the workspace and re-runs
     assert ff.ws_bytes >= need
     op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
-    ref = oracle.farfield(op, oracle.setup(w.wavelength, 1, 0, 2, 128), w.theta_deg, w.phi_deg)
+    ref = oracle.farfield(op, oracle.setup(w.wavelength, 1, 0, 2, 128), th, ph)
     _compare_fp64(ref, F, ff.ncontrib.cpu().numpy())
