@@ -149,13 +149,14 @@ struct HitDesc {
   int nt;     // N << 1 | t
   int itip;   // node row | node column << 16
   int node;   // node index within the chunk (particle-major)
+  int rank;   // place among the node's hits (taken with the node's count)
   G lam[3];
 };
 
 template <typename G>
 struct HitPool {
   int* count;         // [n_nodes] hits of each node (counted by the rasterisers)
-  int* cursor;        // [n_nodes] exclusive prefix of count, advanced by k_store_hits to the node's end
+  int* cursor;        // [n_nodes] exclusive prefix of count: the start of each node's range
   int* key;           // [cap] triangle key of each stored contribution (node-major order)
   G* contrib;         // [cap][n_pol * 4]: (pol, theta|phi, re|im), node-major order
   HitDesc<G>* desc;   // [cap] hits found, stored by k_store_hits
@@ -694,13 +695,14 @@ __device__ __forceinline__ v3<float> node_dir_g<float>(const NodeGrid& ng, int i
   return mk3<float>(st * ng.cphf[ip], st * ng.sphf[ip], ng.cthf[it]);
 }
 
-// Contribution of the hit in pool slot idx (its descriptor), stored at the
-// next free place of its node's range (node-major order).  The place is taken
-// first so that the atomic's latency overlaps the record gathers.
+// Contribution of the hit in pool slot idx (its descriptor), stored at its
+// place in its node's range (node-major order): the range start from the
+// scan plus the rank the rasteriser took with the node's count, so this
+// kernel needs no atomic.
 template <typename G>
 __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, long idx) {
   const HitDesc<G> d = pool.desc[idx];
-  const long at = atomicAdd(&pool.cursor[d.node], 1);
+  const long at = (long)pool.cursor[d.node] + d.rank;
   const int it = d.itip & 0xffff, ip = (int)((unsigned)d.itip >> 16);
   const int N = d.nt >> 1, t = d.nt & 1;
   const long v00 = d.v00;
@@ -945,9 +947,9 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
       d.nt = (T.N << 1) | (T.vid[1] == T.vid[0] + 1 ? 0 : 1);
       d.itip = it | (ip << 16);
       d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
+      d.rank = atomicAdd(&pool.count[d.node], 1);
       d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
       pool.desc[(long)pt * pool.cap_part + pos] = d;
-      atomicAdd(&pool.count[d.node], 1);
     }
   }
 }
@@ -1250,7 +1252,7 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
   const int node = (int)(gn - (long)pl * n_nodes);
   const long ob = (long)B.out_index[pl];
   const int cnt = pool.count[gn];
-  const long s0 = (long)pool.cursor[gn] - cnt;
+  const long s0 = (long)pool.cursor[gn];
   int keys[NODE_SORT_MAX], idxs[NODE_SORT_MAX];
   const int w = n_pol * 4;
   G acc[8], inc[2] = {0, 0};
