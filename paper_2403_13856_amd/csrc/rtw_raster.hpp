@@ -529,11 +529,13 @@ __device__ inline bool fast_box(const NodeGrid& ng, const AxisFast& at, const Ax
   };
   const float q = 1.1f * fmaxf(e2(a, b), fmaxf(e2(b, c), e2(c, a)));
   if (!(q < 1e-2f)) return false;
-  const float l = sqrtf(q);
+  // bounds only: the hardware square root and reciprocal (1 ulp) with a
+  // 1e-4 relative allowance in the safe direction
+  const float l = __builtin_amdgcn_sqrtf(q) * 1.0001f;
   const float pole_gap = fminf(tmin, PI_F - tmax) - l;  // lower bound of the pole distance of any point
   if (!(pole_gap > 2.0f * margin + 1e-3f)) return false;
   const float s_lo = 0.63661977f * pole_gap;  // sin x >= 2x / pi on [0, pi/2]
-  const float bulge = 0.132f * q / s_lo;
+  const float bulge = 0.132f * q * __builtin_amdgcn_rcpf(s_lo) * 1.0001f;
   if (!(bulge <= 1e-3f)) return false;
   const float m = margin + 2e-6f;
   const float tlo = tmin - m - bulge, thi = tmax + m + bulge;
@@ -556,19 +558,30 @@ __device__ inline bool fast_box(const NodeGrid& ng, const AxisFast& at, const Ax
   else if (g01 >= g12) { lo_f = a1; hi_f = a0 + TWO_PI_F; }
   else { lo_f = a2; hi_f = a1 + TWO_PI_F; }
   // phi margin: m / sin(theta) over the box, with sin bounded below by 2 theta / pi
-  const float pm = m * __frcp_rn(0.63661977f * fminf(tlo, PI_F - thi)) * 1.0001f + 1e-6f;
+  const float pm = m * __builtin_amdgcn_rcpf(0.63661977f * fminf(tlo, PI_F - thi)) * 1.0002f + 1e-6f;
+  if (ap.uni) {  // FP32 throughout: its ~5e-7 rad error is a fraction of the margin
+    const float lo = lo_f - pm, hi = hi_f + pm;
+    if (hi - lo >= TWO_PI_F) return false;
+    const float plo = lo < 0.0f ? lo + TWO_PI_F : lo, phi = plo + (hi - lo);
+    cd.ja0 = fast_lower(ap, plo);
+    if (phi < TWO_PI_F) {
+      cd.ja1 = fast_upper(ap, phi);
+    } else {
+      cd.ja1 = ng.n_phi;
+      cd.jb0 = 0; cd.jb1 = fast_upper(ap, phi - TWO_PI_F);
+    }
+    return true;
+  }
   const double TWO_PI = 6.283185307179586;
   const double lo = (double)lo_f - (double)pm, hi = (double)hi_f + (double)pm;
   if (hi - lo >= TWO_PI) return false;
   const double plo = lo < 0.0 ? lo + TWO_PI : lo, phi = plo + (hi - lo);
-  auto lower = [&](double x) { return ap.uni ? fast_lower(ap, (float)x) : seg_lower(ng.seg_p, ng.ph, ng.n_phi, x); };
-  auto upper = [&](double x) { return ap.uni ? fast_upper(ap, (float)x) : seg_upper(ng.seg_p, ng.ph, ng.n_phi, x); };
   if (phi < TWO_PI) {
-    cd.ja0 = lower(plo);
-    cd.ja1 = upper(phi);
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo);
+    cd.ja1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi);
   } else {
-    cd.ja0 = lower(plo); cd.ja1 = ng.n_phi;
-    cd.jb0 = 0; cd.jb1 = upper(phi - TWO_PI);
+    cd.ja0 = seg_lower(ng.seg_p, ng.ph, ng.n_phi, plo); cd.ja1 = ng.n_phi;
+    cd.jb0 = 0; cd.jb1 = seg_upper(ng.seg_p, ng.ph, ng.n_phi, phi - TWO_PI);
   }
   return true;
 }
