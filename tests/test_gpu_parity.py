@@ -248,3 +248,31 @@ def test_workspace_overflow_is_reported_and_recovered(oracle, R):
     op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
     ref = oracle.farfield(op, oracle.setup(w.wavelength, 1, 0, 2, 128), th, ph)
     _compare_fp64(ref, F, ff.ncontrib.cpu().numpy())
+
+
+def test_uniform_axis_boxes_match_segment_tables(R):
+    # Boxes on a uniform node axis use FP32 index arithmetic, on any other axis
+    # the segment tables; boxes only prune, so adding one off-grid node (which
+    # makes the axis non-uniform) must leave every shared node bitwise alike.
+    w = I.ellipsoid_mixed()
+    th_u = I.uniform_angles(0.0, 180.0, 0.25)
+    ph_u = I.uniform_angles(0.0, 359.0, 1.0)
+    for prec in (R.MIXED, R.FP64):
+        gp = R.make_particle(w.semi_axes, w.euler_deg, w.m)
+        gi = R.make_incident(w.wavelength, 2)
+        go = R.make_opts(0, 3, 512, prec)
+        F_u, nc_u, _ = _farfield_gpu(R, gp, gi, go, th_u, ph_u)
+        for axis in ("theta", "phi"):
+            th, ph = th_u, ph_u
+            if axis == "theta":
+                th = np.sort(np.append(th_u, 33.3))
+            else:
+                ph = np.sort(np.append(ph_u, 200.5))
+            F, nc, _ = _farfield_gpu(R, gp, gi, go, th, ph)
+            it = np.searchsorted(th, th_u)
+            ip = np.searchsorted(ph, ph_u)
+            assert np.array_equal(th[it], th_u) and np.array_equal(ph[ip], ph_u)
+            say(f"[uniform axis] precision={prec} extra node on {axis}: "
+                f"{int(nc_u.sum())} contributions on the uniform grid")
+            assert np.array_equal(nc[np.ix_(it, ip)], nc_u)
+            assert np.array_equal(F[:, :, it][:, :, :, ip], F_u)
