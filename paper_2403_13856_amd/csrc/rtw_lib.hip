@@ -332,10 +332,10 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
   }
 }
 
-// Reset of the per-chunk state: node lists and per-chunk counters.
-__global__ void k_chunk_reset(int* count, long n_heads, unsigned* counter) {
+// Reset of the per-chunk state: node hit counts and per-chunk counters.
+__global__ void k_chunk_reset(int* count, long n_nodes_chunk, unsigned* counter) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_heads) count[i] = 0;
+  if (i < n_nodes_chunk) count[i] = 0;
   if (i <= C_QUEUE) counter[i] = 0u;
 }
 
@@ -703,9 +703,9 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     const long rays = pl.ray_off[c1] - pl.ray_off[c0];
     const long quads = pl.quad_off[c1] - pl.quad_off[c0];
     const long items = pl.tile_off[c1] - pl.tile_off[c0];
-    const long n_heads = (long)nc * n_nodes;
-    hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_heads, C_COUNT) + 255) / 256)), dim3(256),
-                       0, st, pool.count, n_heads, counter);
+    const long n_cnodes = (long)nc * n_nodes;
+    hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_cnodes, C_COUNT) + 255) / 256)), dim3(256),
+                       0, st, pool.count, n_cnodes, counter);
     { ProfScope ps(fp64 ? "k_trace_fp64" : "k_trace_mixed", st);
     const long grid_t = std::min<long>(items, (long)cu * tu.blocks_per_cu);
     hipLaunchKernelGGL(k_trace_tiles<G>, dim3((unsigned)grid_t), dim3(256), 0, st, B, rec, counter + C_QUEUE); }
@@ -720,16 +720,16 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     { ProfScope ps(fp64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
     hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
     { ProfScope ps("k_scan", st);
-    const long nsb = (n_heads + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const long nsb = (n_cnodes + SCAN_BLOCK - 1) / SCAN_BLOCK;
     int* bsum = (int*)(ws + L.bsum);
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_heads, pool.cursor, bsum);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_cnodes, pool.cursor, bsum);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_heads, bsum); }
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_cnodes, bsum); }
     { ProfScope ps(fp64 ? "k_store_hits_fp64" : "k_store_hits_mixed", st);
     const long slots = (long)NPART * cap_part;
     hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, rec, ng, pool); }
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
-    hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_heads + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
+    hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
                        S.n_pol, (G*)out, ncontrib, (G*)incoh); }
     hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter);
   }

@@ -362,7 +362,7 @@ struct Tri {
   int orient;   // sign of the triple product of the directions
   v3<G> m[3];   // canonical edge normals d_lo x d_hi of the edges opposite each vertex
   long rb;      // record index of (particle, order slot, ray 0)
-  int part;     // particle within the chunk (selects its node lists)
+  int part;     // particle within the chunk (selects its nodes)
   int N;        // rays per side of the particle
   int key;      // 2 (n_ord quad_off + slot (N-1)^2 + quad) + t: the per-node summation order
 };
@@ -773,28 +773,12 @@ __global__ void __launch_bounds__(256) k_store_hits(const Records<G> rec, const 
   store_hit(rec, ng, pool, i);
 }
 
-// Wave-aggregated append: every lane with hit == true receives a pool slot
-// (or -1 on overflow).  Must be called in wave-uniform control flow.
-__device__ inline long wave_reserve(bool hit, unsigned* counter, int part, int cap_part) {
-  const int lane = threadIdx.x & 63;
-  unsigned long long mask = __ballot(hit);
-  if (mask == 0ull) return -1;
-  int leader = __ffsll((long long)mask) - 1;
-  unsigned base = 0;
-  if (lane == leader) base = atomicAdd(&counter[part], (unsigned)__popcll(mask));
-  base = __shfl(base, leader);
-  if (!hit) return -1;
-  unsigned pos = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-  if (pos >= (unsigned)cap_part) return -1;  // overflow: counted, reported by the status call
-  return (long)part * cap_part + pos;
-}
-
 __device__ inline int wave_partition() {
   return (int)(((long)blockIdx.y * gridDim.x * (blockDim.x >> 6) + (long)blockIdx.x * (blockDim.x >> 6) +
                 (threadIdx.x >> 6)) % NPART);
 }
 
-// A triangle staged in LDS for the wave's flattened candidate loop (64 bytes
+// A triangle staged in LDS for the flattened candidate loop (64 bytes
 // in the mixed path).  Node-grid sides and chunk particle counts are below
 // 2^16 (checked on the host), so index pairs share a word.
 template <typename G>
@@ -843,24 +827,19 @@ __device__ __forceinline__ void slot_get(const TriSlot<G>& S, Tri<G>& T) {
   for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
 }
 
-// A triangle of the wave that needs its directions loaded: its quad, particle,
+// A triangle of the block that needs its directions loaded: its quad, particle,
 // half (bit 0), whether the vertex-angle box applies (bit 1) and that box.
 struct TriQueued {
   int quad, part, tf;
   int i0, i1, ja0, ja1, jb0, jb1;
 };
 
-// Per-wave LDS area of the flattened loop: up to 128 staged triangles (two per
-// lane's quad at most).  The queue of triangles to load shares the slot
-// storage: entry k is read by the lane that then writes slot k.
-constexpr int WAVE_SLOTS = 128;
+// Per-wave LDS area of the row kernel: one staged (triangle, row) per lane.
+constexpr int WAVE_SLOTS = 64;
 template <typename G>
 struct WaveStage {
-  union {
-    TriSlot<G> tri[WAVE_SLOTS];
-    TriQueued queued[WAVE_SLOTS];
-  };
-  int excl[WAVE_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the wave total)
+  TriSlot<G> tri[WAVE_SLOTS];
+  int excl[WAVE_SLOTS];  // exclusive prefix of the slots' candidate counts
 };
 
 // Per-block LDS area of the rasteriser: the triangles of the block's 256 quads
@@ -888,7 +867,7 @@ struct StageView {
 
 template <typename G>
 __device__ __forceinline__ StageView<G> view(WaveStage<G>& W) {
-  return StageView<G>{W.tri, W.excl, 7};
+  return StageView<G>{W.tri, W.excl, 6};
 }
 
 template <typename G>
@@ -1197,7 +1176,6 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
     }
     int wave_total;
     W.excl[lane] = wave_excl_scan(n, &wave_total);
-    W.excl[64 + lane] = wave_total;
     __syncthreads();
     raster_drain(rec, ng, pool, view(W), wave_total, 0, 1, part);
     __syncthreads();  // the stage is rewritten by the next block of items
