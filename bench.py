@@ -80,6 +80,27 @@ def measured_counters():
         return None
 
 
+def measured_batch_trace_issue():
+    """VALU issue fraction of the batched trace kernel (wave instructions over
+    the issue peak) from the committed rocprofv3 summary of this workload, or
+    None if the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_trace_batch4096_valu.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "\t")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["trace_valu_issue_frac"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -214,7 +235,8 @@ def bench_batch(args, rtw, inputs):
                    "tune": {"tile_rays": tune.tile_rays, "blocks_per_cu": tune.blocks_per_cu,
                             "cand_inline": tune.cand_inline},
                    "kernels_ms_per_step": {k: round(t / args.steps, 4) for k, (t, n) in prof.items()},
-                   "dominant_kernel": dom},
+                   "dominant_kernel": dom,
+                   "trace_valu_issue_frac": measured_batch_trace_issue()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -42,3 +42,13 @@ def test_committed_counter_summary_is_parseable():
     assert 0 < float(kv["valu_busy_pct"]) <= 100 and 0 < float(kv["valu_utilization_pct"]) <= 100
     assert float(kv["valu_insts_per_launch"]) > 0
     assert len(kv["source_hash"]) == 16
+
+
+def test_committed_batch_trace_summary_is_parseable():
+    kv = {}
+    with open(os.path.join(ROOT, "profiles", "k_trace_batch4096_valu.txt")) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    assert 0 < float(kv["trace_valu_issue_frac"]) <= 1.0 and len(kv["source_hash"]) == 16
