@@ -26,7 +26,30 @@ namespace rtw {
 // scalar helpers with one spelling for both precisions
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// FP64 1 / b and 1 / sqrt(x) from the hardware estimates refined by two
+// Newton steps (each squares the relative error: a few ulp from the estimate,
+// about one ulp after them), cheaper than IEEE division and square root.
+// Where the estimate is infinite or zero (b = 0, x = 0, infinities) it is
+// returned as is, so that those cases give what 1 / b and 1 / sqrt(x) give.
+__device__ __forceinline__ double rcp_d(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  if (!(fabs(r) < 1.79e308) || r == 0.0) return r;
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  if (!(fabs(y) < 1.79e308) || y == 0.0) return y;
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq(double x) { return rsq_d(x); }
 __device__ __forceinline__ float sqr_t(float x) { return __fsqrt_rn(x); }
 __device__ __forceinline__ double sqr_t(double x) { return sqrt(x); }
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -183,14 +206,14 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   for (int q = 1; q <= P.p_max + 1; ++q) {
     // outward normal and incidence-plane basis (FP64)
     V Ar = mk3(P.A[0] * r.x, P.A[1] * r.y, P.A[2] * r.z);
-    const double inA = 1.0 / sqrt(dot(Ar, Ar));
+    const double inA = rsq_d(dot(Ar, Ar));
     V nh = scl(inA, Ar);
     const double dn = dot(d, nh);  // n . k_hat (signed)
     const double sgn = dn > 0 ? 1.0 : -1.0;
     const double ci = sgn * dn;    // cos(theta_i)
     V c = scl(sgn, cross(d, nh));  // d x nu
     const double c2 = dot(c, c);
-    V ep = c2 < 1e-24 ? u1 : scl(1.0 / sqrt(c2), c);
+    V ep = c2 < 1e-24 ? u1 : scl(rsq_d(c2), c);
     // rotate the carried state into (e_perp, e_par): e_perp = cs u1 + sn u2
     const G cs = (G)dot(ep, u1), sn = (G)dot(ep, u2);
     cx<G> Jl[2][2];
@@ -221,7 +244,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     V dt = d;
     if (!tir) {
       ct = sqrt(ct2);
-      const double sct = sgn * ct, im = 1.0 / mrel;
+      const double sct = sgn * ct, im = rcp_d(mrel);
       dt = mk3((d.x - dn * nh.x) * im + sct * nh.x, (d.y - dn * nh.y) * im + sct * nh.y,
                (d.z - dn * nh.z) * im + sct * nh.z);
       gt = dot(dt, nh);
@@ -266,7 +289,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       const G ko = (G)kod;
       const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
       const V dout = emit_t ? dt : dr;
-      const G inko = 1 / ko, igo = (G)(1.0 / god);
+      const G inko = 1 / ko, igo = (G)rcp_d(god);
       const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
       double Q11 = (double)(a11 * inko);
       double Q12 = (double)(a12 * inko * igo);
@@ -284,7 +307,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
         e_amplif = fmax(e_amplif, (t11a * fabs(b22) + fabs(b11) * t22a + 2.0 * t12a * fabs(b12)) /
                                       fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
       }
-      double amp = sqrt(D / fabs(detQ));
+      double amp = sqrt(D * rcp_d(fabs(detQ)));
       V epo = cross(dout, ep);  // e_par' of the outgoing wave
       // lab vectors: direction rounded once to G; the phase uses exactly that vector
       v3<G> dl = mk3<G>((G)(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z),
@@ -333,7 +356,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     const double god = cont_t ? gt : gr;
     const G ko = (G)kod;
     const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
-    const G inko = 1 / ko, igo = (G)(1.0 / god);
+    const G inko = 1 / ko, igo = (G)rcp_d(god);
     const G Q11 = (M11i + w * C11) * inko;
     const G Q12 = (M12i + w * C12) * inko * igo;
     const G Q22 = (M22i + w * C22) * inko * igo * igo;
@@ -359,9 +382,9 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     // cancellation in det(I + L Q) (relative errors enter through L Q only)
     amplif = fmax(amplif, (fabs(L * (double)Q11) * fabs(g22) + fabs(g11) * fabs(L * (double)Q22) + 2.0 * g12 * g12) /
                               fmax(fabs(detG), 1e-300));
-    D /= fabs(detG);
+    D *= rcp_d(fabs(detG));
     nf += neg_eigs(g11, g12, g22);
-    double idg = 1.0 / detG;
+    double idg = rcp_d(detG);
     // Q G^-1 with G^-1 = [[g22, -g12], [-g12, g11]] / det G  (symmetric result)
     double n11 = ((double)Q11 * g22 - (double)Q12 * g12) * idg;
     double n12 = ((double)Q12 * g11 - (double)Q11 * g12) * idg;
