@@ -14,6 +14,11 @@ Workloads (sizes of the ray and node grids, orders, polarisations):
 * ``large_ellipsoid``  ellipsoid 1000/950/900 um, Euler (0,0,0), m=1.333, p=0..5,
   8192x8192 rays, theta 0..119.5 step 0.5, 120..170 step 0.02, 170.5..180 step
   0.5 deg, phi 0..359.5 step 0.5 deg, x-polarised.
+* ``paper_spheroid``   the paper's own spheroid: a=b=100, c=90 um, m=1.333,
+  plane wave along the particle's x axis (Euler (0, 90, 180): lab z = body x,
+  lab x = body z), x-polarised, p=0..3, 3456x3456 rays (the ray density of
+  ``ellipsoid_mixed``), nodes theta 0..180 x phi 0..359.99 step 0.01 deg
+  (18001 x 36000, the paper's 0.01 deg angular resolution).
 * ``batch``            4096 ellipsoids drawn with SplitMix64 from seed 0
   (``batch_particles``), p=0..3, ray-grid side proportional to size, nodes
   theta 0..180 step 0.5 x phi 0..358 step 2 deg, x and y polarisations.
@@ -69,6 +74,11 @@ def large_theta_grid() -> np.ndarray:
 def large_ellipsoid(grid_n: int = 8192) -> Workload:
     return Workload("large_ellipsoid", (1000.0, 950.0, 900.0), (0.0, 0.0, 0.0), 1.333, WAVELENGTH, 0, 5, grid_n, 1,
                     large_theta_grid(), uniform_angles(0.0, 359.5, 0.5))
+
+
+def paper_spheroid(grid_n: int = 3456) -> Workload:
+    return Workload("paper_spheroid", (100.0, 100.0, 90.0), (0.0, 90.0, 180.0), 1.333, WAVELENGTH, 0, 3, grid_n, 1,
+                    uniform_angles(0.0, 180.0, 0.01), uniform_angles(0.0, 359.99, 0.01))
 
 
 def batch_node_grid() -> Tuple[np.ndarray, np.ndarray]:

@@ -276,3 +276,22 @@ def test_uniform_axis_boxes_match_segment_tables(R):
                 f"{int(nc_u.sum())} contributions on the uniform grid")
             assert np.array_equal(nc[np.ix_(it, ip)], nc_u)
             assert np.array_equal(F[:, :, it][:, :, :, ip], F_u)
+
+
+def test_paper_spheroid_strips_match_oracle(oracle, R):
+    """The paper's spheroid (a=b=100, c=90 um, incidence along its x axis) at its
+    full ray count and the paper's 0.01 deg node spacing, on strips across the
+    primary rainbow and the forward lobe: mixed path against the oracle."""
+    w = I.paper_spheroid()
+    ph = I.uniform_angles(0.0, 90.0, 45.0)
+    op, os_, gp, gi, go = _oracle_pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.wavelength, w.n_pol, w.p_min,
+                                      w.p_max, w.grid_n, R.MIXED)
+    for th in (I.uniform_angles(136.0, 140.0, 0.01), I.uniform_angles(5.0, 6.0, 0.01)):
+        say(f"[paper spheroid] N={w.grid_n}, theta {th[0]:.2f}..{th[-1]:.2f} step 0.01 x phi {ph.tolist()}")
+        ref = oracle.farfield(op, os_, th, ph)
+        F, nc, _ = _farfield_gpu(R, gp, gi, go, th, ph)
+        rel, dph = _compare_mixed(ref, F)
+        say(f"   compared {rel.size} nodes: intensity rel max {rel.max(initial=0.0):.3e} "
+            f"phase max {dph.max(initial=0.0):.3e}")
+        assert rel.size > 0.5 * th.size * ph.size
+        assert rel.max(initial=0.0) < 1e-4 and dph.max(initial=0.0) < 1e-3
