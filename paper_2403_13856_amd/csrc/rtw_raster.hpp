@@ -1119,8 +1119,11 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
   raster_drain(rec, ng, pool, view(S), block_total, wave, 4, wave_partition());
 }
 
-// One thread per listed (triangle, theta row); the block walks the list in
-// blocks of 256 items.  Each row's candidates are the nodes of the row's
+// One thread per listed (triangle, theta row).  A large triangle's rows sit
+// next to each other in the list, so consecutive items go to different waves
+// (item = pass base + lane x total waves + global wave index): the rows of
+// one triangle near a pole, thousands of nodes each, are drained by many
+// waves instead of one.  Each row's candidates are the nodes of the row's
 // longitude window (row_window).
 template <typename G>
 __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Records<G> rec, const NodeGrid ng,
@@ -1131,8 +1134,10 @@ __global__ void __launch_bounds__(256) k_raster_rows(const BatchDev B, const Rec
   const unsigned n_items = min(*pool.n_rows, (unsigned)pool.rows_cap);
   const int part = wave_partition();
   const double sin_margin = sin(margin);
-  for (unsigned first = blockIdx.x * blockDim.x; first < n_items; first += gridDim.x * blockDim.x) {
-    const unsigned item = first + threadIdx.x;
+  const unsigned n_waves = gridDim.x * (blockDim.x >> 6);
+  const unsigned gwave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  for (unsigned first = 0; first < n_items; first += n_waves * 64u) {
+    const unsigned item = first + (unsigned)lane * n_waves + gwave;
     int n = 0;
     int2 w = make_int2(-1, 0);
     if (item < n_items) w = pool.rows[item];
