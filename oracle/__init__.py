@@ -27,7 +27,7 @@ class Particle(ctypes.Structure):
 
 class Setup(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("n_pol", ctypes.c_int), ("p_min", ctypes.c_int),
-                ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int)]
+                ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int), ("source_distance", ctypes.c_double)]
 
 
 class Emit(ctypes.Structure):
@@ -65,6 +65,8 @@ def lib():
                                        dp, dp, ip, ip, dp]
         _lib.rtwo_grid_halfwidth.argtypes = [P(Particle)]
         _lib.rtwo_grid_halfwidth.restype = ctypes.c_double
+        _lib.rtwo_grid_halfwidth_source.argtypes = [P(Particle), ctypes.c_double]
+        _lib.rtwo_grid_halfwidth_source.restype = ctypes.c_double
         _lib.rtwo_fresnel.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib.rtwo_set_threads.argtypes = [ctypes.c_int]
         _lib.rtwo_get_threads.restype = ctypes.c_int
@@ -87,8 +89,10 @@ def particle(semi_axes, euler_deg=(0.0, 0.0, 0.0), m=1.333):
     return p
 
 
-def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64):
+def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64, source_distance=0.0):
+    """Trace settings; source_distance > 0 puts a point source at lab (0, 0, -source_distance)."""
     s = Setup()
+    s.source_distance = float(source_distance)
     s.wavelength = float(wavelength)
     s.n_pol = int(n_pol)
     s.p_min = int(p_min)
@@ -105,8 +109,9 @@ def get_threads():
     return lib().rtwo_get_threads()
 
 
-def grid_halfwidth(part):
-    return lib().rtwo_grid_halfwidth(ctypes.byref(part))
+def grid_halfwidth(part, source_distance=0.0):
+    """Half-width of the incident grid (um), widened for a point source."""
+    return lib().rtwo_grid_halfwidth_source(ctypes.byref(part), float(source_distance))
 
 
 def trace_rays(part, st, xy):

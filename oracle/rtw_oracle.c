@@ -46,6 +46,18 @@
  *      receives the barycentric (central projection) interpolation of the
  *      three ray fields, each carried to the node direction with the
  *      stationary-phase gradient dPhi/d(dir) = -k r_exit.
+ *  R10 Non-plane incidence (the Phi_i term of Eq. 10): a point source S on
+ *      the lab axis at z = -z_s sends a spherical wave toward +z.  The ray
+ *      of grid point (x, y) runs from S through the lab point (x, y, 0);
+ *      at its first interaction point r_1, rho_1 = |r_1 - S| from S, the
+ *      incident WFC is Q_i = I / rho_1 (diverging, reading R1), the amplitude
+ *      A_0 = z_s / rho_1 (unit at the distance of the particle centre) and
+ *      Phi_i = k (rho_1 - z_s) (phase referenced to the particle centre, so
+ *      that z_s -> infinity gives back the plane wave's k z_1).  Its
+ *      polarisation vectors are lab x made transverse to the ray and
+ *      normalised, u_1, and u_2 = d x u_1.  The grid's half-width grows by
+ *      z_s / (z_s - a_max) (a_max the largest semi-axis), the widest
+ *      central projection of the particle from S onto z = 0.
  */
 #include "rtw_oracle.h"
 
@@ -191,6 +203,7 @@ typedef struct {
   double R[3][3];   /* body -> lab */
   double k;         /* 2 pi / lambda */
   double m;
+  double zs;        /* point-source distance (0: plane wave) */
   int n_pol, p_min, p_max;
 } ctx_t;
 
@@ -296,11 +309,22 @@ static void emit_order(const ctx_t* c, const ray_state* s, const double* dir, co
     }
 }
 
-/* Trace one ray entering at the lab point (x, y) (lab plane z = 0, direction +z). */
+/* Trace one ray through the lab point (x, y, 0): a plane-wave ray along +z,
+ * or the ray from the point source (reading R10). */
 static void trace_one(const ctx_t* c, double x, double y, rtwo_ray* out) {
   memset(out, 0, sizeof(*out));
-  const double zl[3] = {0, 0, 1}, xl[3] = {1, 0, 0}, yl[3] = {0, 1, 0};
+  double zl[3] = {0, 0, 1}, xl[3] = {1, 0, 0}, yl[3] = {0, 1, 0};
   double o_lab[3] = {x, y, 0.0};
+  if (c->zs > 0.0) {
+    /* origin at S, direction toward (x, y, 0), x made transverse to it */
+    double v[3] = {x, y, c->zs};
+    scale3(1.0 / norm3(v), v, zl);
+    double xt[3];
+    for (int i = 0; i < 3; i++) xt[i] = xl[i] - zl[0] * zl[i];
+    scale3(1.0 / norm3(xt), xt, xl);
+    cross3(zl, xl, yl);
+    o_lab[0] = 0.0; o_lab[1] = 0.0; o_lab[2] = -c->zs;
+  }
   ray_state s;
   memset(&s, 0, sizeof(s));
   double o[3];
@@ -309,6 +333,14 @@ static void trace_one(const ctx_t* c, double x, double y, rtwo_ray* out) {
   matTvec(c->R, xl, s.u1);
   matTvec(c->R, yl, s.u2);
 
+  /* a distant source: restart the ray at its closest approach to the centre,
+     so that the quadratic below is not solved from far away (its rounding
+     grows with the square of the distance) */
+  double t0 = 0.0;
+  if (c->zs > 0.0) {
+    t0 = -dot3(o, s.d);
+    for (int i = 0; i < 3; i++) o[i] += t0 * s.d[i];
+  }
   /* entry point: smaller root of (o + t d)^T A (o + t d) = 1, stable form */
   double Ad[3], Ao[3];
   Avec(c, s.d, Ad);
@@ -323,12 +355,19 @@ static void trace_one(const ctx_t* c, double x, double y, rtwo_ray* out) {
   for (int i = 0; i < 3; i++) s.r[i] = o[i] + t * s.d[i];
   out->active = 1;
 
-  /* initial state: plane wave (Q = 0), J = identity, incident phase k (khat . r1) */
+  /* initial state: plane wave (Q = 0), J = identity, incident phase k (khat . r1);
+     point source: Q = I / rho_1, J = (z_s / rho_1) identity, phase k (rho_1 - z_s) */
   s.Q.m[0][0] = s.Q.m[0][1] = s.Q.m[1][0] = s.Q.m[1][1] = 0.0;
   s.J[0][0] = 1; s.J[0][1] = 0; s.J[1][0] = 0; s.J[1][1] = 1;
   s.D = 1.0;
   s.nf = 0;
   s.opl = c->k * dot3(s.d, s.r);
+  if (c->zs > 0.0) {
+    double rho = t0 + t; /* |d| = 1 and the ray starts at S */
+    s.Q.m[0][0] = s.Q.m[1][1] = 1.0 / rho;
+    s.J[0][0] = s.J[1][1] = c->zs / rho;
+    s.opl = c->k * (rho - c->zs);
+  }
   s.n_cur = 1.0;
   s.tir_any = 0;
 
@@ -465,6 +504,9 @@ static int setup_ctx(const rtwo_particle* part, const rtwo_setup* st, ctx_t* c) 
   if (!(st->wavelength > 0.0)) return -1;
   if (st->n_pol < 1 || st->n_pol > 2) return -1;
   if (st->p_min < 0 || st->p_max < st->p_min || st->p_max > RTWO_MAX_ORDER) return -1;
+  double amax = fmax(part->semi_axes[0], fmax(part->semi_axes[1], part->semi_axes[2]));
+  if (!(st->source_distance == 0.0 || st->source_distance > amax)) return -1;
+  c->zs = st->source_distance;
   for (int i = 0; i < 3; i++) c->A[i] = 1.0 / (part->semi_axes[i] * part->semi_axes[i]);
   euler_zyz(part->euler_deg, c->R);
   c->k = 2.0 * PI / st->wavelength;
@@ -497,6 +539,15 @@ double rtwo_grid_halfwidth(const rtwo_particle* part) {
   return L;
 }
 
+double rtwo_grid_halfwidth_source(const rtwo_particle* part, double source_distance) {
+  double L = rtwo_grid_halfwidth(part);
+  if (source_distance > 0.0) {
+    double amax = fmax(part->semi_axes[0], fmax(part->semi_axes[1], part->semi_axes[2]));
+    L *= source_distance / (source_distance - amax);
+  }
+  return L;
+}
+
 /* Compact per-ray record used by the far-field assembly. */
 typedef struct {
   int valid, nf, det_neg;
@@ -510,7 +561,7 @@ int rtwo_trace_grid(const rtwo_particle* part, const rtwo_setup* setup, int* fla
   if (setup_ctx(part, setup, &c) != 0 || setup->grid_n < 2) return -1;
   int N = setup->grid_n, n_ord = c.p_max - c.p_min + 1;
   long NN = (long)N * N;
-  double L = rtwo_grid_halfwidth(part), h = 2.0 * L / N;
+  double L = rtwo_grid_halfwidth_source(part, setup->source_distance), h = 2.0 * L / N;
 #pragma omp parallel for schedule(static) num_threads(rtwo_get_threads())
   for (int iy = 0; iy < N; iy++) {
     rtwo_ray ray;
@@ -710,7 +761,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
 
   int N = setup->grid_n, n_ord = c.p_max - c.p_min + 1, n_pol = c.n_pol;
   long NN = (long)N * N, n_nodes = (long)n_theta * n_phi;
-  double L = rtwo_grid_halfwidth(part), h = 2.0 * L / N;
+  double L = rtwo_grid_halfwidth_source(part, setup->source_distance), h = 2.0 * L / N;
   double band = band_deg * PI / 180.0;
 
   /* node directions and the lab (e_theta, e_phi) basis */

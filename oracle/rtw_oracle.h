@@ -9,7 +9,8 @@
  * with the HIP library and must never be linked into the product path.
  *
  * Units: lengths in micrometres, angles in degrees at this interface.
- * Lab frame: the incident plane wave travels along +z, polarisation basis
+ * Lab frame: the incident plane wave travels along +z (or a spherical wave
+ * from a point source on the -z axis, see rtwo_setup), polarisation basis
  * (x, y).  Body frame: x_lab = R x_body with R = Rz(alpha) Ry(beta) Rz(gamma)
  * (intrinsic Z-Y-Z Euler angles).  Time dependence exp(-i w t), so the
  * propagation phase grows as +k * path.
@@ -38,6 +39,8 @@ typedef struct {
   int n_pol;         /* 1: x-polarised incidence only, 2: x and y */
   int p_min, p_max;  /* orders emitted, 0 <= p_min <= p_max <= 15 */
   int grid_n;        /* incident ray grid is grid_n x grid_n, cell centred */
+  double source_distance; /* 0: plane wave along +z; > largest semi-axis: point source
+                             at lab (0, 0, -source_distance), spherical wave (reading R10) */
 } rtwo_setup;
 
 /* Everything the oracle knows about one emitted order of one ray. */
@@ -70,7 +73,7 @@ typedef struct {
   rtwo_emit emit[RTWO_MAX_ORDER + 1];        /* indexed by order p */
 } rtwo_ray;
 
-/* Trace n rays entering at lab-plane points xy[2*i], xy[2*i+1] (um); out[i]
+/* Trace n rays through lab-plane points xy[2*i], xy[2*i+1] (um); out[i]
  * receives the full diagnostic record.  Returns 0 on success, <0 on bad input. */
 int rtwo_trace_rays(const rtwo_particle* part, const rtwo_setup* setup,
                     int n, const double* xy, rtwo_ray* out);
@@ -79,8 +82,13 @@ int rtwo_trace_rays(const rtwo_particle* part, const rtwo_setup* setup,
  * along lab x and y, L = max(sqrt(S_xx), sqrt(S_yy)), S = R diag(a^2,b^2,c^2) R^T. */
 double rtwo_grid_halfwidth(const rtwo_particle* part);
 
+/* Half-width of the grid for a point source at source_distance (> 0): L times
+ * source_distance / (source_distance - largest semi-axis); the plane-wave L at 0. */
+double rtwo_grid_halfwidth_source(const rtwo_particle* part, double source_distance);
+
 /* Trace the full cell-centred grid.  Ray index = iy*N + ix, lab point
- * (-L + (ix+1/2) 2L/N, -L + (iy+1/2) 2L/N).  Outputs are per order slot
+ * (-L + (ix+1/2) 2L/N, -L + (iy+1/2) 2L/N) with
+ * L = rtwo_grid_halfwidth_source(part, setup->source_distance).  Outputs are per order slot
  * o = p - p_min, SoA, all caller-owned host arrays:
  *   flags [n_ord][N*N]   bit0 valid, bits1..7 nf, bit8 det_neg
  *   dir   [n_ord][3][N*N]  rexit [n_ord][3][N*N]  phase [n_ord][N*N]  amp [n_ord][N*N]
