@@ -59,11 +59,24 @@ typedef struct {
   double m;            /* real relative refractive index, m > 0, m != 1 */
 } rtw_particle;
 
-/* Incident plane wave along lab +z (the paper's problem statement: wavelength
- * and polarisation of the incident wave). */
+/* Incident wave (the paper's problem statement: wavelength and polarisation
+ * of the incident wave; Eq. 10's incident phase Phi_i for a non-plane wave).
+ *   source_distance = 0: plane wave along lab +z, polarisation basis (x, y).
+ *   source_distance = z_s > largest semi-axis of every particle: spherical
+ *     wave from a point source at lab (0, 0, -z_s).  The ray of grid point
+ *     (x, y) runs from the source through the lab point (x, y, 0); at its
+ *     first interaction, rho_1 from the source, it has the wavefront
+ *     curvature I / rho_1 (diverging), amplitude z_s / rho_1 and phase
+ *     k (rho_1 - z_s) (unit amplitude and zero phase at the distance of the
+ *     particle centre, so z_s -> infinity gives the plane wave); its
+ *     polarisation vectors are lab x made transverse to the ray, and the ray
+ *     direction crossed with that.  The incident grid's half-width grows by
+ *     z_s / (z_s - largest semi-axis).
+ * Other values of source_distance: RTW_ERR_INVALID_ARG. */
 typedef struct {
-  double wavelength; /* in the surrounding medium (um) */
-  int n_pol;         /* 1: x polarisation only; 2: x and y */
+  double wavelength;      /* in the surrounding medium (um) */
+  int n_pol;              /* 1: x polarisation only; 2: x and y */
+  double source_distance; /* 0: plane wave; z_s (um): point source, see above */
 } rtw_incident;
 
 typedef struct {

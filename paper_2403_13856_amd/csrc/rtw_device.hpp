@@ -118,6 +118,7 @@ struct ParticleConst {
   int N;         // rays per side
   int p_min, p_max, n_pol;
   double amplif_limit;  // mixed path: FP64 re-trace above this error amplification
+  double zs;     // point-source distance on the lab -z axis (um); 0: plane wave
 };
 
 // Two-constant Cody-Waite reduction of x modulo 2 pi in FP64 (Cody & Waite,
@@ -172,9 +173,28 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   const double* R = P.R;
   const double x = -P.L + (ix + 0.5) * P.h;
   const double y = -P.L + (iy + 0.5) * P.h;
-  // lab ray x*ex + y*ey + t ez in body coordinates
+  // plane wave: lab ray x*ex + y*ey + t ez in body coordinates
   V o = mk3(R[0] * x + R[3] * y, R[1] * x + R[4] * y, R[2] * x + R[5] * y);
   V d = mk3(R[6], R[7], R[8]);
+  V u1 = mk3(R[0], R[1], R[2]);  // body image of lab x
+  V u2 = mk3(R[3], R[4], R[5]);  // body image of lab y = d x u1
+  double t0 = 0.0;
+  if (P.zs > 0.0) {
+    // point source at lab (0, 0, -zs): the ray toward the lab point (x, y, 0),
+    // polarisation u1 = lab x made transverse to it, u2 = d x u1
+    const double il = rsq_d(x * x + y * y + P.zs * P.zs);
+    const double lx = x * il, ly = y * il, lz = P.zs * il;
+    const double iu = rsq_d(1.0 - lx * lx);
+    const double ux = (1.0 - lx * lx) * iu, uy = -lx * ly * iu, uz = -lx * lz * iu;
+    d = mk3(R[0] * lx + R[3] * ly + R[6] * lz, R[1] * lx + R[4] * ly + R[7] * lz, R[2] * lx + R[5] * ly + R[8] * lz);
+    u1 = mk3(R[0] * ux + R[3] * uy + R[6] * uz, R[1] * ux + R[4] * uy + R[7] * uz, R[2] * ux + R[5] * uy + R[8] * uz);
+    u2 = cross(d, u1);
+    // start at the closest approach to the centre: the entry quadratic solved
+    // from the source itself would lose digits as the square of its distance
+    o = mk3(-P.zs * R[6], -P.zs * R[7], -P.zs * R[8]);
+    t0 = -dot(o, d);
+    o = axpy(t0, d, o);
+  }
   const V Ad0 = mk3(P.A[0] * d.x, P.A[1] * d.y, P.A[2] * d.z);
   const V Ao = mk3(P.A[0] * o.x, P.A[1] * o.y, P.A[2] * o.z);
   double qa = dot(d, Ad0), qb = 2.0 * dot(d, Ao), qc = dot(o, Ao) - 1.0;
@@ -185,8 +205,6 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   double t = fmin(qq / qa, qc / qq);
 
   V r = axpy(t, d, o);
-  V u1 = mk3(R[0], R[1], R[2]);  // body image of lab x
-  V u2 = mk3(R[3], R[4], R[5]);  // body image of lab y = d x u1
   G q11 = 0, q12 = 0, q22 = 0;   // plane wave
   cx<G> J[2][2];                 // J[component along u_a][incident pol]
   J[0][0].re = 1; J[0][0].im = 0; J[0][1].re = 0; J[0][1].im = 0;
@@ -194,6 +212,15 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   double D = 1.0;
   int nf = 0;
   double opl = P.k * dot(d, r);  // incident phase, referenced to the particle centre
+  if (P.zs > 0.0) {
+    // spherical wave rho = t0 + t from the source: WFC I / rho, amplitude
+    // zs / rho, phase k (rho - zs) (both referenced to the particle centre)
+    const double rho = t0 + t;
+    const double irho = rcp_d(rho);
+    q11 = q22 = (G)irho;
+    J[0][0].re = J[1][1].re = (G)(P.zs * irho);
+    opl = P.k * (rho - P.zs);
+  }
   // Largest relative-error amplification met so far by the divergence factor:
   // the cancellation in det(I + L Q) per propagation (a focal line close to an
   // interface).  Each emission adds the cancellation of its own exit wavefront

@@ -92,6 +92,9 @@ int check_particle(const rtw_particle* p, const rtw_incident* inc, const rtw_tra
   if (!(inc->wavelength > 0.0) || !std::isfinite(inc->wavelength))
     return fail(RTW_ERR_INVALID_ARG, "wavelength must be positive");
   if (inc->n_pol != 1 && inc->n_pol != 2) return fail(RTW_ERR_INVALID_ARG, "n_pol must be 1 or 2");
+  const double amax = std::max(p->semi_axes[0], std::max(p->semi_axes[1], p->semi_axes[2]));
+  if (!(inc->source_distance == 0.0 || (inc->source_distance > amax && std::isfinite(inc->source_distance))))
+    return fail(RTW_ERR_INVALID_ARG, "source_distance must be 0 (plane wave) or beyond the largest semi-axis");
   if (o->p_min < 0 || o->p_max < o->p_min) return fail(RTW_ERR_INVALID_ARG, "need 0 <= p_min <= p_max");
   if (o->p_max > RTW_MAX_ORDER) return fail(RTW_ERR_UNSUPPORTED, "p_max > %d", RTW_MAX_ORDER);
   if (o->grid_n < 2 || o->grid_n > 16384) return fail(RTW_ERR_INVALID_ARG, "grid_n must be in [2, 16384]");
@@ -120,6 +123,12 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
     syy += P.R[3 + k] * P.R[3 + k] * s2;
   }
   P.L = std::max(std::sqrt(sxx), std::sqrt(syy));
+  P.zs = inc->source_distance;
+  if (P.zs > 0.0) {
+    // widest central projection of the particle from the source onto z = 0
+    const double amax = std::max(p->semi_axes[0], std::max(p->semi_axes[1], p->semi_axes[2]));
+    P.L *= P.zs / (P.zs - amax);
+  }
   P.N = o->grid_n;
   P.h = 2.0 * P.L / P.N;
   P.k = 2.0 * PI_H / inc->wavelength;

@@ -54,7 +54,15 @@ def test_argument_validation_without_device():
         (good[0], good[1], rtw.make_opts(0, 16, 64), rtw.RTW_ERR_UNSUPPORTED),
         (good[0], good[1], rtw.make_opts(0, 3, 1), rtw.RTW_ERR_INVALID_ARG),
         (good[0], good[1], rtw.make_opts(0, 3, 64, 7), rtw.RTW_ERR_INVALID_ARG),
+        # point source: beyond the largest semi-axis (50 um), finite, not negative
+        (good[0], rtw.make_incident(0.6328, 2, 50.0), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, 30.0), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, -200.0), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, float("inf")), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, float("nan")), good[2], rtw.RTW_ERR_INVALID_ARG),
     ]
+    rc, n_src = _ws(good[0], rtw.make_incident(0.6328, 2, 50.5), good[2])
+    assert rc == rtw.RTW_OK and n_src == n
     for part, inc, opts, code in cases:
         rc, _ = _ws(part, inc, opts)
         assert rc == code, (rc, code)
@@ -129,3 +137,17 @@ def test_batch_workspace_and_validation_without_device():
                        None) == rtw.RTW_ERR_INVALID_ARG
     assert L.rtw_batch(0, P, G, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g), ctypes.c_void_p(256), None,
                        None, None, None, ctypes.c_void_p(4096), 1 << 30, None) == rtw.RTW_ERR_INVALID_ARG
+
+
+def test_surrogate_rejects_point_source_incidence():
+    """The surrogate models plane-wave incidence only (host-side check)."""
+    L = rtw.load()
+    part = rtw.make_particle((50, 40, 30), (10, 20, 30), 1.333)
+    th = (ctypes.c_double * 1)(130.0)
+    ph = (ctypes.c_double * 1)(10.0)
+    feats = (ctypes.c_float * 64)()
+    fn = L.rtw_surrogate_features
+    for zs, code in ((0.0, rtw.RTW_OK), (500.0, rtw.RTW_ERR_UNSUPPORTED)):
+        inc = rtw.make_incident(0.6328, 2, zs)
+        rc = fn(1, ctypes.byref(part), ctypes.byref(inc), 1, th, ph, feats)
+        assert rc == code, (zs, rc)
