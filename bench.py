@@ -105,12 +105,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def count_units(rtw, w, grid_n):
+def count_units(rtw, w, grid_n, zs=0.0):
     """Active incident rays (rays that emit order 0) and valid triangles (three
     rays emitting the order with equal focal-line counts), from rtw_trace."""
     import torch
     part = rtw.make_particle(w.semi_axes, w.euler_deg, w.m)
-    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1),
+    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1, zs),
                     rtw.make_opts(w.p_min, w.p_max, grid_n, rtw.FP64))
     fl = rec["flags"]
     n_active = int((fl[0] & 1).sum().item()) if w.p_min == 0 else None
@@ -127,9 +127,9 @@ def count_units(rtw, w, grid_n):
     return n_active, n_tri
 
 
-def time_path(rtw, w, grid_n, precision, steps, warmup):
+def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0):
     import torch
-    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m), rtw.make_incident(w.wavelength, w.n_pol),
+    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m), rtw.make_incident(w.wavelength, w.n_pol, zs),
                       rtw.make_opts(w.p_min, w.p_max, grid_n, precision), w.theta_deg, w.phi_deg)
     ff()  # sizes the workspace (grows it if the hit pool overflowed)
     for _ in range(warmup):
@@ -544,6 +544,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--spheroid-grid-n", type=int, default=3456)
     ap.add_argument("--spheroid-bands", type=int, default=16)
+    ap.add_argument("--source-distance", type=float, default=0.0,
+                    help="ellipsoid workload lit by a point source at lab (0, 0, -z) instead of the plane wave (um)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run would shard the ray grid "
@@ -575,18 +577,19 @@ def main():
     if args.workload == "paper_spheroid":
         return bench_paper_spheroid(args, rtw, inputs)
     w = inputs.ellipsoid_mixed(args.grid_n)
-    n_active, n_tri = count_units(rtw, w, args.grid_n)
+    zs = args.source_distance
+    n_active, n_tri = count_units(rtw, w, args.grid_n, zs)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "
         f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}, {n_tri} valid triangles")
 
-    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup)
+    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup, zs)
     log(f"[bench] mixed: {ms_mixed:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
     for k, (t, n) in sorted(prof_mixed.items(), key=lambda kv: -kv[1][0]):
         log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
     fp64 = None
     if not args.no_fp64:
         ms64, prof64, hits64, _ = time_path(rtw, w, args.grid_n, rtw.FP64, max(2, args.steps // 2),
-                                            max(1, args.warmup // 2))
+                                            max(1, args.warmup // 2), zs)
         log(f"[bench] fp64: {ms64:.3f} ms/step")
         for k, (t, n) in sorted(prof64.items(), key=lambda kv: -kv[1][0]):
             log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
@@ -608,7 +611,7 @@ def main():
     else:
         flops = 8 * hits
     achieved = flops / avg_s / 1e12
-    ctr = measured_counters() if dom == "k_raster_mixed" else None
+    ctr = measured_counters() if dom == "k_raster_mixed" and zs == 0 else None  # counters are of the plane wave
     traffic = ctr["traffic"] if ctr else None
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
@@ -624,7 +627,8 @@ def main():
         import oracle
         t0 = time.perf_counter()
         oracle.farfield(oracle.particle(w.semi_axes, w.euler_deg, w.m),
-                        oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n), w.theta_deg, w.phi_deg)
+                        oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n, source_distance=zs),
+                        w.theta_deg, w.phi_deg)
         dt = time.perf_counter() - t0
         cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
                    sample=f"full workload ({args.grid_n}^2 rays, all {w.n_nodes} nodes), one run, {dt:.1f} s")
@@ -644,7 +648,8 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"ellipsoid 60/50/40 um, Euler (30,20,10) deg, m=1.333, lambda=0.6328 um, "
-                               f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed",
+                               f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed"
+                               + (f", point source at {zs:g} um" if zs > 0 else ""),
                    "active_rays": n_active, "valid_triangles": n_tri, "source_hash": source_hash(), "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(w.n_nodes * w.n_pol / (ms_mixed * 1e-3), 1),
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},
