@@ -736,7 +736,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_cnodes, bsum); }
     { ProfScope ps(fp64 ? "k_store_hits_fp64" : "k_store_hits_mixed", st);
     const long slots = (long)NPART * cap_part;
-    hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, rec, ng, pool); }
+    hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, B, rec, ng, pool); }
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
     hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
                        S.n_pol, (G*)out, ncontrib, (G*)incoh); }

@@ -143,10 +143,8 @@ struct alignas(4 * sizeof(G)) V4 {
 
 template <typename G>
 struct HitDesc {
-  int key;
-  int rb;     // record index of (particle, slot, ray 0)
-  int v00;    // corner ray of the quad
-  int nt;     // N << 1 | t
+  int key;    // 2 (n_ord quad_off + slot (N-1)^2 + quad) + t: also gives the triangle's rays
+  int nt;     // t | N << 1 | chunk particle << 16
   int itip;   // node row | node column << 16
   int node;   // node index within the chunk (particle-major)
   int rank;   // place among the node's hits (taken with the node's count)
@@ -713,12 +711,18 @@ __device__ __forceinline__ v3<float> node_dir_g<float>(const NodeGrid& ng, int i
 // scan plus the rank the rasteriser took with the node's count, so this
 // kernel needs no atomic.
 template <typename G>
-__device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool, long idx) {
+__device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const NodeGrid& ng, const HitPool<G>& pool,
+                                 long idx) {
   const HitDesc<G> d = pool.desc[idx];
   const long at = (long)pool.cursor[d.node] + d.rank;
   const int it = d.itip & 0xffff, ip = (int)((unsigned)d.itip >> 16);
-  const int N = d.nt >> 1, t = d.nt & 1;
-  const long v00 = d.v00;
+  const int t = d.nt & 1, N = (d.nt >> 1) & 0x7fff, part = (int)((unsigned)d.nt >> 16);
+  // the triangle's rays from its key: order slot, quad, corner ray
+  const unsigned within = (unsigned)((long)(d.key >> 1) - (long)B.n_ord * (B.quad_off[part] - B.quad_base));
+  const unsigned nq = (unsigned)(N - 1) * (unsigned)(N - 1);
+  const unsigned slot = within / nq, quad = within - slot * nq;
+  const long v00 = (long)quad + quad / (unsigned)(N - 1);
+  const long rb = (long)B.n_ord * (B.ray_off[part] - B.ray_base) + (long)slot * N * N;
   const long vid[3] = {v00, t == 0 ? v00 + 1 : v00 + N + 1, t == 0 ? v00 + N + 1 : v00 + N};
   const double st = ng.sth[it], ct = ng.cth[it], sp = ng.sph[ip], cp = ng.cph[ip];
   const v3<double> eth = mk3<double>(ct * cp, ct * sp, -st);
@@ -728,7 +732,7 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
   const v3<double> n = node_dir(ng, it, ip);
   for (int k = 0; k < 3; ++k) {
-    const RayRec<G>& vr = rec.rr[d.rb + vid[k]];
+    const RayRec<G>& vr = rec.rr[rb + vid[k]];
     const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
     // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
@@ -764,13 +768,14 @@ __device__ inline void store_hit(const Records<G>& rec, const NodeGrid& ng, cons
 // One thread per pool slot: contributions of every hit the rasterisers found,
 // placed node by node (slots past a partition's fill are idle).
 template <typename G>
-__global__ void __launch_bounds__(256) k_store_hits(const Records<G> rec, const NodeGrid ng, const HitPool<G> pool) {
+__global__ void __launch_bounds__(256) k_store_hits(const BatchDev B, const Records<G> rec, const NodeGrid ng,
+                                                    const HitPool<G> pool) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long part = i / pool.cap_part;
   if (part >= NPART) return;
   const unsigned pos = (unsigned)(i - part * pool.cap_part);
   if (pos >= min(pool.counter[part], (unsigned)pool.cap_part)) return;
-  store_hit(rec, ng, pool, i);
+  store_hit(B, rec, ng, pool, i);
 }
 
 __device__ inline int wave_partition() {
@@ -778,16 +783,16 @@ __device__ inline int wave_partition() {
                 (threadIdx.x >> 6)) % NPART);
 }
 
-// A triangle staged in LDS for the flattened candidate loop (64 bytes
-// in the mixed path).  Node-grid sides and chunk particle counts are below
-// 2^16 (checked on the host), so index pairs share a word.
+// A triangle staged in LDS for the flattened candidate loop (56 bytes in the
+// mixed path, so that five blocks' stages fit a CU's LDS).  Its rays are not
+// kept: the hit store derives them from the key.  Node-grid sides and chunk
+// particle counts are below 2^16 (checked on the host), so index pairs share
+// a word.
 template <typename G>
 struct TriSlot {
   G m[9];    // canonical edge normals (edge_normals)
-  int v00;   // ray id of the quad's (ix, iy) corner
   int meta;  // bit 0: t (which half of the quad), bit 1: orient > 0, bits 2..16: N
   int key;   // per-node summation order
-  int rb;    // record index of (particle, slot, ray 0)
   int pk0;   // i0 | len << 16: candidate rows start at i0; len candidates per row
   int pk1;   // ja0 | la << 16: phi range a = [ja0, ja0 + la)
   int pk2;   // jb0 | part << 16: phi range b starts at jb0 (len - la nodes); chunk particle
@@ -800,10 +805,8 @@ __device__ __forceinline__ void slot_put(TriSlot<G>& S, Tri<G>& T, const Cand& c
   for (int k = 0; k < 3; ++k) {
     S.m[3 * k] = T.m[k].x; S.m[3 * k + 1] = T.m[k].y; S.m[3 * k + 2] = T.m[k].z;
   }
-  S.v00 = (int)T.vid[0];
   S.meta = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.orient > 0 ? 2 : 0) | (T.N << 2);
   S.key = T.key;
-  S.rb = (int)T.rb;
   S.pk0 = cd.i0 | (cd.len() << 16);
   S.pk1 = cd.ja0 | ((cd.ja1 - cd.ja0) << 16);
   S.pk2 = cd.jb0 | (T.part << 16);
@@ -815,13 +818,14 @@ __device__ __forceinline__ void slot_get(const TriSlot<G>& S, Tri<G>& T) {
   for (int k = 0; k < 3; ++k) T.m[k] = mk3<G>(S.m[3 * k], S.m[3 * k + 1], S.m[3 * k + 2]);
   const int t = S.meta & 1;
   const int N = (S.meta >> 2) & 0x7fff;
-  const long v00 = S.v00;
-  T.vid[0] = v00;
-  T.vid[1] = t == 0 ? v00 + 1 : v00 + N + 1;
-  T.vid[2] = t == 0 ? v00 + N + 1 : v00 + N;
+  // ray ids relative to the quad's corner: their order (all the tie rule
+  // needs) is that of the absolute ids
+  T.vid[0] = 0;
+  T.vid[1] = t == 0 ? 1 : N + 1;
+  T.vid[2] = t == 0 ? N + 1 : N;
   T.orient = (S.meta & 2) ? 1 : -1;
   T.N = N;
-  T.rb = S.rb;
+  T.rb = -1;
   T.part = (int)((unsigned)S.pk2 >> 16);
   T.key = S.key;
   for (int e = 0; e < 3; ++e) T.sig[e] = T.vid[(e + 1) % 3] < T.vid[(e + 2) % 3] ? 1 : -1;
@@ -934,9 +938,7 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
     if (pos < (unsigned)pool.cap_part) {  // beyond: overflow, reported by the status call
       HitDesc<G> d;
       d.key = T.key;
-      d.rb = (int)T.rb;
-      d.v00 = (int)T.vid[0];
-      d.nt = (T.N << 1) | (T.vid[1] == T.vid[0] + 1 ? 0 : 1);
+      d.nt = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.N << 1) | (T.part << 16);
       d.itip = it | (ip << 16);
       d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
       d.rank = atomicAdd(&pool.count[d.node], 1);
