@@ -136,7 +136,10 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   P.p_min = o->p_min;
   P.p_max = o->p_max;
   P.n_pol = inc->n_pol;
-  P.amplif_limit = 32.0;
+  // FP64 re-trace above this amplification: an FP32 divergence factor then
+  // carries at most 128 x 2^-24 relative error, 1.5e-5 in intensity (15% of
+  // the mixed path's 1e-4 bar)
+  P.amplif_limit = 128.0;
   return P;
 }
 
