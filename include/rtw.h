@@ -70,8 +70,9 @@ typedef struct {
  *     k (rho_1 - z_s) (unit amplitude and zero phase at the distance of the
  *     particle centre, so z_s -> infinity gives the plane wave); its
  *     polarisation vectors are lab x made transverse to the ray, and the ray
- *     direction crossed with that.  The incident grid's half-width grows by
- *     z_s / (z_s - largest semi-axis).
+ *     direction crossed with that.  The incident grid's half-width is the
+ *     largest extent along lab x or y of the particle's tangent cone from the
+ *     source on the plane z = 0.
  * Other values of source_distance: RTW_ERR_INVALID_ARG. */
 typedef struct {
   double wavelength;      /* in the surrounding medium (um) */

@@ -55,9 +55,9 @@
  *      Phi_i = k (rho_1 - z_s) (phase referenced to the particle centre, so
  *      that z_s -> infinity gives back the plane wave's k z_1).  Its
  *      polarisation vectors are lab x made transverse to the ray and
- *      normalised, u_1, and u_2 = d x u_1.  The grid's half-width grows by
- *      z_s / (z_s - a_max) (a_max the largest semi-axis), the widest
- *      central projection of the particle from S onto z = 0.
+ *      normalised, u_1, and u_2 = d x u_1.  The grid's half-width is the
+ *      largest extent along x or y of the particle's tangent cone from S on
+ *      the plane z = 0 (rtwo_grid_halfwidth_source).
  */
 #include "rtw_oracle.h"
 
@@ -539,11 +539,33 @@ double rtwo_grid_halfwidth(const rtwo_particle* part) {
   return L;
 }
 
+/* Point source S = (0, 0, -z_s): the rays from S that touch the particle form
+ * its tangent cone; the grid's half-width is the cone's largest extent along
+ * lab x or y on the plane z = 0.  With D = X - S, the line S + t D meets
+ * X^T M X = 1 (M = R diag(1/a^2) R^T) in a double root exactly when
+ * (D^T M S)^2 = (D^T M D)(S^T M S - 1), i.e. D^T K D = 0 with
+ * K = z_s^2 (m m^T - m_z M) + M, m = M e_z (so S^T M S = z_s^2 m_z).  On z = 0,
+ * D = (x, y, z_s); the extreme x = c of that conic is where the quadratic in
+ * y has a double root, a quadratic in c (likewise for y). */
 double rtwo_grid_halfwidth_source(const rtwo_particle* part, double source_distance) {
-  double L = rtwo_grid_halfwidth(part);
-  if (source_distance > 0.0) {
-    double amax = fmax(part->semi_axes[0], fmax(part->semi_axes[1], part->semi_axes[2]));
-    L *= source_distance / (source_distance - amax);
+  if (!(source_distance > 0.0)) return rtwo_grid_halfwidth(part);
+  double zs = source_distance, R[3][3], M[3][3], K[3][3];
+  euler_zyz(part->euler_deg, R);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      M[i][j] = 0.0;
+      for (int k = 0; k < 3; k++) M[i][j] += R[i][k] * R[j][k] / (part->semi_axes[k] * part->semi_axes[k]);
+    }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) K[i][j] = zs * zs * (M[i][2] * M[j][2] - M[2][2] * M[i][j]) + M[i][j];
+  double L = 0.0;
+  for (int i = 0; i < 2; i++) {
+    int j = 1 - i;
+    double A = K[i][j] * K[i][j] - K[j][j] * K[i][i];
+    double B = 2.0 * zs * (K[i][j] * K[j][2] - K[j][j] * K[i][2]);
+    double C = zs * zs * (K[j][2] * K[j][2] - K[j][j] * K[2][2]);
+    double sq = sqrt(B * B - 4.0 * A * C);
+    L = fmax(L, fmax(fabs((-B + sq) / (2.0 * A)), fabs((-B - sq) / (2.0 * A))));
   }
   return L;
 }
@@ -735,6 +757,31 @@ static void tri_node(int node, void* user) {
 
 typedef struct { int* nflags; } band_job;
 static void band_node(int node, void* user) { ((band_job*)user)->nflags[node] |= 2; }
+static double ang(const double* a, const double* b);
+/* nodes within `band` of the great-circle segment a-b (a == b: of the point a) */
+typedef struct { int* nflags; const nodes_t* nd; const double *a, *b; double band; } edge_job;
+static void edge_node(int node, void* user) {
+  const edge_job* E = (const edge_job*)user;
+  const double* n = &E->nd->nvec[3 * (long)node];
+  double c[3];
+  cross3(E->a, E->b, c);
+  double cn = norm3(c), dist;
+  double da = ang(n, E->a), db = ang(n, E->b);
+  dist = da < db ? da : db;
+  if (cn > 0.0) {
+    /* foot of the node on the great circle lies between a and b when it is on
+       the inner side of both end planes */
+    double pa[3], pb[3];
+    cross3(c, E->a, pa); /* points from a toward b within the circle */
+    cross3(E->b, c, pb); /* points from b toward a */
+    if (dot3(n, pa) >= 0.0 && dot3(n, pb) >= 0.0) {
+      double s = fabs(dot3(n, c)) / cn;
+      double d = asin(s > 1.0 ? 1.0 : s);
+      if (d < dist) dist = d;
+    }
+  }
+  if (dist <= E->band) E->nflags[node] |= 8;
+}
 
 static void unit_centroid(const double* a, const double* b, const double* c, double* o) {
   double s[3] = {a[0] + b[0] + c[0], a[1] + b[1] + c[1], a[2] + b[2] + c[2]};
@@ -831,7 +878,25 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
             V[k] = &rec[o * NN + tris[t][k]];
             if (!V[k]->valid) all_valid = 0;
           }
-          if (!all_valid) continue;
+          if (!all_valid) {
+            /* a triangle on the edge of the order's sheet (one or two of its
+               rays do not emit the order): the field ends along the segment
+               between its emitting rays, so mark the nodes within the band of
+               that segment (or of a lone emitting ray) */
+            int kv[3], nv = 0;
+            for (int k = 0; k < 3; k++)
+              if (V[k]->valid) kv[nv++] = k;
+            if (nv == 0) continue;
+            edge_job ej = {fl_buf, &nd, V[kv[0]]->dir, V[kv[nv - 1]]->dir, band};
+            double ce[3];
+            if (nv == 1) copy3(ej.a, ce);
+            else {
+              double s2[3] = {ej.a[0] + ej.b[0], ej.a[1] + ej.b[1], ej.a[2] + ej.b[2]};
+              scale3(1.0 / norm3(s2), s2, ce);
+            }
+            for_nodes_in_cap(&nd, ce, ang(ce, ej.a) + band + 1e-9, edge_node, &ej);
+            continue;
+          }
           double cen[3];
           unit_centroid(V[0]->dir, V[1]->dir, V[2]->dir, cen);
           double rho = ang(cen, V[0]->dir);

@@ -82,8 +82,9 @@ int rtwo_trace_rays(const rtwo_particle* part, const rtwo_setup* setup,
  * along lab x and y, L = max(sqrt(S_xx), sqrt(S_yy)), S = R diag(a^2,b^2,c^2) R^T. */
 double rtwo_grid_halfwidth(const rtwo_particle* part);
 
-/* Half-width of the grid for a point source at source_distance (> 0): L times
- * source_distance / (source_distance - largest semi-axis); the plane-wave L at 0. */
+/* Half-width of the grid for a point source at source_distance (> 0): the
+ * largest extent along lab x or y, on the plane z = 0, of the particle's
+ * tangent cone from the source; the plane-wave L at 0. */
 double rtwo_grid_halfwidth_source(const rtwo_particle* part, double source_distance);
 
 /* Trace the full cell-centred grid.  Ray index = iy*N + ix, lab point
@@ -104,7 +105,9 @@ int rtwo_trace_grid(const rtwo_particle* part, const rtwo_setup* setup,
  *   incoh  [n_theta*n_phi]  sum over contributions b of |f_b|^2 (pols, comps)
  *   nflags [n_theta*n_phi]  bit0 tie node (a barycentric weight within 1e-9 of 0),
  *                           bit1 within band_deg of a dropped fold triangle,
- *                           bit2 within band_deg of theta = 0 or 180
+ *                           bit2 within band_deg of theta = 0 or 180,
+ *                           bit3 within band_deg of the edge of an order's sheet
+ *                           (a triangle some of whose rays do not emit the order)
  *   ncontrib[n_theta*n_phi] number of triangle contributions
  *   uncancelled[n_theta*n_phi] sum over contributions of (sum over the three
  *                           rays of |lambda_v| |F_v|)^2 (pols, comps): the size of

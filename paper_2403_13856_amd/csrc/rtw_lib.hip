@@ -125,9 +125,32 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   P.L = std::max(std::sqrt(sxx), std::sqrt(syy));
   P.zs = inc->source_distance;
   if (P.zs > 0.0) {
-    // widest central projection of the particle from the source onto z = 0
-    const double amax = std::max(p->semi_axes[0], std::max(p->semi_axes[1], p->semi_axes[2]));
-    P.L *= P.zs / (P.zs - amax);
+    // Point source S = (0, 0, -zs): the grid spans the particle's tangent cone
+    // from S on the plane z = 0.  With D = X - S the cone is D^T K D = 0,
+    // K = zs^2 (m m^T - m_z M) + M for the lab matrix M = R diag(1/a^2) R^T
+    // and m = M e_z (the tangency condition (D^T M S)^2 = (D^T M D)(S^T M S - 1));
+    // its extreme x (or y) on z = 0, where D = (x, y, zs), is the double-root
+    // condition of the conic's quadratic in the other coordinate.
+    const double zs = P.zs;
+    double M[3][3], K[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += P.R[3 * i + k] * P.R[3 * j + k] * P.A[k];
+        M[i][j] = acc;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) K[i][j] = zs * zs * (M[i][2] * M[j][2] - M[2][2] * M[i][j]) + M[i][j];
+    double L = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      const int j = 1 - i;
+      const double a = K[i][j] * K[i][j] - K[j][j] * K[i][i];
+      const double b = 2.0 * zs * (K[i][j] * K[j][2] - K[j][j] * K[i][2]);
+      const double c = zs * zs * (K[j][2] * K[j][2] - K[j][j] * K[2][2]);
+      const double sq = std::sqrt(b * b - 4.0 * a * c);
+      L = std::max(L, std::max(std::fabs((-b + sq) / (2.0 * a)), std::fabs((-b - sq) / (2.0 * a))));
+    }
+    P.L = L;
   }
   P.N = o->grid_n;
   P.h = 2.0 * P.L / P.N;

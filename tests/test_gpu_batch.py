@@ -99,7 +99,7 @@ def _cmp_fp64(ref, F, tol=1e-10):
     seeded particles, ~4e-8 relative); the few nodes such a ray reaches
     differ by that times its interpolation weight (4.9e-10 at one node of
     63471 on particle 4, the next node 2.0e-11)."""
-    clean = ref["flags"] == 0
+    clean = (ref["flags"] & 7) == 0  # sheet-edge bands (bit 3) stay compared: FP64 membership there agrees
     inc = np.sqrt(ref["incoh"])
     err = np.abs(F - ref["field"]).max(axis=(0, 1))
     worst = (err / np.maximum(inc, 1e-300))[clean & (inc > 0)]
@@ -175,7 +175,8 @@ def test_batch_incoherent_intensity_matches_oracle(oracle, R):
         inc = b.incoh.cpu().numpy().sum(axis=1).reshape(len(parts), th.size, ph.size)
         for i in range(len(parts)):
             ref = oracle.farfield(oracle.particle(*parts[i]), oracle.setup(0.6328, 2, 0, 3, sides[i]), th, ph)
-            clean = ref["flags"] == 0
+            # FP64 keeps the sheet-edge bands (bit 3); the mixed path drops them
+            clean = (ref["flags"] & (7 if prec == "fp64" else 15)) == 0
             rel = np.abs(inc[i] - ref["incoh"])[clean] / np.maximum(ref["incoh"][clean], 1e-300)
             rel = rel[ref["incoh"][clean] > 0]
             say(f"[incoherent {prec}] particle {i}: max relative difference {rel.max(initial=0):.2e}")

@@ -12,7 +12,10 @@ Bars (written per test):
   barycentric weight within 1e-9 of zero -- either neighbouring triangle is a
   valid owner), 0.1 deg bands around dropped fold triangles (the caustics,
   where geometric optics diverges), and the poles theta < 0.1 deg or
-  > 179.9 deg.
+  > 179.9 deg.  The mixed path also leaves out the 0.1 deg bands along the
+  edges of each order's ray sheet (where some rays stop emitting the order):
+  the field ends there, so a node within FP32 rounding of the last triangle
+  belongs to it on one side and not on the other.  FP64 compares them.
 """
 import sys
 
@@ -123,7 +126,7 @@ def _farfield_gpu(R, gp, gi, go, theta, phi, hits_per_node=6.0):
 
 def _compare_fp64(ref, F, nc, tol=1e-10):
     flags = ref["flags"]
-    clean = flags == 0
+    clean = (flags & 7) == 0  # sheet-edge bands (bit 3) stay compared: FP64 membership there agrees
     inc = np.sqrt(ref["incoh"])
     err = np.abs(F - ref["field"]).max(axis=(0, 1))
     worst = (err / np.maximum(inc, 1e-300))[clean & (inc > 0)]

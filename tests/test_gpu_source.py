@@ -112,7 +112,7 @@ def test_source_farfield_fp64_matches_oracle(oracle, R):
     op, os_, gp, gi, go = _pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.n_pol, w.p_min, w.p_max, N, zs, R.FP64)
     ref = oracle.farfield(op, os_, w.theta_deg, w.phi_deg)
     F, nc = _farfield(R, gp, gi, go, w.theta_deg, w.phi_deg)
-    clean = ref["flags"] == 0
+    clean = (ref["flags"] & 7) == 0  # sheet-edge bands (bit 3) stay compared: FP64 membership there agrees
     inc = np.sqrt(ref["incoh"])
     err = np.abs(F - ref["field"]).max(axis=(0, 1))
     worst = (err / np.maximum(inc, 1e-300))[clean & (inc > 0)]

@@ -125,23 +125,48 @@ def test_off_axis_reflection_matches_ray_tube_balance(zs, alpha_deg):
     assert min(abs(w / abs(w) - 1), abs(w / abs(w) + 1)) <= 2e-8
 
 
-def test_grid_widens_for_the_source_and_covers_the_particle():
-    """Every ray of the widened grid's outer ring misses the particle, and the
-    half-width is z_s / (z_s - a_max) times the plane-wave one."""
-    part = O.particle((60.0, 50.0, 40.0), (30, 20, 10), M)
+@pytest.mark.parametrize("zs", [51.0, 75.0, 150.0, 1e4])
+def test_grid_halfwidth_of_a_sphere_is_its_shadow_cone(zs):
+    """A sphere's tangent cone from S has half-angle asin(a / z_s); it crosses
+    z = 0 at radius z_s tan(asin(a / z_s))."""
+    L = O.grid_halfwidth(_sphere(), zs)
+    assert L == pytest.approx(zs * A / math.sqrt(zs * zs - A * A), rel=1e-12)
+
+
+def _scan_hits(part, st, pts):
+    rays = O.trace_rays(part, st, pts)
+    return np.array([rays[i].active for i in range(len(pts))], bool)
+
+
+@pytest.mark.parametrize("euler", [(30, 20, 10), (80, 55, -35)])
+def test_grid_halfwidth_is_tight_around_the_particle(euler):
+    """Traced rays (the entry quadratic, not the cone formula): no ray just
+    outside the half-width on any side meets the tilted ellipsoid, and some
+    ray just inside it does on at least one side."""
+    part = O.particle((60.0, 50.0, 40.0), euler, M)
     zs = 150.0
-    L0 = O.grid_halfwidth(part)
     L = O.grid_halfwidth(part, zs)
-    assert L == pytest.approx(L0 * zs / (zs - 60.0), rel=1e-15)
-    N = 128
-    h = 2 * L / N
-    c = -L + (np.arange(N) + 0.5) * h
-    ring = [(c[i], c[j]) for i in range(N) for j in range(N) if min(i, j, N - 1 - i, N - 1 - j) == 0]
-    st = O.setup(LAM, 1, 0, 1, N, source_distance=zs)
-    rays = O.trace_rays(part, st, ring)
-    assert not any(rays[i].active for i in range(len(ring)))
-    inner = O.trace_rays(part, st, [(0.0, 0.0)])
-    assert inner[0].active
+    st = O.setup(LAM, 1, 0, 0, 8, source_distance=zs)
+    u = np.linspace(-L, L, 40001)
+    inside_any = False
+    for f in (1 + 1e-6, 1 - 1e-4):
+        hit = False
+        for sx, sy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            c = f * L
+            pts = np.stack([np.full_like(u, sx * c) if sx else u, np.full_like(u, sy * c) if sy else u], 1)
+            hit |= bool(_scan_hits(part, st, pts).any())
+        if f > 1:
+            assert not hit
+        else:
+            inside_any = hit
+    assert inside_any
+    # the point source sees the particle wider than the plane wave, and the
+    # width tends to the plane wave's as 1/z_s when the source recedes
+    L0 = O.grid_halfwidth(part)
+    assert L > L0
+    ex = [O.grid_halfwidth(part, z) / L0 - 1 for z in (1e7, 1e9, 1e13)]
+    assert ex[1] / ex[0] == pytest.approx(1e-2, rel=1e-3)
+    assert abs(ex[2]) < 1e-11
 
 
 def test_far_source_converges_to_the_plane_wave():
