@@ -848,16 +848,22 @@ struct WaveStage {
 
 // Per-block LDS area of the rasteriser: the triangles of the block's 256 quads
 // that have candidates (at most two per quad), shared by its four waves; the
-// queue of triangles to load shares the slot storage.
-constexpr int BLOCK_SLOTS = 512;
+// queue of triangles to load shares the slot storage.  The mixed path stages
+// all 512 at once; the FP64 path's slots are 96 bytes, so it stages and drains
+// 256 at a time (five blocks per CU instead of three).
+template <typename G>
+struct BlockSlots {
+  static constexpr int value = sizeof(G) == 8 ? 256 : 512;
+  static constexpr int log2 = sizeof(G) == 8 ? 8 : 9;
+};
 template <typename G>
 struct BlockStage {
   union {
-    TriSlot<G> tri[BLOCK_SLOTS];
-    TriQueued queued[BLOCK_SLOTS];
+    TriSlot<G> tri[BlockSlots<G>::value];
+    TriQueued queued[512];
   };
-  int excl[BLOCK_SLOTS];  // exclusive prefix of the slots' candidate counts (unused slots: the block total)
-  int wave_q[4];          // queued triangles of each wave
+  int excl[BlockSlots<G>::value];  // exclusive prefix of the slots' candidate counts (unused slots: the total)
+  int wave_q[4];                   // queued triangles of each wave
 };
 
 // What the candidate loop needs of a stage: 2^log_slots slots with their
@@ -876,7 +882,7 @@ __device__ __forceinline__ StageView<G> view(WaveStage<G>& W) {
 
 template <typename G>
 __device__ __forceinline__ StageView<G> view(BlockStage<G>& S) {
-  return StageView<G>{S.tri, S.excl, 9};
+  return StageView<G>{S.tri, S.excl, BlockSlots<G>::log2};
 }
 
 // Candidate g of the stage: its triangle and node (row it, column ip).
@@ -1111,14 +1117,27 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
       }
       if (!fits && r > 0) n = c.count();  // list full: rasterise the whole box here (slow but exact)
     }
-    if (n > 0) slot_put(S.tri[k], T, c);
+    constexpr bool all_at_once = BlockSlots<G>::value == 512;
+    const int sk = all_at_once ? k : (int)threadIdx.x;
+    if (n > 0) slot_put(S.tri[sk], T, c);
     int it_total;
-    S.excl[k] = block_total + block_excl_scan(n, &it_total, S.wave_q);
-    block_total += it_total;
+    const int ex = block_excl_scan(n, &it_total, S.wave_q);
+    if constexpr (all_at_once) {
+      S.excl[k] = block_total + ex;
+      block_total += it_total;
+    } else {
+      // this half's triangles: drain them before the next half takes the slots
+      S.excl[threadIdx.x] = ex;
+      __syncthreads();
+      raster_drain(rec, ng, pool, view(S), it_total, wave, 4, wave_partition());
+      __syncthreads();
+    }
   }
-  if (n_iter == 1) S.excl[256 + threadIdx.x] = block_total;
-  __syncthreads();
-  raster_drain(rec, ng, pool, view(S), block_total, wave, 4, wave_partition());
+  if constexpr (BlockSlots<G>::value == 512) {
+    if (n_iter == 1) S.excl[256 + threadIdx.x] = block_total;
+    __syncthreads();
+    raster_drain(rec, ng, pool, view(S), block_total, wave, 4, wave_partition());
+  }
 }
 
 // One thread per listed (triangle, theta row).  A large triangle's rows sit
