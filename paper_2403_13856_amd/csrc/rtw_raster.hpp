@@ -1022,14 +1022,16 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
     const long rb = B.n_ord * (B.ray_off[p] - B.ray_base) + (long)slot * NN;
     const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
     const long v00 = (long)iy * N + ix;
+    // flags and vertex angles are loaded together: one memory round trip per
+    // block instead of two (the angles of an invalid quad are not used)
+    const float2* an = rec.ang + rb;
     const int f0 = rec.flags[rb + v00], f1 = rec.flags[rb + v00 + 1];
     const int f2 = rec.flags[rb + v00 + N], f3 = rec.flags[rb + v00 + N + 1];
+    const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + N], a11 = an[v00 + N + 1];
     const int nf0 = f0 >> 1 & 127;
     const bool tv0 = (f0 & 1) && (f1 & 1) && (f3 & 1) && nf0 == (f1 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
     const bool tv1 = (f0 & 1) && (f2 & 1) && (f3 & 1) && nf0 == (f2 >> 1 & 127) && nf0 == (f3 >> 1 & 127);
     if (tv0 || tv1) {
-      const float2* an = rec.ang + rb;
-      const float2 a00 = an[v00], a01 = an[v00 + 1], a10 = an[v00 + N], a11 = an[v00 + N + 1];
       if (tv0) {
         fast0 = fast_box(ng, axt, axp, a00, a01, a11, (float)margin, c0);
         need0 = !fast0 || c0.count() > 0;
