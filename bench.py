@@ -316,6 +316,44 @@ def bench_paper_spheroid(args, rtw, inputs):
     print(json.dumps(result), flush=True)
 
 
+def bench_large(args, rtw, inputs):
+    """The large scatterer: ellipsoid 1000/950/900 um (size parameter ~10^4),
+    axis-aligned, m=1.333, p=0..5, 8192^2 rays, theta 0..180 with the rainbow
+    band 120..170 at 0.02 deg, phi 0..359.5 step 0.5, x-polarised, mixed.
+    One step = one rtw_farfield call.  The active rays (those meeting the
+    particle) are counted from the shadow ellipse x^2/a^2 + y^2/b^2 < 1 of the
+    axis-aligned particle on the cell-centred grid."""
+    import numpy as np
+    import torch
+    w = inputs.large_ellipsoid(args.large_grid_n)
+    N = w.grid_n
+    a, b, c = w.semi_axes
+    L = max(a, b)  # the grid half-width of an axis-aligned particle
+    h = 2 * L / N
+    u = -L + (np.arange(N) + 0.5) * h
+    n_active = 0
+    for r0 in range(0, N, 512):
+        y = u[r0:r0 + 512, None]
+        n_active += int(((u[None, :] / a) ** 2 + (y / b) ** 2 < 1.0).sum())
+    log(f"[large] {N}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} nodes, p={w.p_min}..{w.p_max}")
+    ms, prof, hits, fp64_rays = time_path(rtw, w, N, rtw.MIXED, args.steps, args.warmup)
+    log(f"[large] mixed: {ms:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
+    for k, (t, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
+    result = {
+        "metric": "rays/s (p<=5) mixed, large ellipsoid", "value": round(n_active / (ms * 1e-3), 1),
+        "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"ellipsoid 1000/950/900 um, Euler (0,0,0), m=1.333, lambda=0.6328 um, p=0..5, "
+                               f"{N}x{N} rays, {w.theta_deg.size}x{w.phi_deg.size} nodes (rainbow band 0.02 deg), "
+                               f"x-polarised, mixed",
+                   "active_rays": n_active, "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
+                   "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof.items()}},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def bench_surrogate(args, rtw, inputs):
     """Surrogate of the batched workload: train the BF16 MLP on cell-averaged
     ln-intensities that rtw_batch computes for seeded particles (cells 5 x 10
@@ -536,14 +574,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
-    ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate", "paper_spheroid"], default="ellipsoid",
+    ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate", "paper_spheroid", "large"],
+                    default="ellipsoid",
                     help="ellipsoid: the 2048^2-ray ellipsoid (default); batch: 4096 seeded ellipsoids via rtw_batch; "
                          "surrogate: train the MLP on rtw_batch data, then time 1M queries with RTW fallback; "
-                         "paper_spheroid: the paper's spheroid on the whole sphere at 0.01 deg")
+                         "paper_spheroid: the paper's spheroid on the whole sphere at 0.01 deg; "
+                         "large: the 1000 um ellipsoid, p<=5, 8192^2 rays")
     ap.add_argument("--train-steps", type=int, default=40000)
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--spheroid-grid-n", type=int, default=3456)
     ap.add_argument("--spheroid-bands", type=int, default=16)
+    ap.add_argument("--large-grid-n", type=int, default=8192)
     ap.add_argument("--source-distance", type=float, default=0.0,
                     help="ellipsoid workload lit by a point source at lab (0, 0, -z) instead of the plane wave (um)")
     args = ap.parse_args()
@@ -576,6 +617,8 @@ def main():
         return bench_surrogate(args, rtw, inputs)
     if args.workload == "paper_spheroid":
         return bench_paper_spheroid(args, rtw, inputs)
+    if args.workload == "large":
+        return bench_large(args, rtw, inputs)
     w = inputs.ellipsoid_mixed(args.grid_n)
     zs = args.source_distance
     n_active, n_tri = count_units(rtw, w, args.grid_n, zs)
