@@ -281,6 +281,30 @@ def test_uniform_axis_boxes_match_segment_tables(R):
             assert np.array_equal(F[:, :, it][:, :, :, ip], F_u)
 
 
+def test_three_run_axis_boxes_match_segment_tables(R):
+    # An axis of three uniform runs (a refined band, as on the large
+    # workload's theta grid) and the same axis with one off-grid node more
+    # (five runs) index their boxes through the segment tables with different
+    # runs.  Boxes only prune, so every shared node must come out bitwise alike.
+    w = I.ellipsoid_mixed()
+    th_3 = np.concatenate([I.uniform_angles(0.0, 119.5, 0.5), I.uniform_angles(120.0, 140.0, 0.02),
+                           I.uniform_angles(140.5, 180.0, 0.5)])
+    ph_u = I.uniform_angles(0.0, 359.0, 1.0)
+    th_x = np.sort(np.append(th_3, 60.3))
+    it = np.searchsorted(th_x, th_3)
+    assert np.array_equal(th_x[it], th_3)
+    for prec in (R.MIXED, R.FP64):
+        gp = R.make_particle(w.semi_axes, w.euler_deg, w.m)
+        gi = R.make_incident(w.wavelength, 2)
+        go = R.make_opts(0, 3, 512, prec)
+        F3, nc3, _ = _farfield_gpu(R, gp, gi, go, th_3, ph_u)
+        Fx, ncx, _ = _farfield_gpu(R, gp, gi, go, th_x, ph_u)
+        say(f"[three-run axis] precision={prec}: {int(nc3.sum())} contributions")
+        assert nc3.sum() > 0
+        assert np.array_equal(ncx[it], nc3)
+        assert np.array_equal(Fx[:, :, it], F3)
+
+
 def test_paper_spheroid_strips_match_oracle(oracle, R):
     """The paper's spheroid (a=b=100, c=90 um, incidence along its x axis) at its
     full ray count and the paper's 0.01 deg node spacing, on strips across the
