@@ -1012,14 +1012,24 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
   bool need0 = false, need1 = false, fast0 = false, fast1 = false;
   int p = s_p0;
   long quad = 0;
+  // the block's first particle: its metadata in one round of independent loads
+  const long qend0 = B.quad_off[p + 1] - B.quad_base;
+  const int N0 = B.P[p].N;
+  const long qoff0 = B.quad_off[p] - B.quad_base, roff0 = B.ray_off[p] - B.ray_base;
   if (gq < n_quads) {
-    while (B.quad_off[p + 1] - B.quad_base <= gq) ++p;  // a block spans few particles
-    const int N = B.P[p].N;
-    const long qoff = B.quad_off[p] - B.quad_base;
+    int N = N0;
+    long qoff = qoff0, roff = roff0;
+    if (gq >= qend0) {  // a block spans few particles
+      ++p;
+      while (B.quad_off[p + 1] - B.quad_base <= gq) ++p;
+      N = B.P[p].N;
+      qoff = B.quad_off[p] - B.quad_base;
+      roff = B.ray_off[p] - B.ray_base;
+    }
     quad = gq - qoff;
     const int Nq = N - 1;
     const long NN = (long)N * N;
-    const long rb = B.n_ord * (B.ray_off[p] - B.ray_base) + (long)slot * NN;
+    const long rb = B.n_ord * roff + (long)slot * NN;
     const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
     const long v00 = (long)iy * N + ix;
     // flags and vertex angles are loaded together: one memory round trip per
@@ -1086,10 +1096,11 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
     if (k < nq) {
       const TriQueued& e = mine[h];
       const int t = e.tf & 1, pp = e.part;
-      const int N = B.P[pp].N;
-      const long qoff = B.quad_off[pp] - B.quad_base;
+      const bool first = pp == s_p0;  // the block's first particle: metadata already in registers
+      const int N = first ? N0 : B.P[pp].N;
+      const long qoff = first ? qoff0 : B.quad_off[pp] - B.quad_base;
       const long nq2 = (long)(N - 1) * (N - 1);
-      const long rb = B.n_ord * (B.ray_off[pp] - B.ray_base) + (long)slot * N * N;
+      const long rb = B.n_ord * (first ? roff0 : B.ray_off[pp] - B.ray_base) + (long)slot * N * N;
       tri_load(rec, rb, N, (long)e.quad, t, tri_key(B.n_ord, qoff, slot, nq2, (long)e.quad, t), pp, T);
       if (T.orient != 0) {
         if (e.tf & 2) {
