@@ -74,15 +74,17 @@ struct alignas(16 * sizeof(G)) RayRec {
 // (e_theta, e_phi) of a direction d (not necessarily of unit length, as
 // stored): with rho = |(dx, dy)|, cos phi = dx / rho, sin phi = dy / rho
 // (phi = 0 on the axis), e_theta = (dz cos phi, dz sin phi, -rho) and
-// e_phi = (-sin phi, cos phi, 0).  Both the writer and the reader of a record
-// evaluate it in FP64 from the same stored direction, so they agree exactly.
+// e_phi = (-sin phi, cos phi, 0).  1 / rho from the reciprocal square root
+// (rsq_d: about one ulp).  Both the writer and the reader of a record evaluate
+// it in FP64 from the same stored direction, so they agree exactly.
 __device__ __forceinline__ void dir_basis(double dx, double dy, double dz, v3<double>& et, v3<double>& ep) {
-  const double rho = sqrt(dx * dx + dy * dy);
-  double cp = 1.0, sp = 0.0;
-  if (rho > 0.0) {
-    const double r = 1.0 / rho;
+  const double rho2 = dx * dx + dy * dy;
+  double cp = 1.0, sp = 0.0, rho = 0.0;
+  if (rho2 > 1e-300) {
+    const double r = rsq_d(rho2);
     cp = dx * r;
     sp = dy * r;
+    rho = rho2 * r;
   }
   et = mk3<double>(dz * cp, dz * sp, -rho);
   ep = mk3<double>(-sp, cp, 0.0);
