@@ -50,6 +50,12 @@ __device__ __forceinline__ double rsq_d(double x) {
   return fma(y, e, y);
 }
 __device__ __forceinline__ double rsq(double x) { return rsq_d(x); }
+// sqrt(x) = x / sqrt(x) for x >= 0 from rsq_d (0 for x = 0)
+__device__ __forceinline__ double sqrt_d(double x) { return x > 0.0 ? x * rsq_d(x) : 0.0; }
+// 1 / x of the wave quantities: the hardware reciprocal in FP32 (1 ulp; the
+// arguments here are normal numbers of order 1 to 10), rcp_d in FP64
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return rcp_d(x); }
 __device__ __forceinline__ float sqr_t(float x) { return __fsqrt_rn(x); }
 __device__ __forceinline__ double sqr_t(double x) { return sqrt(x); }
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -200,7 +206,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   double qa = dot(d, Ad0), qb = 2.0 * dot(d, Ao), qc = dot(o, Ao) - 1.0;
   double disc = qb * qb - 4.0 * qa * qc;
   if (!(disc > 0.0)) return;
-  double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
+  double qq = -0.5 * (qb + copysign(sqrt_d(disc), qb));
   if (qq == 0.0) return;
   double t = fmin(qq / qa, qc / qq);
 
@@ -270,7 +276,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     double ct = 0.0, gt = 0.0;
     V dt = d;
     if (!tir) {
-      ct = sqrt(ct2);
+      ct = sqrt_d(ct2);
       const double sct = sgn * ct, im = rcp_d(mrel);
       dt = mk3((d.x - dn * nh.x) * im + sct * nh.x, (d.y - dn * nh.y) * im + sct * nh.y,
                (d.z - dn * nh.z) * im + sct * nh.z);
@@ -282,7 +288,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       const G cig = (G)ci, mg = (G)mrel, m2 = mg * mg;
       if (!tir) {
         const G b = (G)(mrel * ct);  // k_rn / (n_cur k)
-        const G inv1 = 1 / (cig + b), inv2 = 1 / (m2 * cig + b);
+        const G inv1 = rcp_t(cig + b), inv2 = rcp_t(m2 * cig + b);
         rp.re = (cig - b) * inv1;  rp.im = 0;
         rl.re = (m2 * cig - b) * inv2;  rl.im = 0;
         tp.re = 2 * cig * inv1;  tp.im = 0;
@@ -316,7 +322,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       const G ko = (G)kod;
       const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
       const V dout = emit_t ? dt : dr;
-      const G inko = 1 / ko, igo = (G)rcp_d(god);
+      const G inko = rcp_t(ko), igo = (G)rcp_d(god);
       const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
       double Q11 = (double)(a11 * inko);
       double Q12 = (double)(a12 * inko * igo);
@@ -334,7 +340,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
         e_amplif = fmax(e_amplif, (t11a * fabs(b22) + fabs(b11) * t22a + 2.0 * t12a * fabs(b12)) /
                                       fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
       }
-      double amp = sqrt(D * rcp_d(fabs(detQ)));
+      double amp = sqrt_d(D * rcp_d(fabs(detQ)));
       V epo = cross(dout, ep);  // e_par' of the outgoing wave
       // lab vectors: direction rounded once to G; the phase uses exactly that vector
       v3<G> dl = mk3<G>((G)(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z),
@@ -383,7 +389,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     const double god = cont_t ? gt : gr;
     const G ko = (G)kod;
     const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
-    const G inko = 1 / ko, igo = (G)rcp_d(god);
+    const G inko = rcp_t(ko), igo = (G)rcp_d(god);
     const G Q11 = (M11i + w * C11) * inko;
     const G Q12 = (M12i + w * C12) * inko * igo;
     const G Q22 = (M22i + w * C22) * inko * igo * igo;
