@@ -676,6 +676,25 @@ def main():
         cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
                    sample=f"full workload ({args.grid_n}^2 rays, all {w.n_nodes} nodes), one run, {dt:.1f} s")
         log(f"[bench] cpu oracle: {dt:.1f} s on {oracle.get_threads()} threads")
+        # the same oracle on one thread, over a bounded sample: the same
+        # particle and node grid at 512^2 rays (its active rays counted from
+        # the oracle's own trace)
+        n1 = 512
+        cores = oracle.get_threads()
+        oracle.set_threads(1)
+        try:
+            op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
+            st1 = oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, n1, source_distance=zs)
+            act1 = int((oracle.trace_grid(op, oracle.setup(w.wavelength, 1, 0, 0, n1, source_distance=zs))["flags"][0]
+                        & 1).sum())
+            t0 = time.perf_counter()
+            oracle.farfield(op, st1, w.theta_deg, w.phi_deg)
+            dt1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(cores)
+        cpu["one_thread"] = dict(value=round(act1 / dt1, 1), unit="rays/s", cores=1,
+                                 sample=f"{n1}^2 rays ({act1} active), all {w.n_nodes} nodes, one run, {dt1:.1f} s")
+        log(f"[bench] cpu oracle, one thread: {dt1:.1f} s for {n1}^2 rays")
 
     out = {
         "metric": "rays/s (p<=3) mixed vs FP64 at 1e-4 rel",
