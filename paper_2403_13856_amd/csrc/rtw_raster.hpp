@@ -17,10 +17,13 @@
 // triangles sharing an edge see the same value and exactly one of them claims
 // a node on it (the one on the edge's positive side on an exact tie).
 //
-// Hits are appended to a pool with one atomic per wave per step (wave ballot)
-// on one of NPART counters; each hit is pushed on its node's list with an
-// atomic exchange.  No floating-point atomics are used: the per-node kernel
-// sorts the node's hits by triangle key and sums them in that order.
+// Hits are appended to a pool as descriptors with one atomic per wave per pass
+// (wave ballot) on one of NPART counters; each hit takes its rank among its
+// node's hits from the node's count atomic.  A scan of the counts gives each
+// node's range, the hit store places every hit's contribution at its range
+// start plus its rank, and the per-node kernel sorts the node's hits by
+// triangle key and sums them in that order.  No floating-point atomics are
+// used, so the sums are deterministic.
 #pragma once
 #include "rtw_device.hpp"
 
