@@ -202,7 +202,7 @@ __device__ __forceinline__ ParticleConst load_uniform(const ParticleConst* src) 
 // numbered particle by particle in launch order (largest particles first),
 // so the cheap items of small particles fill the tail.
 template <typename G>
-__global__ void __launch_bounds__(256, 3) k_trace_tiles(const BatchDev B, const Records<G> rec, unsigned* queue) {
+__global__ void __launch_bounds__(256, sizeof(G) == 8 ? 2 : 3) k_trace_tiles(const BatchDev B, const Records<G> rec, unsigned* queue) {
   __shared__ long s_item;
   const long n_items = B.tile_off[B.n] - B.tile_base;
   for (;;) {
