@@ -2,7 +2,9 @@
  * rtw.h -- C ABI of the MI355X-native Ray Theory of Waves library (librtw.so).
  *
  * Method: Ren et al., "Ray Theory of Waves" (arXiv 2403.13856).  A plane wave
- * travelling along lab +z meets one smooth ellipsoid.  A cell-centred square
+ * travelling along lab +z (or the spherical wave of a point source on the
+ * -z axis, see rtw_incident) meets one smooth ellipsoid, or each ellipsoid of
+ * a batch.  A cell-centred square
  * grid of incident rays is traced; every ray carries a 2x2 wavefront-curvature
  * (WFC) matrix updated at each reflection and refraction by the wavefront
  * equation (Eq. 3), its direction by vector Snell (Eq. 4) and its
@@ -21,8 +23,9 @@
  *   - time dependence exp(-i w t); the far field F(theta, phi) is
  *     lim r exp(-ikr) E(r) / E0, in micrometres, projected on (e_theta, e_phi);
  *     |F|^2 is the differential cross-section (um^2/sr) of the summed orders;
- *   - ray grid: N x N cell-centred over [-L, L]^2, L = max(sqrt(S_xx),
- *     sqrt(S_yy)), S = R diag(a^2, b^2, c^2) R^T; ray index iy*N + ix;
+ *   - ray grid: N x N cell-centred over [-L, L]^2 of the plane z = 0,
+ *     L = max(sqrt(S_xx), sqrt(S_yy)), S = R diag(a^2, b^2, c^2) R^T, for the
+ *     plane wave (for a point source: see rtw_incident); ray index iy*N + ix;
  *   - every device pointer is caller-owned; the library never allocates or
  *     frees caller memory.  All calls are asynchronous on the given HIP stream
  *     (NULL = default stream); argument errors are returned immediately.
@@ -47,8 +50,11 @@ extern "C" {
 #define RTW_ERR_DEVICE (-4)
 
 #define RTW_FP64 0  /* every step in double precision */
-#define RTW_MIXED 1 /* FP32 geometry, Fresnel and WFC; FP64 positions, path length,
-                       phase reduction, divergence factor and caustic Jacobian */
+#define RTW_MIXED 1 /* FP32 wave quantities (Fresnel, Jones, WFC, fields) and far-field
+                       assembly; FP64 polyline (positions, directions, Snell, chords),
+                       path length, phase reduction, divergence factor and caustic
+                       Jacobian; rays with an ill-conditioned divergence factor are
+                       traced again in FP64 */
 
 #define RTW_MAX_ORDER 15
 
