@@ -151,3 +151,20 @@ def test_surrogate_rejects_point_source_incidence():
         inc = rtw.make_incident(0.6328, 2, zs)
         rc = fn(1, ctypes.byref(part), ctypes.byref(inc), 1, th, ph, feats)
         assert rc == code, (zs, rc)
+
+
+def test_batch_rejects_a_source_inside_one_particle():
+    """Every particle of a batch is checked against the point source (host side)."""
+    L = rtw.load()
+    parts = (rtw.Particle * 2)(rtw.make_particle((30, 25, 20), (0, 0, 0), 1.333),
+                               rtw.make_particle((200, 150, 120), (10, 20, 30), 1.4))
+    sides = (ctypes.c_int * 2)(64, 64)
+    opts = rtw.make_opts(0, 3, 2, rtw.MIXED)
+    g = rtw.Grid(10, 1, 20, 1)
+    n = ctypes.c_size_t(0)
+    for zs, code in ((500.0, rtw.RTW_OK), (150.0, rtw.RTW_ERR_INVALID_ARG)):
+        inc = rtw.make_incident(0.6328, 2, zs)
+        rc = L.rtw_batch_workspace_size(2, parts, sides, ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(g), None,
+                                        ctypes.byref(n))
+        assert rc == code, (zs, rc)
+    assert "source_distance" in L.rtw_last_error().decode()
