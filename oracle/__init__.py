@@ -27,7 +27,8 @@ class Particle(ctypes.Structure):
 
 class Setup(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("n_pol", ctypes.c_int), ("p_min", ctypes.c_int),
-                ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int), ("source_distance", ctypes.c_double)]
+                ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int), ("source_distance", ctypes.c_double),
+                ("observation_radius", ctypes.c_double)]
 
 
 class Emit(ctypes.Structure):
@@ -35,7 +36,7 @@ class Emit(ctypes.Structure):
                 ("dir", ctypes.c_double * 3), ("rexit", ctypes.c_double * 3), ("opl", ctypes.c_double),
                 ("phase", ctypes.c_double), ("amp", ctypes.c_double), ("D", ctypes.c_double),
                 ("q", ctypes.c_double * 3), ("eperp", ctypes.c_double * 3), ("epar", ctypes.c_double * 3),
-                ("jones", ctypes.c_double * 8), ("field", ctypes.c_double * 12)]
+                ("jones", ctypes.c_double * 8), ("field", ctypes.c_double * 12), ("obs", ctypes.c_double * 3)]
 
 
 class Ray(ctypes.Structure):
@@ -89,10 +90,12 @@ def particle(semi_axes, euler_deg=(0.0, 0.0, 0.0), m=1.333):
     return p
 
 
-def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64, source_distance=0.0):
-    """Trace settings; source_distance > 0 puts a point source at lab (0, 0, -source_distance)."""
+def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64, source_distance=0.0, observation_radius=0.0):
+    """Trace settings; source_distance > 0 puts a point source at lab (0, 0, -source_distance);
+    observation_radius > 0 observes on the sphere of that radius instead of the far field."""
     s = Setup()
     s.source_distance = float(source_distance)
+    s.observation_radius = float(observation_radius)
     s.wavelength = float(wavelength)
     s.n_pol = int(n_pol)
     s.p_min = int(p_min)

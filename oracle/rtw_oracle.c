@@ -58,6 +58,22 @@
  *      normalised, u_1, and u_2 = d x u_1.  The grid's half-width is the
  *      largest extent along x or y of the particle's tangent cone from S on
  *      the plane z = 0 (rtwo_grid_halfwidth_source).
+ *  R11 Observation at a finite distance (the point M of Eqs. 6 and 9): the
+ *      nodes lie on the sphere of radius R about the particle centre.  A ray
+ *      leaving r_exit along d meets it after d_M (|r_exit + d_M d| = R); the
+ *      last Gaussian-curvature ratio of Eq. 6 is 1/det(I + d_M Q'), so the
+ *      field there is A_0 |eps| sqrt(D / |det(I + d_M Q')|); N_f counts the
+ *      negative eigenvalues of I + d_M Q' on that leg; the path phase of Eq. 9
+ *      ends with k d_M.  The output is R e^{-ikR} E(M) (tending to the far
+ *      field F as R grows), so its phase is OPL + k (d_M - R) - N_f pi/2.
+ *      The ray's node-space direction is u = M / R; interpolation (R9) runs on
+ *      u, and each vertex field is carried to a node n along the sphere as a
+ *      wave leaving the ray's exit point, phase k (|R n - r_exit| - |R u -
+ *      r_exit|) (its gradient on the sphere at u is the ray's, and for
+ *      R -> infinity it tends to R9's -k r_exit.(n - u)).  Only the part of
+ *      E(M) tangent to the sphere at M is an output (the radial part, of
+ *      relative size |r_exit| / R, is dropped at the vertex); the output is its
+ *      projection on the node's (e_theta, e_phi).
  */
 #include "rtw_oracle.h"
 
@@ -204,6 +220,7 @@ typedef struct {
   double k;         /* 2 pi / lambda */
   double m;
   double zs;        /* point-source distance (0: plane wave) */
+  double robs;      /* observation radius (0: far field) */
   int n_pol, p_min, p_max;
 } ctx_t;
 
@@ -282,6 +299,23 @@ static void emit_order(const ctx_t* c, const ray_state* s, const double* dir, co
   double detQ = m2det(Qx);
   double S = sqrt(s->D / fabs(detQ));
   double phase = s->opl - c->k * dot3(dir, s->r) - nf_total * (PI / 2.0);
+  if (c->robs > 0.0) {
+    /* finite observation radius (reading R11) */
+    double dr = dot3(dir, s->r);
+    double dM = -dr + sqrt(dr * dr - dot3(s->r, s->r) + c->robs * c->robs);
+    mat2 G;
+    G.m[0][0] = 1.0 + dM * Qx.m[0][0];
+    G.m[0][1] = dM * Qx.m[0][1];
+    G.m[1][0] = dM * Qx.m[1][0];
+    G.m[1][1] = 1.0 + dM * Qx.m[1][1];
+    nf_total = s->nf + m2neg(G);
+    S = c->robs * sqrt(s->D / fabs(m2det(G)));
+    phase = s->opl + c->k * (dM - c->robs) - nf_total * (PI / 2.0);
+    double M[3] = {s->r[0] + dM * dir[0], s->r[1] + dM * dir[1], s->r[2] + dM * dir[2]};
+    double Ml[3];
+    matvec(c->R, M, Ml);
+    scale3(1.0 / c->robs, Ml, e->obs);
+  }
   e->valid = 1;
   e->nf = nf_total;
   e->det_neg = detQ < 0.0;
@@ -506,7 +540,9 @@ static int setup_ctx(const rtwo_particle* part, const rtwo_setup* st, ctx_t* c) 
   if (st->p_min < 0 || st->p_max < st->p_min || st->p_max > RTWO_MAX_ORDER) return -1;
   double amax = fmax(part->semi_axes[0], fmax(part->semi_axes[1], part->semi_axes[2]));
   if (!(st->source_distance == 0.0 || st->source_distance > amax)) return -1;
+  if (!(st->observation_radius == 0.0 || st->observation_radius > amax)) return -1;
   c->zs = st->source_distance;
+  c->robs = st->observation_radius;
   for (int i = 0; i < 3; i++) c->A[i] = 1.0 / (part->semi_axes[i] * part->semi_axes[i]);
   euler_zyz(part->euler_deg, c->R);
   c->k = 2.0 * PI / st->wavelength;
@@ -687,6 +723,7 @@ static void for_nodes_in_cap(const nodes_t* nd, const double* cdir, double rho, 
 typedef struct {
   const nodes_t* nd;
   const cray* v[3];      /* vertices in triangle order */
+  double kappa;          /* k R at a finite observation radius, 0 in the far field */
   long vid[3];           /* global ray ids (canonical edge orientation) */
   int n_pol;
   double* field;         /* accumulators */
@@ -737,7 +774,18 @@ static void tri_node(int node, void* user) {
     for (int k = 0; k < 3; k++) {
       const cray* v = J->v[k];
       double dn[3] = {n[0] - v->dir[0], n[1] - v->dir[1], n[2] - v->dir[2]};
-      cplx carry = cexp(-I * dot3(v->kr, dn));  /* stationary-phase gradient */
+      cplx carry;
+      if (J->kappa > 0.0) {
+        /* path difference from the exit point to R n and to R u (reading R11) */
+        double a[3], b[3];
+        for (int x = 0; x < 3; x++) {
+          a[x] = J->kappa * n[x] - v->kr[x];
+          b[x] = J->kappa * v->dir[x] - v->kr[x];
+        }
+        carry = cexp(I * (norm3(a) - norm3(b)));
+      } else {
+        carry = cexp(-I * dot3(v->kr, dn));  /* stationary-phase gradient */
+      }
       cplx vt = 0, vp = 0;
       for (int x = 0; x < 3; x++) { vt += v->f[p][x] * et[x]; vp += v->f[p][x] * ep[x]; }
       ft += lam[k] * carry * vt;
@@ -856,11 +904,19 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
         r->nf = e->nf;
         r->det_neg = e->det_neg;
         for (int x = 0; x < 3; x++) {
-          r->dir[x] = e->dir[x];
+          /* node-space direction: the exit direction, or at a finite radius
+             (R11) the direction of M */
+          r->dir[x] = c.robs > 0.0 ? e->obs[x] : e->dir[x];
           r->kr[x] = c.k * e->rexit[x];
         }
-        for (int p = 0; p < 2; p++)
+        for (int p = 0; p < 2; p++) {
           for (int x = 0; x < 3; x++) r->f[p][x] = e->field[p][x][0] + I * e->field[p][x][1];
+          if (c.robs > 0.0) {
+            /* the part tangent to the sphere at M */
+            cplx fr = r->f[p][0] * r->dir[0] + r->f[p][1] * r->dir[1] + r->f[p][2] * r->dir[2];
+            for (int x = 0; x < 3; x++) r->f[p][x] -= fr * r->dir[x];
+          }
+        }
       }
     }
   }
@@ -922,6 +978,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
           J.nd = &nd;
           for (int k = 0; k < 3; k++) { J.v[k] = V[k]; J.vid[k] = tris[t][k]; }
           J.n_pol = n_pol;
+          J.kappa = c.robs > 0.0 ? c.k * c.robs : 0.0;
           J.field = field;
           J.incoh = inc_buf;
           J.nflags = fl_buf;

@@ -41,6 +41,9 @@ typedef struct {
   int grid_n;        /* incident ray grid is grid_n x grid_n, cell centred */
   double source_distance; /* 0: plane wave along +z; > largest semi-axis: point source
                              at lab (0, 0, -source_distance), spherical wave (reading R10) */
+  double observation_radius; /* 0: far field; > largest semi-axis: the nodes lie on the
+                                sphere of this radius and the output is R e^{-ikR} E(M)
+                                (reading R11) */
 } rtwo_setup;
 
 /* Everything the oracle knows about one emitted order of one ray. */
@@ -60,6 +63,10 @@ typedef struct {
   double epar[3];  /* lab e_par' = dir x e_perp */
   double jones[2][2][2]; /* [perp|par][incident pol x|y][re|im], Fresnel product only */
   double field[2][3][2]; /* [pol][lab xyz][re|im] = amp e^{i phase} (J_perp e_perp + J_par e_par') */
+  double obs[3];   /* finite observation radius R: unit vector of the point where the ray
+                      meets the sphere of radius R (then amp, phase, nf and field refer to
+                      that point: amp = R sqrt(D / |det(I + d_M Q')|), phase = OPL + k (d_M - R)
+                      - nf pi/2); zero in the far field */
 } rtwo_emit;
 
 /* Per-ray trace: the interaction polyline and the WFC after each interaction. */
