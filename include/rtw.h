@@ -79,11 +79,28 @@ typedef struct {
  *     direction crossed with that.  The incident grid's half-width is the
  *     largest extent along lab x or y of the particle's tangent cone from the
  *     source on the plane z = 0.
- * Other values of source_distance: RTW_ERR_INVALID_ARG. */
+ * Observation (Eqs. 6 and 9 at the observation point M):
+ *   observation_radius = 0: far field; the nodes are directions and the
+ *     output is the far-field amplitude F (um).
+ *   observation_radius = R > largest semi-axis of every particle: the nodes
+ *     lie on the sphere of radius R about the particle centre.  Each ray is
+ *     continued from its exit point r to the point M where it meets the
+ *     sphere (d_M further); its divergence factor there is
+ *     R sqrt(D / |det(I + d_M Q')|), its focal-line count includes the
+ *     negative eigenvalues of I + d_M Q', its phase is OPL + k (d_M - R)
+ *     - N_f pi/2.  The output is R e^{-ikR} times the tangential part of E(M)
+ *     on the node's (e_theta, e_phi) (R -> infinity gives F).  Triangles are
+ *     interpolated over the directions of M, each vertex carried to a node n
+ *     by k (|R n - r| - |R u - r|) (u the vertex's direction of M).  The
+ *     per-ray records of rtw_trace report amp, phase, focal lines and field
+ *     at M; dir and rexit stay the exit direction and point.
+ * Other values of source_distance or observation_radius:
+ * RTW_ERR_INVALID_ARG. */
 typedef struct {
   double wavelength;      /* in the surrounding medium (um) */
   int n_pol;              /* 1: x polarisation only; 2: x and y */
   double source_distance; /* 0: plane wave; z_s (um): point source, see above */
+  double observation_radius; /* 0: far field; R (um): nodes on the sphere of radius R */
 } rtw_incident;
 
 typedef struct {

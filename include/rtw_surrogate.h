@@ -106,8 +106,8 @@ int rtw_surrogate_train_step(rtw_surrogate* h, int n, const float* feats, const 
 
 /* Host-side features of every (particle, cell centre) pair: feats[p][c][9]
  * (HOST), cell centres given in degrees.  The surrogate models plane-wave
- * incidence: here and in rtw_surrogate_query a non-zero inc->source_distance
- * gives RTW_ERR_UNSUPPORTED. */
+ * incidence and the far field: here and in rtw_surrogate_query a non-zero
+ * inc->source_distance or inc->observation_radius gives RTW_ERR_UNSUPPORTED. */
 int rtw_surrogate_features(int n_part, const rtw_particle* parts, const rtw_incident* inc, int n_cell,
                            const double* cell_theta_deg, const double* cell_phi_deg, float* feats);
 

@@ -125,7 +125,22 @@ struct ParticleConst {
   int p_min, p_max, n_pol;
   double amplif_limit;  // mixed path: FP64 re-trace above this error amplification
   double zs;     // point-source distance on the lab -z axis (um); 0: plane wave
+  double robs;   // observation radius (um); 0: far field
 };
+
+// Observation at a finite radius R (kappa = k R): a wave leaving the exit
+// point r (kr = k r) gains k (|R n - r| - |R u - r|) between the directions u
+// and n on the sphere.  For unit u and n that equals
+// kr.(u - n) * 2 kappa / (|kappa n - kr| + |kappa u - kr|), free of the
+// cancellation of the plain difference; this returns the factor, 1 in the far
+// field (kappa = 0), where the carry is kr.(u - n).
+__device__ __forceinline__ double near_scale(double kappa, double krx, double kry, double krz, double ux, double uy,
+                                             double uz, double nx, double ny, double nz) {
+  if (kappa == 0.0) return 1.0;
+  const double ax = kappa * nx - krx, ay = kappa * ny - kry, az = kappa * nz - krz;
+  const double bx = kappa * ux - krx, by = kappa * uy - kry, bz = kappa * uz - krz;
+  return 2.0 * kappa / (sqrt(ax * ax + ay * ay + az * az) + sqrt(bx * bx + by * by + bz * bz));
+}
 
 // Two-constant Cody-Waite reduction of x modulo 2 pi in FP64 (Cody & Waite,
 // Software Manual for the Elementary Functions, 1980).  TWO_PI_HI keeps 31
@@ -154,9 +169,12 @@ struct Emission {
   int nf;              // focal lines, far-field leg included
   int det_neg;         // det Q' < 0
   v3<G> dir;           // lab exit direction (the phase is computed with exactly this vector)
+  v3<G> obs;           // node-space direction: dir in the far field, else the direction of the
+                       // point M where the ray meets the observation sphere (the phase refers
+                       // to exactly this vector)
   v3<double> rexit;    // lab exit point (um)
-  double phase;        // OPL - k dir.rexit - nf pi/2, unreduced
-  double amp;          // sqrt(D / |det Q'|)
+  double phase;        // OPL - k dir.rexit - nf pi/2, unreduced; at radius R: OPL + k (d_M - R) - nf pi/2
+  double amp;          // sqrt(D / |det Q'|); at radius R: R sqrt(D / |det(I + d_M Q')|)
   double amplif;       // error amplification of the divergence factor along this ray (>= 1)
   double drift;        // growth of a direction perturbation along the ray: prod of the largest |eig(I + L Q)|
   cx<G> f[2][3];       // lab field vectors amp e^{i phase} (J_perp e_perp + J_par e_par)
@@ -341,6 +359,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
                                       fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
       }
       double amp = sqrt_d(D * rcp_d(fabs(detQ)));
+      v3<G> ul;
       V epo = cross(dout, ep);  // e_par' of the outgoing wave
       // lab vectors: direction rounded once to G; the phase uses exactly that vector
       v3<G> dl = mk3<G>((G)(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z),
@@ -349,6 +368,34 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       V rl_lab = mk3(R[0] * r.x + R[1] * r.y + R[2] * r.z, R[3] * r.x + R[4] * r.y + R[5] * r.z,
                      R[6] * r.x + R[7] * r.y + R[8] * r.z);
       double phase = opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
+      ul = dl;
+      if (P.robs > 0.0) {
+        // finite observation radius: continue the ray by d_M to M on the
+        // sphere; the last leg's divergence factor is 1 / det(I + d_M Q')
+        const double drr = dot(dout, r);
+        const double dM = -drr + sqrt_d(drr * drr - dot(r, r) + P.robs * P.robs);
+        const double g11 = 1.0 + dM * Q11, g12 = dM * Q12, g22 = 1.0 + dM * Q22;
+        const double detG = g11 * g22 - g12 * g12;
+        nft = nf + neg_eigs(g11, g12, g22);
+        amp = P.robs * sqrt_d(D * rcp_d(fabs(detG)));
+        // Q' carries the error amplified so far; det(I + d_M Q') scales it
+        // again, by half its entry-wise condition (1 away from a caustic at
+        // M, where the sum is about twice |det|)
+        e_amplif *= fmax(1.0, 0.5 * (fabs(dM * Q11) * fabs(g22) + fabs(g11) * fabs(dM * Q22) + 2.0 * dM * dM * Q12 * Q12) /
+                                  fmax(fabs(detG), 1e-300));
+        phase = opl + P.k * (dM - P.robs) - nft * 1.5707963267948966;
+        const V Mb = mk3(r.x + dM * dout.x, r.y + dM * dout.y, r.z + dM * dout.z);
+        const double ir = rcp_d(P.robs);
+        const V u = mk3((R[0] * Mb.x + R[1] * Mb.y + R[2] * Mb.z) * ir, (R[3] * Mb.x + R[4] * Mb.y + R[5] * Mb.z) * ir,
+                        (R[6] * Mb.x + R[7] * Mb.y + R[8] * Mb.z) * ir);
+        ul = mk3<G>((G)u.x, (G)u.y, (G)u.z);
+        // refer the phase to the rounded direction, as the far field does: the
+        // carry from u to (G)u, whose near_scale is R / d_M to second order in
+        // the rounding
+        if (sizeof(G) < 8)
+          phase += P.k * (rl_lab.x * (u.x - (double)ul.x) + rl_lab.y * (u.y - (double)ul.y) +
+                          rl_lab.z * (u.z - (double)ul.z)) * (P.robs * rcp_d(dM));
+      }
       G sph, cph;
       if (sizeof(G) == 8) sincos_t((G)phase, &sph, &cph);
       else sincos_t((G)reduce_2pi(phase), &sph, &cph);
@@ -366,6 +413,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       e.nf = nft;
       e.det_neg = detQ < 0.0;
       e.dir = dl;
+      e.obs = ul;
       e.rexit = rl_lab;
       e.phase = phase;
       e.amp = amp;

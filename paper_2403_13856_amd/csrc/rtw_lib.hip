@@ -95,6 +95,9 @@ int check_particle(const rtw_particle* p, const rtw_incident* inc, const rtw_tra
   const double amax = std::max(p->semi_axes[0], std::max(p->semi_axes[1], p->semi_axes[2]));
   if (!(inc->source_distance == 0.0 || (inc->source_distance > amax && std::isfinite(inc->source_distance))))
     return fail(RTW_ERR_INVALID_ARG, "source_distance must be 0 (plane wave) or beyond the largest semi-axis");
+  if (!(inc->observation_radius == 0.0 ||
+        (inc->observation_radius > amax && std::isfinite(inc->observation_radius))))
+    return fail(RTW_ERR_INVALID_ARG, "observation_radius must be 0 (far field) or beyond the largest semi-axis");
   if (o->p_min < 0 || o->p_max < o->p_min) return fail(RTW_ERR_INVALID_ARG, "need 0 <= p_min <= p_max");
   if (o->p_max > RTW_MAX_ORDER) return fail(RTW_ERR_UNSUPPORTED, "p_max > %d", RTW_MAX_ORDER);
   if (o->grid_n < 2 || o->grid_n > 16384) return fail(RTW_ERR_INVALID_ARG, "grid_n must be in [2, 16384]");
@@ -124,6 +127,7 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   }
   P.L = std::max(std::sqrt(sxx), std::sqrt(syy));
   P.zs = inc->source_distance;
+  P.robs = inc->observation_radius;
   if (P.zs > 0.0) {
     // Point source S = (0, 0, -zs): the grid spans the particle's tangent cone
     // from S on the plane z = 0.  With D = X - S the cone is D^T K D = 0,
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(256, sizeof(G) == 8 ? 2 : 3) k_trace_tiles(con
       bool redo = false;
       if (id < last) {
         for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
-        RecordSink<G> sink{rec, rbase, NN, id, P.k, P.amplif_limit, false};
+        RecordSink<G> sink{rec, rbase, NN, id, P.k, P.amplif_limit, false, P.k * P.robs};
         const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
         trace_ray<G>(P, ix, iy, sink);
         redo = sink.need64;
@@ -256,7 +260,7 @@ __global__ void __launch_bounds__(256) k_retrace64(const BatchDev B, const Recor
     const long id = g - (B.ray_off[p] - B.ray_base);
     const long rbase = B.n_ord * (B.ray_off[p] - B.ray_base);
     for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
-    RecordSink<float> sink{rec, rbase, NN, id, P.k, 0.0, false};
+    RecordSink<float> sink{rec, rbase, NN, id, P.k, 0.0, false, P.k * P.robs};
     const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
     trace_ray<double>(P, ix, iy, sink);
   }
@@ -677,6 +681,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   ng.sph = (double*)(ws + L.sph); ng.cph = (double*)(ws + L.cph);
   ng.seg_t = (const AxisSeg*)(ws + L.seg);
   ng.seg_p = (const AxisSeg*)(ws + L.seg) + 1;
+  ng.kappa = pl.P[0].k * pl.P[0].robs;  // one incident set-up for every particle of a call
   float* tf = (float*)(ws + L.tf);
   ng.sthf = tf; ng.cthf = tf + grid->n_theta;
   ng.sphf = tf + 2 * grid->n_theta; ng.cphf = tf + 2 * grid->n_theta + grid->n_phi;

@@ -824,6 +824,7 @@ int rtw_surrogate_features(int n_part, const rtw_particle* parts, const rtw_inci
     return mfail(RTW_ERR_INVALID_ARG, "bad arguments");
   if (!(inc->wavelength > 0.0)) return mfail(RTW_ERR_INVALID_ARG, "wavelength must be positive");
   if (inc->source_distance != 0.0) return mfail(RTW_ERR_UNSUPPORTED, "the surrogate models plane-wave incidence");
+  if (inc->observation_radius != 0.0) return mfail(RTW_ERR_UNSUPPORTED, "the surrogate models the far field");
   const double k = 2.0 * 3.14159265358979323846 / inc->wavelength;
   for (int p = 0; p < n_part; ++p) {
     const double* s = parts[p].semi_axes;
@@ -879,6 +880,7 @@ int rtw_surrogate_query(rtw_surrogate* h, int n_query, const float* feats, const
   if (opts->precision != RTW_MIXED || inc->n_pol != 2)
     return mfail(RTW_ERR_UNSUPPORTED, "the fallback runs the mixed path with two polarisations");
   if (inc->source_distance != 0.0) return mfail(RTW_ERR_UNSUPPORTED, "the surrogate models plane-wave incidence");
+  if (inc->observation_radius != 0.0) return mfail(RTW_ERR_UNSUPPORTED, "the surrogate models the far field");
   size_t need_bytes = 0;
   int rc = rtw_surrogate_query_scratch_size(n_part, parts, grid_n, inc, opts, grid, cells, &need_bytes);
   if (rc) return rc;

@@ -56,6 +56,7 @@ struct NodeGrid {
   const float* cphf;
   const AxisSeg* seg_t;
   const AxisSeg* seg_p;
+  double kappa;       // k R for nodes on the sphere of radius R; 0: far field
 };
 
 // One ray's emission record for one order, contiguous so that the three
@@ -189,6 +190,7 @@ struct RecordSink {
   double k;
   double amplif_limit;
   bool need64;
+  double kappa;  // k R at a finite observation radius, 0 in the far field
   template <typename E>
   __device__ void emit(const Emission<E>& e) {
     if (sizeof(E) == 4 && e.amplif > amplif_limit) need64 = true;
@@ -196,7 +198,7 @@ struct RecordSink {
     rec.flags[at] = 1 | (e.nf << 1) | (e.det_neg << 8);
     RayRec<G> r;
     Dir4<G> dv;
-    dv.x = (G)e.dir.x; dv.y = (G)e.dir.y; dv.z = (G)e.dir.z; dv.pad = (G)0;
+    dv.x = (G)e.obs.x; dv.y = (G)e.obs.y; dv.z = (G)e.obs.z; dv.pad = (G)0;
     r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
     // The field's phase contains -k dir.r_exit and the rasteriser carries it
     // with k r_exit.(dir - n) using the stored direction, so the two must use
@@ -205,9 +207,11 @@ struct RecordSink {
     // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
     double cre = 1.0, cim = 0.0;
     if (sizeof(E) > sizeof(G)) {
-      const double dpx = (double)e.dir.x - (double)dv.x, dpy = (double)e.dir.y - (double)dv.y,
-                   dpz = (double)e.dir.z - (double)dv.z;
-      const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz);
+      const double dpx = (double)e.obs.x - (double)dv.x, dpy = (double)e.obs.y - (double)dv.y,
+                   dpz = (double)e.obs.z - (double)dv.z;
+      const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz) *
+                          near_scale(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
+                                     (double)e.obs.y, (double)e.obs.z, (double)dv.x, (double)dv.y, (double)dv.z);
       sincos(dphi, &cim, &cre);
     }
     v3<double> et, ep;
@@ -227,7 +231,7 @@ struct RecordSink {
     r.pad[0] = r.pad[1] = (G)0;
     rec.rr[at] = r;
     rec.dir[at] = dv;
-    const float dx = (float)e.dir.x, dy = (float)e.dir.y, dz = (float)e.dir.z;
+    const float dx = (float)e.obs.x, dy = (float)e.obs.y, dz = (float)e.obs.z;
     float phi = atan2f(dy, dx);
     if (phi < 0.0f) phi += 6.28318531f;
     if (phi >= 6.28318531f) phi = 0.0f;
@@ -741,8 +745,11 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
     const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
     // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
-    const double psi = (double)vr.kr[0] * ((double)dk.x - n.x) + (double)vr.kr[1] * ((double)dk.y - n.y) +
-                       (double)vr.kr[2] * ((double)dk.z - n.z);
+    double psi = (double)vr.kr[0] * ((double)dk.x - n.x) + (double)vr.kr[1] * ((double)dk.y - n.y) +
+                 (double)vr.kr[2] * ((double)dk.z - n.z);
+    if (ng.kappa > 0.0)
+      psi *= near_scale(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dk.x, (double)dk.y,
+                        (double)dk.z, n.x, n.y, n.z);
     G s_, c_;
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
     else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);

@@ -26,7 +26,8 @@ class Particle(ctypes.Structure):
 
 
 class Incident(ctypes.Structure):
-    _fields_ = [("wavelength", ctypes.c_double), ("n_pol", ctypes.c_int), ("source_distance", ctypes.c_double)]
+    _fields_ = [("wavelength", ctypes.c_double), ("n_pol", ctypes.c_int), ("source_distance", ctypes.c_double),
+                ("observation_radius", ctypes.c_double)]
 
 
 class TraceOpts(ctypes.Structure):
@@ -136,12 +137,15 @@ def make_particle(semi_axes: Sequence[float], euler_deg: Sequence[float] = (0, 0
     return p
 
 
-def make_incident(wavelength: float = 0.6328, n_pol: int = 1, source_distance: float = 0.0):
-    """Incident wave: a plane wave along +z, or (source_distance > 0) a point source at lab (0, 0, -source_distance)."""
+def make_incident(wavelength: float = 0.6328, n_pol: int = 1, source_distance: float = 0.0,
+                  observation_radius: float = 0.0):
+    """Incident wave: a plane wave along +z, or (source_distance > 0) a point source at lab (0, 0, -source_distance);
+    observation_radius > 0 puts the nodes on the sphere of that radius instead of the far field."""
     inc = Incident()
     inc.wavelength = float(wavelength)
     inc.n_pol = int(n_pol)
     inc.source_distance = float(source_distance)
+    inc.observation_radius = float(observation_radius)
     return inc
 
 

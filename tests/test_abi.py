@@ -60,7 +60,14 @@ def test_argument_validation_without_device():
         (good[0], rtw.make_incident(0.6328, 2, -200.0), good[2], rtw.RTW_ERR_INVALID_ARG),
         (good[0], rtw.make_incident(0.6328, 2, float("inf")), good[2], rtw.RTW_ERR_INVALID_ARG),
         (good[0], rtw.make_incident(0.6328, 2, float("nan")), good[2], rtw.RTW_ERR_INVALID_ARG),
+        # observation radius: 0 (far field) or beyond the largest semi-axis, finite
+        (good[0], rtw.make_incident(0.6328, 2, 0.0, 50.0), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, 0.0, -500.0), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, 200.0, float("inf")), good[2], rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, 0.0, float("nan")), good[2], rtw.RTW_ERR_INVALID_ARG),
     ]
+    rc, n_obs = _ws(good[0], rtw.make_incident(0.6328, 2, 0.0, 50.5), good[2])
+    assert rc == rtw.RTW_OK and n_obs == n
     rc, n_src = _ws(good[0], rtw.make_incident(0.6328, 2, 50.5), good[2])
     assert rc == rtw.RTW_OK and n_src == n
     for part, inc, opts, code in cases:
@@ -140,15 +147,16 @@ def test_batch_workspace_and_validation_without_device():
 
 
 def test_surrogate_rejects_point_source_incidence():
-    """The surrogate models plane-wave incidence only (host-side check)."""
+    """The surrogate models plane-wave incidence and the far field only (host-side check)."""
     L = rtw.load()
     part = rtw.make_particle((50, 40, 30), (10, 20, 30), 1.333)
     th = (ctypes.c_double * 1)(130.0)
     ph = (ctypes.c_double * 1)(10.0)
     feats = (ctypes.c_float * 64)()
     fn = L.rtw_surrogate_features
-    for zs, code in ((0.0, rtw.RTW_OK), (500.0, rtw.RTW_ERR_UNSUPPORTED)):
-        inc = rtw.make_incident(0.6328, 2, zs)
+    for zs, R, code in ((0.0, 0.0, rtw.RTW_OK), (500.0, 0.0, rtw.RTW_ERR_UNSUPPORTED),
+                        (0.0, 500.0, rtw.RTW_ERR_UNSUPPORTED)):
+        inc = rtw.make_incident(0.6328, 2, zs, R)
         rc = fn(1, ctypes.byref(part), ctypes.byref(inc), 1, th, ph, feats)
         assert rc == code, (zs, rc)
 
