@@ -105,12 +105,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def count_units(rtw, w, grid_n, zs=0.0):
+def count_units(rtw, w, grid_n, zs=0.0, robs=0.0):
     """Active incident rays (rays that emit order 0) and valid triangles (three
     rays emitting the order with equal focal-line counts), from rtw_trace."""
     import torch
     part = rtw.make_particle(w.semi_axes, w.euler_deg, w.m)
-    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1, zs),
+    rec = rtw.trace(part, rtw.make_incident(w.wavelength, 1, zs, robs),
                     rtw.make_opts(w.p_min, w.p_max, grid_n, rtw.FP64))
     fl = rec["flags"]
     n_active = int((fl[0] & 1).sum().item()) if w.p_min == 0 else None
@@ -127,9 +127,10 @@ def count_units(rtw, w, grid_n, zs=0.0):
     return n_active, n_tri
 
 
-def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0):
+def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0, robs=0.0):
     import torch
-    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m), rtw.make_incident(w.wavelength, w.n_pol, zs),
+    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m),
+                      rtw.make_incident(w.wavelength, w.n_pol, zs, robs),
                       rtw.make_opts(w.p_min, w.p_max, grid_n, precision), w.theta_deg, w.phi_deg)
     ff()  # sizes the workspace (grows it if the hit pool overflowed)
     for _ in range(warmup):
@@ -587,6 +588,8 @@ def main():
     ap.add_argument("--large-grid-n", type=int, default=8192)
     ap.add_argument("--source-distance", type=float, default=0.0,
                     help="ellipsoid workload lit by a point source at lab (0, 0, -z) instead of the plane wave (um)")
+    ap.add_argument("--observation-radius", type=float, default=0.0,
+                    help="ellipsoid workload observed on the sphere of this radius instead of the far field (um)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run would shard the ray grid "
@@ -621,18 +624,19 @@ def main():
         return bench_large(args, rtw, inputs)
     w = inputs.ellipsoid_mixed(args.grid_n)
     zs = args.source_distance
-    n_active, n_tri = count_units(rtw, w, args.grid_n, zs)
+    robs = args.observation_radius
+    n_active, n_tri = count_units(rtw, w, args.grid_n, zs, robs)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "
         f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}, {n_tri} valid triangles")
 
-    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup, zs)
+    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup, zs, robs)
     log(f"[bench] mixed: {ms_mixed:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
     for k, (t, n) in sorted(prof_mixed.items(), key=lambda kv: -kv[1][0]):
         log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
     fp64 = None
     if not args.no_fp64:
         ms64, prof64, hits64, _ = time_path(rtw, w, args.grid_n, rtw.FP64, max(2, args.steps // 2),
-                                            max(1, args.warmup // 2), zs)
+                                            max(1, args.warmup // 2), zs, robs)
         log(f"[bench] fp64: {ms64:.3f} ms/step")
         for k, (t, n) in sorted(prof64.items(), key=lambda kv: -kv[1][0]):
             log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
@@ -654,7 +658,8 @@ def main():
     else:
         flops = 8 * hits
     achieved = flops / avg_s / 1e12
-    ctr = measured_counters() if dom == "k_raster_mixed" and zs == 0 else None  # counters are of the plane wave
+    # the counters are of the plane wave observed in the far field
+    ctr = measured_counters() if dom == "k_raster_mixed" and zs == 0 and robs == 0 else None
     traffic = ctr["traffic"] if ctr else None
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
@@ -670,7 +675,8 @@ def main():
         import oracle
         t0 = time.perf_counter()
         oracle.farfield(oracle.particle(w.semi_axes, w.euler_deg, w.m),
-                        oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n, source_distance=zs),
+                        oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n, source_distance=zs,
+                                     observation_radius=robs),
                         w.theta_deg, w.phi_deg)
         dt = time.perf_counter() - t0
         cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
@@ -684,7 +690,8 @@ def main():
         oracle.set_threads(1)
         try:
             op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
-            st1 = oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, n1, source_distance=zs)
+            st1 = oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, n1, source_distance=zs,
+                               observation_radius=robs)
             act1 = int((oracle.trace_grid(op, oracle.setup(w.wavelength, 1, 0, 0, n1, source_distance=zs))["flags"][0]
                         & 1).sum())
             t0 = time.perf_counter()
@@ -711,7 +718,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"ellipsoid 60/50/40 um, Euler (30,20,10) deg, m=1.333, lambda=0.6328 um, "
                                f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed"
-                               + (f", point source at {zs:g} um" if zs > 0 else ""),
+                               + (f", point source at {zs:g} um" if zs > 0 else "")
+                               + (f", nodes on the sphere of radius {robs:g} um" if robs > 0 else ""),
                    "active_rays": n_active, "valid_triangles": n_tri, "source_hash": source_hash(), "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(w.n_nodes * w.n_pol / (ms_mixed * 1e-3), 1),
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},

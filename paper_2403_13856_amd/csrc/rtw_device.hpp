@@ -378,11 +378,15 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
         const double detG = g11 * g22 - g12 * g12;
         nft = nf + neg_eigs(g11, g12, g22);
         amp = P.robs * sqrt_d(D * rcp_d(fabs(detG)));
-        // Q' carries the error amplified so far; det(I + d_M Q') scales it
-        // again, by half its entry-wise condition (1 away from a caustic at
-        // M, where the sum is about twice |det|)
-        e_amplif *= fmax(1.0, 0.5 * (fabs(dM * Q11) * fabs(g22) + fabs(g11) * fabs(dM * Q22) + 2.0 * dM * dM * Q12 * Q12) /
-                                  fmax(fabs(detG), 1e-300));
+        // Q' carries the error amplified so far; det(I + d_M Q') scales its
+        // entries' rounding by half its entry-wise condition.  Far from the
+        // particle that tends to det Q''s own condition, which e_amplif
+        // already holds, so only the excess over it multiplies e_amplif (it
+        // grows where a caustic meets the observation sphere)
+        const double cg = 0.5 * (fabs(dM * Q11) * fabs(g22) + fabs(g11) * fabs(dM * Q22) + 2.0 * dM * dM * Q12 * Q12) /
+                          fmax(fabs(detG), 1e-300);
+        const double cq = (fabs(Q11 * Q22) + Q12 * Q12) / fmax(fabs(detQ), 1e-300);
+        e_amplif *= fmax(1.0, cg / cq);
         phase = opl + P.k * (dM - P.robs) - nft * 1.5707963267948966;
         const V Mb = mk3(r.x + dM * dout.x, r.y + dM * dout.y, r.z + dM * dout.z);
         const double ir = rcp_d(P.robs);
