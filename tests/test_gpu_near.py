@@ -121,10 +121,10 @@ def _farfield(R, gp, gi, go, th, ph):
     return F, ff.ncontrib.cpu().numpy()
 
 
-@pytest.mark.parametrize("zs,robs", [(0.0, 150.0), (0.0, 2000.0), (250.0, 400.0)])
-def test_near_farfield_fp64_matches_oracle(oracle, R, zs, robs):
+@pytest.mark.parametrize("zs,robs,N", [(0.0, 150.0, 96), (0.0, 2000.0, 96), (250.0, 400.0, 96), (0.0, 500.0, 2048)])
+def test_near_farfield_fp64_matches_oracle(oracle, R, zs, robs, N):
+    """N = 2048 at R = 500 um is the configuration `bench.py --observation-radius 500` times."""
     w = I.ellipsoid_mixed()
-    N = 96
     say(f"[near farfield fp64] ellipsoid N={N} zs={zs} R={robs} full node grid")
     op, os_, gp, gi, go = _pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.n_pol, w.p_min, w.p_max, N, zs, robs,
                                 R.FP64)
@@ -144,10 +144,10 @@ def test_near_farfield_fp64_matches_oracle(oracle, R, zs, robs):
     assert clean.mean() > 0.7
 
 
-@pytest.mark.parametrize("robs", [90.0, 1e4])
-def test_near_farfield_mixed_matches_oracle(oracle, R, robs):
+@pytest.mark.parametrize("robs,N", [(90.0, 256), (1e4, 256), (500.0, 2048)])
+def test_near_farfield_mixed_matches_oracle(oracle, R, robs, N):
+    """N = 2048 at R = 500 um is the configuration `bench.py --observation-radius 500` times."""
     w = I.ellipsoid_mixed()
-    N = 256
     say(f"[near farfield mixed] ellipsoid N={N} R={robs}")
     op, os_, gp, gi, go = _pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.n_pol, w.p_min, w.p_max, N, 0.0, robs,
                                 R.MIXED)
