@@ -301,8 +301,12 @@ static void emit_order(const ctx_t* c, const ray_state* s, const double* dir, co
   double phase = s->opl - c->k * dot3(dir, s->r) - nf_total * (PI / 2.0);
   if (c->robs > 0.0) {
     /* finite observation radius (reading R11) */
+    /* d_M - R = -d.r - |r_perp|^2 / (sqrt(R^2 - |r_perp|^2) + R): the root of
+       |r + d_M d| = R written without the cancellation of d_M - R at large R */
     double dr = dot3(dir, s->r);
-    double dM = -dr + sqrt(dr * dr - dot3(s->r, s->r) + c->robs * c->robs);
+    double rp2 = dot3(s->r, s->r) - dr * dr;
+    double dMR = -dr - rp2 / (sqrt(c->robs * c->robs - rp2) + c->robs);
+    double dM = c->robs + dMR;
     mat2 G;
     G.m[0][0] = 1.0 + dM * Qx.m[0][0];
     G.m[0][1] = dM * Qx.m[0][1];
@@ -310,7 +314,7 @@ static void emit_order(const ctx_t* c, const ray_state* s, const double* dir, co
     G.m[1][1] = 1.0 + dM * Qx.m[1][1];
     nf_total = s->nf + m2neg(G);
     S = c->robs * sqrt(s->D / fabs(m2det(G)));
-    phase = s->opl + c->k * (dM - c->robs) - nf_total * (PI / 2.0);
+    phase = s->opl + c->k * dMR - nf_total * (PI / 2.0);
     double M[3] = {s->r[0] + dM * dir[0], s->r[1] + dM * dir[1], s->r[2] + dM * dir[2]};
     double Ml[3];
     matvec(c->R, M, Ml);
@@ -776,13 +780,16 @@ static void tri_node(int node, void* user) {
       double dn[3] = {n[0] - v->dir[0], n[1] - v->dir[1], n[2] - v->dir[2]};
       cplx carry;
       if (J->kappa > 0.0) {
-        /* path difference from the exit point to R n and to R u (reading R11) */
+        /* path difference from the exit point to R n and to R u (reading R11):
+           |a| - |b| with a = kR n - k r, b = kR u - k r.  For unit n and u,
+           |a|^2 - |b|^2 = 2 kR k r.(u - n), so |a| - |b| is that over |a| + |b|,
+           which avoids subtracting two lengths near kR */
         double a[3], b[3];
         for (int x = 0; x < 3; x++) {
           a[x] = J->kappa * n[x] - v->kr[x];
           b[x] = J->kappa * v->dir[x] - v->kr[x];
         }
-        carry = cexp(I * (norm3(a) - norm3(b)));
+        carry = cexp(I * (-dot3(v->kr, dn) * 2.0 * J->kappa / (norm3(a) + norm3(b))));
       } else {
         carry = cexp(-I * dot3(v->kr, dn));  /* stationary-phase gradient */
       }
