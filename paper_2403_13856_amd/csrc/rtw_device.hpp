@@ -372,8 +372,11 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       if (P.robs > 0.0) {
         // finite observation radius: continue the ray by d_M to M on the
         // sphere; the last leg's divergence factor is 1 / det(I + d_M Q')
+        // d_M - R without the cancellation of the plain difference at large R
         const double drr = dot(dout, r);
-        const double dM = -drr + sqrt_d(drr * drr - dot(r, r) + P.robs * P.robs);
+        const double rp2 = dot(r, r) - drr * drr;
+        const double dMR = -drr - rp2 * rcp_d(sqrt_d(P.robs * P.robs - rp2) + P.robs);
+        const double dM = P.robs + dMR;
         const double g11 = 1.0 + dM * Q11, g12 = dM * Q12, g22 = 1.0 + dM * Q22;
         const double detG = g11 * g22 - g12 * g12;
         nft = nf + neg_eigs(g11, g12, g22);
@@ -387,7 +390,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
                           fmax(fabs(detG), 1e-300);
         const double cq = (fabs(Q11 * Q22) + Q12 * Q12) / fmax(fabs(detQ), 1e-300);
         e_amplif *= fmax(1.0, cg / cq);
-        phase = opl + P.k * (dM - P.robs) - nft * 1.5707963267948966;
+        phase = opl + P.k * dMR - nft * 1.5707963267948966;
         const V Mb = mk3(r.x + dM * dout.x, r.y + dM * dout.y, r.z + dM * dout.z);
         const double ir = rcp_d(P.robs);
         const V u = mk3((R[0] * Mb.x + R[1] * Mb.y + R[2] * Mb.z) * ir, (R[3] * Mb.x + R[4] * Mb.y + R[5] * Mb.z) * ir,
