@@ -199,14 +199,15 @@ def test_near_batch_equals_single_calls(R):
 
 
 def test_near_edge_cases(oracle, R):
-    """A single quad (N = 2), a lone order on the sphere a hair outside the
-    particle (R = a_max (1 + 1e-6): the call must complete; its nodes all lie
-    in flagged bands) and a distant sphere (R = 1e7 um, where k (d_M - R) and
-    the carry must be formed without cancellation), both precisions."""
+    """A single quad (N = 2), the sphere a hair outside the particle
+    (R = a_max (1 + 1e-6), where d_M shrinks to zero at the particle's
+    widest point) and a distant sphere (R = 1e7 um, where k (d_M - R) and the
+    carry must be formed without cancellation), both precisions."""
     axes, euler, m = (40.0, 35.0, 30.0), (15.0, 25.0, 35.0), 1.333
     for P in (R.FP64, R.MIXED):
         for (N, th, ph, pmin, pmax, robs) in [(2, [90.0, 150.0, 180.0], [0.0, 90.0, 270.0], 0, 2, 100.0),
-                                              (24, [0.0, 20.0], [0.0, 45.0, 359.0], 1, 1, 40.0 * (1 + 1e-6)),
+                                              (24, np.arange(0, 181, 10.0), np.arange(0, 360, 30.0), 0, 1,
+                                               40.0 * (1 + 1e-6)),
                                               (96, np.arange(0, 181, 3.0), np.arange(0, 360, 7.0), 0, 3, 1e7)]:
             th = np.asarray(th, float)
             ph = np.asarray(ph, float)
@@ -220,6 +221,7 @@ def test_near_edge_cases(oracle, R):
                 err = np.abs(F - ref["field"]).max(axis=(0, 1)) / np.maximum(np.sqrt(inc), 1e-300)
                 worst = err[clean & (inc > 0)]
                 say(f"   fp64 worst {worst.max(initial=0):.2e} on {clean.sum()} clean nodes")
+                assert (clean & (inc > 0)).sum() > 0
                 assert worst.max(initial=0) < 1e-10
                 assert np.array_equal(nc[clean], ref["ncontrib"][clean])
             else:
