@@ -13,6 +13,10 @@ with HIP events on the library's stream (rtw_profile_*).  The CPU baseline is
 the FP64 oracle on the full workload, timed on the host cores.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
+Other modes, each printing its own JSON line: --workload batch | surrogate |
+paper_spheroid | large; --source-distance Z (the ellipsoid lit by a point
+source at lab (0, 0, -Z)); --observation-radius R (the ellipsoid's field on
+the sphere of radius R instead of the far field).
 """
 import argparse
 import json
