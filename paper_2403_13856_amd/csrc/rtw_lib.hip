@@ -608,10 +608,14 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   pl.S.n_parts = n;
   pl.S.max_chunk_rays = 0;
   pl.S.max_chunk_parts = 0;
+  // node indices of a chunk (chunk particle, theta, phi) are 32-bit: a chunk
+  // holds at most (2^31 - 1) / n_nodes particles
+  const long n_nodes = (long)grid->n_theta * grid->n_phi;
+  const long max_parts = std::min<long>(65535, ((1L << 31) - 1) / n_nodes);
   int c0 = 0;
   while (c0 < n) {
     int c1 = c0 + 1;
-    while (c1 < n && c1 - c0 < 65535 && pl.ray_off[c1 + 1] - pl.ray_off[c0] <= rays_per_chunk) ++c1;
+    while (c1 < n && c1 - c0 < max_parts && pl.ray_off[c1 + 1] - pl.ray_off[c0] <= rays_per_chunk) ++c1;
     pl.chunks.push_back({c0, c1});
     pl.S.max_chunk_rays = std::max(pl.S.max_chunk_rays, pl.ray_off[c1] - pl.ray_off[c0]);
     pl.S.max_chunk_parts = std::max(pl.S.max_chunk_parts, c1 - c0);

@@ -176,3 +176,22 @@ def test_batch_rejects_a_source_inside_one_particle():
                                         ctypes.byref(n))
         assert rc == code, (zs, rc)
     assert "source_distance" in L.rtw_last_error().decode()
+
+
+def test_batch_chunks_keep_node_indices_32bit():
+    """Node indices within a chunk (chunk particle, theta, phi) are 32-bit: on a
+    node grid of 2^30 nodes a chunk holds one particle, so the per-node
+    count and range arrays of a three-particle batch are those of one particle."""
+    inc, opts = rtw.make_incident(0.6328, 1), rtw.make_opts(0, 0, 2, rtw.MIXED)
+    parts = [rtw.make_particle((20.0, 20.0, 20.0), (0, 0, 0), 1.333) for _ in range(3)]
+    n_theta, n_phi = 32768, 32768  # 2^30 nodes, the largest grid accepted
+    assert 2 * n_theta * n_phi > (1 << 31) - 1
+    rc1, one = _batch_ws(parts[:1], [16], inc, opts, n_theta, n_phi)
+    rc3, three = _batch_ws(parts, [16, 16, 16], inc, opts, n_theta, n_phi)
+    assert rc1 == rtw.RTW_OK and rc3 == rtw.RTW_OK
+    per_node_arrays = 2 * 4 * n_theta * n_phi  # counts and range starts, int32
+    assert three - one < per_node_arrays // 8, (one, three)
+    # a grid of a few thousand nodes still packs the three particles in one chunk
+    _, small1 = _batch_ws(parts[:1], [16], inc, opts, 64, 64)
+    _, small3 = _batch_ws(parts, [16, 16, 16], inc, opts, 64, 64)
+    assert small3 - small1 >= 2 * 2 * 4 * 64 * 64
