@@ -177,6 +177,28 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
                  const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* workspace,
                  size_t workspace_bytes, void* hip_stream);
 
+/* ---- Far field without device allocation ---------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation and kernels as rtw_farfield, with the workspace taken from a
+ * static device array of RTW_STATIC_WORKSPACE_MIB MiB inside the library (one
+ * copy per GPU, held until the process ends).  The call allocates and frees
+ * nothing; the caller passes the inputs and outputs as for rtw_farfield.
+ *   status_out DEVICE int32 [1] or NULL: written on the stream after the sum,
+ *              RTW_OK, or RTW_ERR_WORKSPACE if the hit pool overflowed (the
+ *              result is then incomplete).
+ * Every call on one GPU shares that GPU's array and overwrites what the last
+ * call left there (the kernels clear what must start at zero): calls that
+ * overlap on one GPU, on different streams or host threads, race.
+ * Errors as rtw_farfield, plus RTW_ERR_WORKSPACE, on the host before anything
+ * is launched, when the call needs more than the static array at the default
+ * pool sizing (6 contributions per node); RTW_ERR_DEVICE when there is no
+ * current device.  Profiling events (rtw_profile_enable) are not recorded. */
+#define RTW_STATIC_WORKSPACE_MIB 128
+int rtw_farfield_static(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
+                        const rtw_grid* grid, void* out_field, int32_t* ncontrib, int32_t* status_out,
+                        void* hip_stream);
+
 /* ---- Batches of particles (many ellipsoids, one call) -------------------
  * The same far field for n particles that share the incident wave, the
  * orders, the precision and the node grid, each with its own shape,

@@ -23,6 +23,13 @@
 
 using namespace rtw;
 
+// Workspace of rtw_farfield_static: library-owned device memory, one copy per
+// GPU (each at its own address), held until the process ends.  Host code
+// never passes this name to a kernel: it is a host-side stand-in there.  The
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t STATIC_WS_BYTES = (size_t)RTW_STATIC_WORKSPACE_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -36,13 +43,14 @@ struct ProfRec {
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 bool g_prof_on = false;
+thread_local bool g_prof_off = false;  // set while a call must not create events
 
 struct ProfScope {
   const char* name;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_prof_off) return;
     hipEventCreate(&a);
     hipEventCreate(&b);
     hipEventRecord(a, st);
@@ -406,6 +414,14 @@ __global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter) {
 }
 
 constexpr int ROWS_CAP = 1 << 24;  // (triangle, row) items of large triangles
+// row list of the static workspace (512 KB): a full list sends further large
+// triangles to the rasteriser's own loop, which is slower but exact
+constexpr int STATIC_ROWS_CAP = 1 << 16;
+
+// Status word of rtw_farfield_static: whether the hit pool held every hit.
+__global__ void k_static_status(const unsigned* counter, int cap_part, int32_t* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) status[0] = (long)counter[C_NEED] > cap_part ? RTW_ERR_WORKSPACE : RTW_OK;
+}
 
 // Split each node-angle list into uniformly spaced runs (block 0: theta,
 // block 1: phi).  A "break" is an index where the spacing changes; more than
@@ -490,6 +506,7 @@ struct Shape {
   int n_parts;          // particles of the call
   long max_chunk_rays;  // incident rays of the largest chunk
   int max_chunk_parts;  // particles of the largest chunk
+  long rows_cap;        // (triangle, row) items of the row list
 };
 
 Layout layout(const Shape& S, long cap_total) {
@@ -518,7 +535,7 @@ Layout layout(const Shape& S, long cap_total) {
   L.cursor = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.bsum = take(4 * ((size_t)S.max_chunk_parts * n_nodes / SCAN_BLOCK + 1));
   L.redo = take(S.precision == RTW_FP64 ? 4 : 4 * (size_t)S.max_chunk_rays);
-  L.rows = take(sizeof(int2) * (size_t)ROWS_CAP);
+  L.rows = take(sizeof(int2) * (size_t)S.rows_cap);
   L.fixed = off;
   const size_t ds = S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>);
   L.bytes_per_hit = sizeof(int) + gs * 4 * S.n_pol + ds;
@@ -608,6 +625,7 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   pl.S.n_parts = n;
   pl.S.max_chunk_rays = 0;
   pl.S.max_chunk_parts = 0;
+  pl.S.rows_cap = ROWS_CAP;
   // node indices of a chunk (chunk particle, theta, phi) are 32-bit: a chunk
   // holds at most (2^31 - 1) / n_nodes particles
   const long n_nodes = (long)grid->n_theta * grid->n_phi;
@@ -708,7 +726,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   pool.cap_part = (int)cap_part;
   pool.rows = (int2*)(ws + L.rows);
   pool.n_rows = counter + C_ROWS;
-  pool.rows_cap = ROWS_CAP;
+  pool.rows_cap = (int)S.rows_cap;
 
   ParticleConst* mP = (ParticleConst*)(ws + L.mP);
   long* moff = (long*)(ws + L.moff);
@@ -906,6 +924,64 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
     return launch_plan<double>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)workspace, workspace_bytes, st,
                                true);
   return launch_plan<float>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)workspace, workspace_bytes, st, true);
+}
+
+int rtw_farfield_static(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
+                        const rtw_grid* grid, void* out_field, int32_t* ncontrib, int32_t* status_out,
+                        void* hip_stream) {
+  if (!opts) return fail(RTW_ERR_INVALID_ARG, "NULL argument struct");
+  int rc = check_particle(part, inc, opts);
+  if (rc) return rc;
+  rc = check_keys(opts);
+  if (rc) return rc;
+  if (!out_field) return fail(RTW_ERR_INVALID_ARG, "NULL output");
+  const Tuning tu = tuning_of(nullptr);
+  Plan pl;
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, pl);
+  if (rc) return rc;
+  pl.S.rows_cap = STATIC_ROWS_CAP;
+  const size_t need = plan_bytes(pl, 0.0);
+  if (need > STATIC_WS_BYTES)
+    return fail(RTW_ERR_WORKSPACE, "rtw_farfield_static: this call needs %zu bytes of workspace, the static "
+                "workspace holds %zu", need, STATIC_WS_BYTES);
+  // the device's copy of the static workspace: its address is taken once per
+  // device, with that device current
+  static std::mutex mu;
+  static void* dev_ptr[64] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= 64)
+    return fail(RTW_ERR_DEVICE, "rtw_farfield_static: no current device (%s)", hipGetErrorString(e));
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!dev_ptr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(RTW_ERR_DEVICE, "rtw_farfield_static: static workspace address: %s", hipGetErrorString(e));
+      dev_ptr[dev] = p;
+    }
+    ws = dev_ptr[dev];
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  g_prof_off = true;  // no events (they would be created here)
+  if (opts->precision == RTW_FP64)
+    rc = launch_plan<double>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)ws, STATIC_WS_BYTES, st, true);
+  else
+    rc = launch_plan<float>(pl, tu, grid, out_field, ncontrib, nullptr, (char*)ws, STATIC_WS_BYTES, st, true);
+  g_prof_off = false;
+  if (rc) return rc;
+  if (status_out) {
+    const Layout L0 = layout(pl.S, 0);
+    long cap_part = cap_from_bytes(L0, STATIC_WS_BYTES);
+    if (cap_part > (1L << 30) / NPART) cap_part = (1L << 30) / NPART;
+    hipLaunchKernelGGL(k_static_status, dim3(1), dim3(64), 0, st, (const unsigned*)((char*)ws + L0.counter),
+                       (int)cap_part, status_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return RTW_OK;
 }
 
 int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,

@@ -54,7 +54,7 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("rays_per_chunk", ctypes.c_longlong), ("hits_per_node", ctypes.c_double)]
 
 
-EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_status",
+EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_static", "rtw_farfield_status",
             "rtw_farfield_stats", "rtw_batch_workspace_size", "rtw_batch", "rtw_batch_autotune",
             "rtw_profile_enable", "rtw_profile_read", "rtw_last_error", "rtw_version"]
 
@@ -86,6 +86,8 @@ def load():
                                               P(ctypes.c_size_t)]
     L.rtw_farfield.argtypes = [P(Particle), P(Incident), P(TraceOpts), P(Grid), ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    L.rtw_farfield_static.argtypes = [P(Particle), P(Incident), P(TraceOpts), P(Grid), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.rtw_farfield_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_size_t)]
     L.rtw_batch_workspace_size.argtypes = [ctypes.c_int, P(Particle), P(ctypes.c_int), P(Incident), P(TraceOpts),
                                            P(Grid), P(BatchOpts), P(ctypes.c_size_t)]
@@ -254,6 +256,17 @@ class FarField:
         """Complex view [n_pol, 2 (theta, phi), n_theta, n_phi]."""
         import torch
         return torch.view_as_complex(self.out)
+
+
+def farfield_static(part, inc, opts, theta, phi, out, ncontrib=None, status=None, stream=None):
+    """rtw_farfield_static: the far field with the library's static workspace
+    (no device allocation).  theta, phi: device float64 node angles (deg); out:
+    device [n_pol, 2, n_theta, n_phi, 2] (float64 for FP64, float32 for MIXED);
+    ncontrib: device int32 [n_theta, n_phi] or None; status: device int32 [1]
+    or None (RTW_OK, or RTW_ERR_WORKSPACE on hit-pool overflow)."""
+    grid = Grid(theta.numel(), theta.data_ptr(), phi.numel(), phi.data_ptr())
+    _check(load().rtw_farfield_static(ctypes.byref(part), ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(grid),
+                                      _ptr(out), _ptr(ncontrib), _ptr(status), _stream_ptr(stream)))
 
 
 @dataclass
