@@ -63,7 +63,7 @@ def lib():
         _lib.rtwo_trace_rays.argtypes = [P(Particle), P(Setup), ctypes.c_int, dp, P(Ray)]
         _lib.rtwo_trace_grid.argtypes = [P(Particle), P(Setup), ip, dp, dp, dp, dp, dp]
         _lib.rtwo_farfield.argtypes = [P(Particle), P(Setup), ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_double,
-                                       dp, dp, ip, ip, dp]
+                                       ctypes.c_double, dp, dp, ip, ip, dp]
         _lib.rtwo_grid_halfwidth.argtypes = [P(Particle)]
         _lib.rtwo_grid_halfwidth.restype = ctypes.c_double
         _lib.rtwo_grid_halfwidth_source.argtypes = [P(Particle), ctypes.c_double]
@@ -153,9 +153,13 @@ def trace_grid(part, st):
     return dict(flags=flags, dir=d, rexit=r, phase=ph, amp=amp, field=field)
 
 
-def farfield(part, st, theta_deg, phi_deg, band_deg=0.1):
+def farfield(part, st, theta_deg, phi_deg, band_deg=0.1, edge_band_deg=None):
     """Far field F(theta, phi) (um): complex array [n_pol, 2 (theta, phi), n_theta, n_phi],
-    plus per-node incoherent sums, flags and contribution counts."""
+    plus per-node incoherent sums, flags and contribution counts.  band_deg is the
+    width of the caustic and pole bands (flag bits 1, 2), edge_band_deg that of
+    the sheet-edge band (bit 3; None: band_deg)."""
+    if edge_band_deg is None:
+        edge_band_deg = band_deg
     th = np.ascontiguousarray(theta_deg, dtype=np.float64)
     ph = np.ascontiguousarray(phi_deg, dtype=np.float64)
     nt, nphi = th.size, ph.size
@@ -165,7 +169,7 @@ def farfield(part, st, theta_deg, phi_deg, band_deg=0.1):
     ncon = np.zeros(nt * nphi, np.int32)
     unc = np.zeros(nt * nphi)
     rc = lib().rtwo_farfield(ctypes.byref(part), ctypes.byref(st), nt, _dp(th), nphi, _dp(ph), float(band_deg),
-                             _dp(field), _dp(incoh), _ip(nflags), _ip(ncon), _dp(unc))
+                             float(edge_band_deg), _dp(field), _dp(incoh), _ip(nflags), _ip(ncon), _dp(unc))
     if rc != 0:
         raise ValueError("rtwo_farfield rejected its arguments")
     F = field[..., 0] + 1j * field[..., 1]

@@ -813,7 +813,8 @@ static void tri_node(int node, void* user) {
 typedef struct { int* nflags; } band_job;
 static void band_node(int node, void* user) { ((band_job*)user)->nflags[node] |= 2; }
 static double ang(const double* a, const double* b);
-/* nodes within `band` of the great-circle segment a-b (a == b: of the point a) */
+/* nodes within `band` of the great-circle segment a-b (a == b: of the point a):
+   the segment along which an order's field ends (bit 3) */
 typedef struct { int* nflags; const nodes_t* nd; const double *a, *b; double band; } edge_job;
 static void edge_node(int node, void* user) {
   const edge_job* E = (const edge_job*)user;
@@ -851,8 +852,8 @@ static double ang(const double* a, const double* b) {
 }
 
 int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_theta, const double* theta_deg,
-                  int n_phi, const double* phi_deg, double band_deg, double* field, double* incoh, int* nflags,
-                  int* ncontrib, double* uncancelled) {
+                  int n_phi, const double* phi_deg, double band_deg, double edge_band_deg, double* field,
+                  double* incoh, int* nflags, int* ncontrib, double* uncancelled) {
   ctx_t c;
   if (setup_ctx(part, setup, &c) != 0 || setup->grid_n < 2 || n_theta < 1 || n_phi < 1 || !theta_deg ||
       !phi_deg || !field)
@@ -864,7 +865,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
   int N = setup->grid_n, n_ord = c.p_max - c.p_min + 1, n_pol = c.n_pol;
   long NN = (long)N * N, n_nodes = (long)n_theta * n_phi;
   double L = rtwo_grid_halfwidth_source(part, setup->source_distance), h = 2.0 * L / N;
-  double band = band_deg * PI / 180.0;
+  double band = band_deg * PI / 180.0, edge_band = edge_band_deg * PI / 180.0;
 
   /* node directions and the lab (e_theta, e_phi) basis */
   double* th = malloc(sizeof(double) * n_theta);
@@ -950,15 +951,28 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
             for (int k = 0; k < 3; k++)
               if (V[k]->valid) kv[nv++] = k;
             if (nv == 0) continue;
-            edge_job ej = {fl_buf, &nd, V[kv[0]]->dir, V[kv[nv - 1]]->dir, band};
+            edge_job ej = {fl_buf, &nd, V[kv[0]]->dir, V[kv[nv - 1]]->dir, edge_band};
             double ce[3];
             if (nv == 1) copy3(ej.a, ce);
             else {
               double s2[3] = {ej.a[0] + ej.b[0], ej.a[1] + ej.b[1], ej.a[2] + ej.b[2]};
               scale3(1.0 / norm3(s2), s2, ce);
             }
-            for_nodes_in_cap(&nd, ce, ang(ce, ej.a) + band + 1e-9, edge_node, &ej);
+            for_nodes_in_cap(&nd, ce, ang(ce, ej.a) + edge_band + 1e-9, edge_node, &ej);
             continue;
+          }
+          /* an edge of the incident grid (both rays in its first or last row
+             or column) also ends the sheet: no ray lies beyond it, so mark the
+             nodes within the band of its image as well */
+          for (int k = 0; k < 3; k++) {
+            long ra = tris[t][(k + 1) % 3], rb = tris[t][(k + 2) % 3];
+            long ya = ra / N, xa = ra % N, yb = rb / N, xb = rb % N;
+            int on_grid_edge = (ya == yb && (ya == 0 || ya == N - 1)) || (xa == xb && (xa == 0 || xa == N - 1));
+            if (!on_grid_edge) continue;
+            edge_job ej = {fl_buf, &nd, V[(k + 1) % 3]->dir, V[(k + 2) % 3]->dir, edge_band};
+            double s2[3] = {ej.a[0] + ej.b[0], ej.a[1] + ej.b[1], ej.a[2] + ej.b[2]}, ce[3];
+            scale3(1.0 / norm3(s2), s2, ce);
+            for_nodes_in_cap(&nd, ce, ang(ce, ej.a) + edge_band + 1e-9, edge_node, &ej);
           }
           double cen[3];
           unit_centroid(V[0]->dir, V[1]->dir, V[2]->dir, cen);

@@ -113,8 +113,10 @@ int rtwo_trace_grid(const rtwo_particle* part, const rtwo_setup* setup,
  *   nflags [n_theta*n_phi]  bit0 tie node (a barycentric weight within 1e-9 of 0),
  *                           bit1 within band_deg of a dropped fold triangle,
  *                           bit2 within band_deg of theta = 0 or 180,
- *                           bit3 within band_deg of the edge of an order's sheet
- *                           (a triangle some of whose rays do not emit the order)
+ *                           bit3 within edge_band_deg of the edge of an order's sheet:
+ *                           the segment between the emitting rays of a triangle some
+ *                           of whose rays do not emit the order, or an edge of the
+ *                           incident grid (no ray lies beyond it)
  *   ncontrib[n_theta*n_phi] number of triangle contributions
  *   uncancelled[n_theta*n_phi] sum over contributions of (sum over the three
  *                           rays of |lambda_v| |F_v|)^2 (pols, comps): the size of
@@ -122,7 +124,7 @@ int rtwo_trace_grid(const rtwo_particle* part, const rtwo_setup* setup,
  * incoh, nflags, ncontrib and uncancelled may be NULL. */
 int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup,
                   int n_theta, const double* theta_deg, int n_phi, const double* phi_deg,
-                  double band_deg, double* field, double* incoh, int* nflags, int* ncontrib,
+                  double band_deg, double edge_band_deg, double* field, double* incoh, int* nflags, int* ncontrib,
                   double* uncancelled);
 
 /* Fresnel coefficients of the paper's Eq. 8 for a real relative index m_rel =
