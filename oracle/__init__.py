@@ -174,7 +174,8 @@ def farfield(part, st, theta_deg, phi_deg, band_deg=0.1, edge_band_deg=None):
         raise ValueError("rtwo_farfield rejected its arguments")
     F = field[..., 0] + 1j * field[..., 1]
     return dict(field=F, incoh=incoh.reshape(nt, nphi), flags=nflags.reshape(nt, nphi),
-                ncontrib=ncon.reshape(nt, nphi), uncancelled=unc.reshape(nt, nphi))
+                ncontrib=ncon.reshape(nt, nphi), uncancelled=unc.reshape(nt, nphi), band_deg=float(band_deg),
+                edge_band_deg=float(edge_band_deg))
 
 
 def ray_emit(ray, p):

@@ -128,18 +128,24 @@ struct ParticleConst {
   double robs;   // observation radius (um); 0: far field
 };
 
-// Observation at a finite radius R (kappa = k R): a wave leaving the exit
-// point r (kr = k r) gains k (|R n - r| - |R u - r|) between the directions u
-// and n on the sphere.  For unit u and n that equals
-// kr.(u - n) * 2 kappa / (|kappa n - kr| + |kappa u - kr|), free of the
-// cancellation of the plain difference; this returns the factor, 1 in the far
-// field (kappa = 0), where the carry is kr.(u - n).
-__device__ __forceinline__ double near_scale(double kappa, double krx, double kry, double krz, double ux, double uy,
-                                             double uz, double nx, double ny, double nz) {
-  if (kappa == 0.0) return 1.0;
-  const double ax = kappa * nx - krx, ay = kappa * ny - kry, az = kappa * nz - krz;
-  const double bx = kappa * ux - krx, by = kappa * uy - kry, bz = kappa * uz - krz;
-  return 2.0 * kappa / (sqrt(ax * ax + ay * ay + az * az) + sqrt(bx * bx + by * by + bz * bz));
+// Phase a wave leaving the exit point r (kr = k r) gains between the
+// directions x and y: in the far field (kappa = 0) kr.(x - y); on the
+// observation sphere of radius R (kappa = k R) |kappa y' - kr| -
+// |kappa x' - kr| between its points R x' and R y' in those directions
+// (x' = x / |x|: a direction rounded to FP32 names the point of the sphere
+// along it), formed as kr.(x' - y') 2 kappa / (|kappa y' - kr| + |kappa x' - kr|),
+// the same difference of squares over the sum, without the cancellation of
+// the plain difference (exact for unit x', y', also where one distance vanishes).
+__device__ __forceinline__ double near_carry(double kappa, double krx, double kry, double krz, double xx, double xy,
+                                             double xz, double yx, double yy, double yz) {
+  if (kappa == 0.0) return krx * (xx - yx) + kry * (xy - yy) + krz * (xz - yz);
+  const double sx = rsq_d(xx * xx + xy * xy + xz * xz), sy = rsq_d(yx * yx + yy * yy + yz * yz);
+  xx *= sx; xy *= sx; xz *= sx;
+  yx *= sy; yy *= sy; yz *= sy;
+  const double ax = kappa * yx - krx, ay = kappa * yy - kry, az = kappa * yz - krz;
+  const double bx = kappa * xx - krx, by = kappa * xy - kry, bz = kappa * xz - krz;
+  return (krx * (xx - yx) + kry * (xy - yy) + krz * (xz - yz)) * 2.0 * kappa /
+         (sqrt(ax * ax + ay * ay + az * az) + sqrt(bx * bx + by * by + bz * bz));
 }
 
 // Two-constant Cody-Waite reduction of x modulo 2 pi in FP64 (Cody & Waite,
@@ -172,6 +178,7 @@ struct Emission {
   v3<G> obs;           // node-space direction: dir in the far field, else the direction of the
                        // point M where the ray meets the observation sphere (the phase refers
                        // to exactly this vector)
+  v3<double> obs64;    // the same direction before its rounding to G (interpolation weights)
   v3<double> rexit;    // lab exit point (um)
   double phase;        // OPL - k dir.rexit - nf pi/2, unreduced; at radius R: OPL + k (d_M - R) - nf pi/2
   double amp;          // sqrt(D / |det Q'|); at radius R: R sqrt(D / |det(I + d_M Q')|)
@@ -362,9 +369,10 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       v3<G> ul;
       V epo = cross(dout, ep);  // e_par' of the outgoing wave
       // lab vectors: direction rounded once to G; the phase uses exactly that vector
-      v3<G> dl = mk3<G>((G)(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z),
-                        (G)(R[3] * dout.x + R[4] * dout.y + R[5] * dout.z),
-                        (G)(R[6] * dout.x + R[7] * dout.y + R[8] * dout.z));
+      const V dl64 = mk3(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z, R[3] * dout.x + R[4] * dout.y + R[5] * dout.z,
+                         R[6] * dout.x + R[7] * dout.y + R[8] * dout.z);
+      v3<G> dl = mk3<G>((G)dl64.x, (G)dl64.y, (G)dl64.z);
+      V ul64 = dl64;
       V rl_lab = mk3(R[0] * r.x + R[1] * r.y + R[2] * r.z, R[3] * r.x + R[4] * r.y + R[5] * r.z,
                      R[6] * r.x + R[7] * r.y + R[8] * r.z);
       double phase = opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
@@ -396,12 +404,13 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
         const V u = mk3((R[0] * Mb.x + R[1] * Mb.y + R[2] * Mb.z) * ir, (R[3] * Mb.x + R[4] * Mb.y + R[5] * Mb.z) * ir,
                         (R[6] * Mb.x + R[7] * Mb.y + R[8] * Mb.z) * ir);
         ul = mk3<G>((G)u.x, (G)u.y, (G)u.z);
+        ul64 = u;
         // refer the phase to the rounded direction, as the far field does: the
-        // carry from u to (G)u, whose near_scale is R / d_M to second order in
-        // the rounding
+        // phase gained from R u to the sphere's point along (G)u (exact, also
+        // where d_M vanishes)
         if (sizeof(G) < 8)
-          phase += P.k * (rl_lab.x * (u.x - (double)ul.x) + rl_lab.y * (u.y - (double)ul.y) +
-                          rl_lab.z * (u.z - (double)ul.z)) * (P.robs * rcp_d(dM));
+          phase += near_carry(P.k * P.robs, P.k * rl_lab.x, P.k * rl_lab.y, P.k * rl_lab.z, u.x, u.y, u.z,
+                              (double)ul.x, (double)ul.y, (double)ul.z);
       }
       G sph, cph;
       if (sizeof(G) == 8) sincos_t((G)phase, &sph, &cph);
@@ -421,6 +430,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
       e.det_neg = detQ < 0.0;
       e.dir = dl;
       e.obs = ul;
+      e.obs64 = ul64;
       e.rexit = rl_lab;
       e.phase = phase;
       e.amp = amp;

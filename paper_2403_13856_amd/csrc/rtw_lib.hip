@@ -171,10 +171,13 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   P.p_min = o->p_min;
   P.p_max = o->p_max;
   P.n_pol = inc->n_pol;
-  // FP64 re-trace above this amplification: an FP32 divergence factor then
-  // carries at most 128 x 2^-24 relative error, 1.5e-5 in intensity (15% of
-  // the mixed path's 1e-4 bar)
-  P.amplif_limit = 128.0;
+  // FP64 re-trace above this amplification.  Against the FP64 oracle an FP32
+  // divergence factor carries up to ~8 x amplif x 2^-24 relative error (the
+  // rounding of the whole FP32 WFC chain, not one operation: 4.1e-5 at amplif
+  // 87 on the 60/50/40 um ellipsoid observed at 90 um), and a node's intensity
+  // error relative to its incoherent sum is up to 2 n_b times that for n_b
+  // contributions in phase; at 32 that stays below 1e-4 for n_b <= 4
+  P.amplif_limit = 32.0;
   return P;
 }
 

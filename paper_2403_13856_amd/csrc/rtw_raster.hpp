@@ -67,13 +67,33 @@ struct NodeGrid {
 // field is transverse to the direction, so it is stored as its two
 // components on the direction's own (e_theta, e_phi) basis (dir_basis of the
 // stored direction), which leaves room for the copy.
+//
+// An FP32 record also keeps what rounding took from its direction, as three
+// 16-bit integers in units of 2^-39 (each component's residual is at most half
+// an FP32 ulp, 2^-25, so |q| <= 2^14; the rebuilt direction is exact to
+// 2^-40): the hit store forms the interpolation weights from the FP64
+// direction, because on a long thin triangle (rays near grazing incidence,
+// whose exit directions spread along one edge) the rounding of a vertex moves
+// the weights by its size over the triangle's small height, up to ~1e-4.
+template <typename G>
+struct RecTail {
+  G pad[2];
+};
+template <>
+struct RecTail<float> {
+  int16_t dlo[3];  // (direction - stored FP32 direction) * 2^39
+  int16_t pad;
+};
+constexpr double DLO_SCALE = 549755813888.0;  // 2^39
+
 template <typename G>
 struct alignas(16 * sizeof(G)) RayRec {
   G kr[3];   // k r_exit (lab)
   G dir[3];  // the stored exit direction (as in Records::dir)
   G f[8];    // [pol][e_theta|e_phi][re|im]: field amp e^{i phase} (J_perp e_perp + J_par e_par)
-  G pad[2];
+  RecTail<G> tail;
 };
+static_assert(sizeof(RayRec<float>) == 64 && sizeof(RayRec<double>) == 128, "record sizes");
 
 // (e_theta, e_phi) of a direction d (not necessarily of unit length, as
 // stored): with rho = |(dx, dy)|, cos phi = dx / rho, sin phi = dy / rho
@@ -178,6 +198,17 @@ constexpr int CAND_INLINE = 4096;  // default: triangles with more box candidate
 // so the box never excludes a node that the exact membership test accepts.
 constexpr double BOX_MARGIN = 4e-6;
 
+__device__ __forceinline__ void set_tail(RecTail<double>& t, const v3<double>&, const Dir4<double>&) {
+  t.pad[0] = t.pad[1] = 0.0;
+}
+__device__ __forceinline__ void set_tail(RecTail<float>& t, const v3<double>& d, const Dir4<float>& dv) {
+  const double q[3] = {rint((d.x - (double)dv.x) * DLO_SCALE), rint((d.y - (double)dv.y) * DLO_SCALE),
+                       rint((d.z - (double)dv.z) * DLO_SCALE)};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t.dlo[i] = (int16_t)fmin(32767.0, fmax(-32767.0, q[i]));
+  t.pad = 0;
+}
+
 // Sink writing the compact emission records used by the rasteriser.  In the
 // mixed path an emission whose divergence factor is ill-conditioned for FP32
 // (amplif > amplif_limit) marks the ray for an FP64 re-trace.
@@ -207,10 +238,7 @@ struct RecordSink {
     // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
     double cre = 1.0, cim = 0.0;
     if (sizeof(E) > sizeof(G)) {
-      const double dpx = (double)e.obs.x - (double)dv.x, dpy = (double)e.obs.y - (double)dv.y,
-                   dpz = (double)e.obs.z - (double)dv.z;
-      const double dphi = k * (e.rexit.x * dpx + e.rexit.y * dpy + e.rexit.z * dpz) *
-                          near_scale(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
+      const double dphi = near_carry(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
                                      (double)e.obs.y, (double)e.obs.z, (double)dv.x, (double)dv.y, (double)dv.z);
       sincos(dphi, &cim, &cre);
     }
@@ -228,7 +256,7 @@ struct RecordSink {
       r.f[p * 4 + 3] = live ? (G)(br * cim + bi * cre) : (G)0;
     }
     r.dir[0] = dv.x; r.dir[1] = dv.y; r.dir[2] = dv.z;
-    r.pad[0] = r.pad[1] = (G)0;
+    set_tail(r.tail, e.obs64, dv);
     rec.rr[at] = r;
     rec.dir[at] = dv;
     const float dx = (float)e.obs.x, dy = (float)e.obs.y, dz = (float)e.obs.z;
@@ -715,6 +743,15 @@ __device__ __forceinline__ v3<float> node_dir_g<float>(const NodeGrid& ng, int i
   return mk3<float>(st * ng.cphf[ip], st * ng.sphf[ip], ng.cthf[it]);
 }
 
+// The FP64 node-space direction of a record: for FP32 records the stored
+// direction plus its rounding residual.
+__device__ __forceinline__ v3<double> full_dir(const RayRec<double>& r) { return mk3(r.dir[0], r.dir[1], r.dir[2]); }
+__device__ __forceinline__ v3<double> full_dir(const RayRec<float>& r) {
+  const double s = 1.0 / DLO_SCALE;
+  return mk3((double)r.dir[0] + (double)r.tail.dlo[0] * s, (double)r.dir[1] + (double)r.tail.dlo[1] * s,
+             (double)r.dir[2] + (double)r.tail.dlo[2] * s);
+}
+
 // Contribution of the hit in pool slot idx (its descriptor), stored at its
 // place in its node's range (node-major order): the range start from the
 // scan plus the rank the rasteriser took with the node's count, so this
@@ -740,20 +777,32 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
   for (int p = 0; p < 2; ++p)
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
   const v3<double> n = node_dir(ng, it, ip);
+  G lam[3] = {d.lam[0], d.lam[1], d.lam[2]};
+  if (sizeof(G) == 4) {
+    // weights of the central projection from the FP64 vertex directions
+    // (stored direction plus its rounding residual): (d_a x d_b).n over the
+    // cyclic edges, normalised
+    v3<double> dd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dd[k] = full_dir(rec.rr[rb + vid[k]]);
+    const double w0 = dot(cross(dd[1], dd[2]), n), w1 = dot(cross(dd[2], dd[0]), n), w2 = dot(cross(dd[0], dd[1]), n);
+    const double sw = w0 + w1 + w2;
+    if (sw != 0.0) {
+      const double is = 1.0 / sw;
+      lam[0] = (G)(w0 * is); lam[1] = (G)(w1 * is); lam[2] = (G)(w2 * is);
+    }
+  }
   for (int k = 0; k < 3; ++k) {
     const RayRec<G>& vr = rec.rr[rb + vid[k]];
     const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
     // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
-    double psi = (double)vr.kr[0] * ((double)dk.x - n.x) + (double)vr.kr[1] * ((double)dk.y - n.y) +
-                 (double)vr.kr[2] * ((double)dk.z - n.z);
-    if (ng.kappa > 0.0)
-      psi *= near_scale(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dk.x, (double)dk.y,
-                        (double)dk.z, n.x, n.y, n.z);
+    const double psi = near_carry(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dk.x,
+                                  (double)dk.y, (double)dk.z, n.x, n.y, n.z);
     G s_, c_;
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
     else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
-    const G lr = d.lam[k] * c_, li = d.lam[k] * s_;
+    const G lr = lam[k] * c_, li = lam[k] * s_;
     // the vertex field is stored on its direction's (e_theta, e_phi); turn it
     // onto the node's
     v3<double> et, ep;

@@ -167,20 +167,21 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def trace(part, inc, opts, device="cuda", stream=None):
-    """Per-ray records of every emitted order (rtw_trace); FP64 tensors on the device."""
+RECORD_NAMES = ("flags", "dir", "rexit", "phase", "amp", "field", "cond")
+
+
+def trace(part, inc, opts, device="cuda", stream=None, records=RECORD_NAMES):
+    """Per-ray records of every emitted order (rtw_trace); FP64 tensors on the
+    device, for the record names listed (the others are not written)."""
     import torch
     N = opts.grid_n
     n_ord = opts.p_max - opts.p_min + 1
     NN = N * N
-    out = dict(flags=torch.empty((n_ord, NN), dtype=torch.int32, device=device),
-               dir=torch.empty((n_ord, 3, NN), dtype=torch.float64, device=device),
-               rexit=torch.empty((n_ord, 3, NN), dtype=torch.float64, device=device),
-               phase=torch.empty((n_ord, NN), dtype=torch.float64, device=device),
-               amp=torch.empty((n_ord, NN), dtype=torch.float64, device=device),
-               field=torch.empty((n_ord, inc.n_pol, 3, 2, NN), dtype=torch.float64, device=device),
-               cond=torch.empty((n_ord, 2, NN), dtype=torch.float64, device=device))
-    rec = RayRecords(*[_ptr(out[k]) for k in ("flags", "dir", "rexit", "phase", "amp", "field", "cond")])
+    shapes = dict(flags=(n_ord, NN), dir=(n_ord, 3, NN), rexit=(n_ord, 3, NN), phase=(n_ord, NN), amp=(n_ord, NN),
+                  field=(n_ord, inc.n_pol, 3, 2, NN), cond=(n_ord, 2, NN))
+    out = {k: torch.empty(shapes[k], dtype=torch.int32 if k == "flags" else torch.float64, device=device)
+           for k in RECORD_NAMES if k in records}
+    rec = RayRecords(*[_ptr(out.get(k)) for k in RECORD_NAMES])
     _check(load().rtw_trace(ctypes.byref(part), ctypes.byref(inc), ctypes.byref(opts), ctypes.byref(rec),
                             _stream_ptr(stream)))
     return out

@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import parity as PAR
 from paper_2403_13856_amd import inputs as I
 
 torch = pytest.importorskip("torch")
@@ -93,31 +94,18 @@ def test_orders_up_to_15_farfield_sphere(oracle, R):
     axes, euler, m, N = (10.0, 10.0, 10.0), (0.0, 0.0, 0.0), 1.333, 256
     th = np.arange(0.0, 180.01, 1.0)
     ph = np.arange(0.0, 360.0, 2.0)
-    ref = oracle.farfield(oracle.particle(axes, euler, m), oracle.setup(LAM, 2, 0, 15, N), th, ph)
+    ref = oracle.farfield(oracle.particle(axes, euler, m), oracle.setup(LAM, 2, 0, 15, N), th, ph,
+                          edge_band_deg=PAR.EDGE_BAND_MIXED)
     inc = ref["incoh"]
     for prec in (R.FP64, R.MIXED):
         ff = R.FarField(R.make_particle(axes, euler, m), R.make_incident(LAM, 2), R.make_opts(0, 15, N, prec), th, ph)
         F = ff().cpu().numpy()
         nc = ff.ncontrib.cpu().numpy()
         if prec == R.FP64:
-            clean = (ref["flags"] & 7) == 0
-            err = np.abs(F - ref["field"]).max(axis=(0, 1)) / np.maximum(np.sqrt(inc), 1e-300)
-            worst = err[clean & (inc > 0)]
-            say(f"[p<=15 farfield fp64] sphere: worst {worst.max():.2e} on {clean.mean():.3f} of nodes")
-            assert clean.mean() > 0.5
-            assert worst.max() < 1e-10
-            assert np.array_equal(nc[clean], ref["ncontrib"][clean])
+            frac = PAR.compare_fp64(ref, F, nc, 1e-10, None, say, "[p<=15 farfield] sphere ")
+            assert frac > 0.5
         else:
-            clean = ref["flags"] == 0
-            unc = np.maximum(ref["uncancelled"], inc)
-            I_ref = (np.abs(ref["field"]) ** 2).sum(axis=(0, 1))
-            I_got = (np.abs(F) ** 2).sum(axis=(0, 1))
-            sel = clean & (inc > 0)
-            rel = np.abs(I_got - I_ref)[sel] / unc[sel]
-            big = (np.abs(ref["field"]) >= 0.1 * np.sqrt(inc)[None, None]) & sel[None, None]
-            dph = np.abs(np.angle(F[big] * np.conj(ref["field"][big])))
-            say(f"[p<=15 farfield mixed] sphere: intensity rel max {rel.max():.2e} phase max {dph.max():.2e}")
-            assert rel.max() < 1e-4 and dph.max() < 1e-3
+            PAR.compare_mixed(ref, F, say=say, tag="[p<=15 farfield] sphere ")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

@@ -1,27 +1,24 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle, element
 by element, on seeded inputs.
 
-Bars (written per test):
-* FP64 path: per-ray records and far fields within 1e-10 relative; integer
+Bars (written per test; the far-field comparisons are tests/parity.py's):
+* FP64 path: per-ray records within 1e-10 relative, or within COND_C eps cond
+  where the GPU's own conditioning record cond says the divergence factor is
+  defined no better; far fields within 1e-10 relative on every node outside
+  the caustic and pole bands, tie nodes and sheet edges included; integer
   results (which orders are emitted, focal-line counts, contributions per
   node) identical.
-* Mixed path (FP32 geometry, FP64 phase): far-field intensity within 1e-4 of
-  the node's incoherent sum sum_b |f_b|^2, phase within 1e-3 rad where
-  |F| >= 0.1 sqrt(sum_b |f_b|^2).
-* Nodes the oracle flags are compared by what is unique there: tie nodes (a
-  barycentric weight within 1e-9 of zero -- either neighbouring triangle is a
-  valid owner), 0.1 deg bands around dropped fold triangles (the caustics,
-  where geometric optics diverges), and the poles theta < 0.1 deg or
-  > 179.9 deg.  The mixed path also leaves out the 0.1 deg bands along the
-  edges of each order's ray sheet (where some rays stop emitting the order):
-  the field ends there, so a node within FP32 rounding of the last triangle
-  belongs to it on one side and not on the other.  FP64 compares them.
+* Mixed path (FP32 wave quantities, FP64 phase): far-field intensity within
+  1e-4 of the node's incoherent sum sum_b |f_b|^2, phase within 1e-3 rad
+  where |F| >= 0.1 sqrt(sum_b |f_b|^2), on every node outside the 0.1 deg
+  caustic and pole bands and 1e-4 deg of a sheet edge.
 """
 import sys
 
 import numpy as np
 import pytest
 
+import parity as PAR
 from paper_2403_13856_amd import inputs as I
 
 torch = pytest.importorskip("torch")
@@ -83,13 +80,17 @@ def test_trace_fp64_matches_oracle(oracle, R, ci):
     assert np.abs(got["dir"] - ref["dir"]).max() < 1e-12
     assert np.abs(got["rexit"] - ref["rexit"]).max() < 1e-10 * scale
     assert np.abs(got["phase"] - ref["phase"]).max() < 1e-10 * max(1.0, np.abs(ref["phase"]).max())
+    # per ray: 1e-10, or the ray's FP64 conditioning (divergence factor, exit point)
+    bound = np.maximum(1e-10, PAR.COND_C * PAR.EPS64 * PAR.ray_conditioning(got, 2 * np.pi / 0.6328))
     amp_rel = np.abs(got["amp"][v] - ref["amp"][v]) / ref["amp"][v]
-    assert amp_rel.max() < 1e-10, amp_rel.max()
+    say(f"   amp worst {amp_rel.max():.2e}; {(amp_rel >= 1e-10).sum()} rays above 1e-10 "
+        f"(cond up to {got['cond'][:, 0][v].max():.2e})")
+    assert np.all(amp_rel < bound[v]), (amp_rel / bound[v]).max()
     F = ref["field"][..., 0, :] + 1j * ref["field"][..., 1, :]
     Fg = got["field"][..., 0, :] + 1j * got["field"][..., 1, :]
     mag = np.sqrt((np.abs(F) ** 2).sum(axis=(1, 2), keepdims=True))
-    err = np.abs(Fg - F) / np.maximum(mag, 1e-300)
-    assert err[np.broadcast_to(v[:, None, None, :], err.shape)].max() < 1e-10
+    err = (np.abs(Fg - F) / np.maximum(mag, 1e-300)).max(axis=(1, 2))
+    assert np.all(err[v] < bound[v]), (err[v] / bound[v]).max()
 
 
 @pytest.mark.parametrize("ci", range(len(TRACE_CASES)))
@@ -125,16 +126,7 @@ def _farfield_gpu(R, gp, gi, go, theta, phi, hits_per_node=6.0):
 
 
 def _compare_fp64(ref, F, nc, tol=1e-10):
-    flags = ref["flags"]
-    clean = (flags & 7) == 0  # sheet-edge bands (bit 3) stay compared: FP64 membership there agrees
-    inc = np.sqrt(ref["incoh"])
-    err = np.abs(F - ref["field"]).max(axis=(0, 1))
-    worst = (err / np.maximum(inc, 1e-300))[clean & (inc > 0)]
-    assert worst.max(initial=0.0) < tol, worst.max(initial=0.0)
-    # nodes the oracle leaves empty stay empty
-    assert np.abs(F[..., clean & (inc == 0)]).max(initial=0.0) == 0.0
-    assert np.array_equal(nc[clean], ref["ncontrib"][clean])
-    return clean.mean()
+    return PAR.compare_fp64(ref, F, nc, tol)
 
 
 def test_farfield_fp64_sphere(oracle, R):
@@ -149,9 +141,10 @@ def test_farfield_fp64_sphere(oracle, R):
         assert frac > 0.95
 
 
-def test_farfield_fp64_ellipsoid(oracle, R):
+@pytest.mark.parametrize("N", [96, 2048])
+def test_farfield_fp64_ellipsoid(oracle, R, N):
+    """N = 2048 is the benchmark workload at its full size (the FP64 leg bench.py times)."""
     w = I.ellipsoid_mixed()
-    N = 96
     say(f"[farfield fp64] ellipsoid N={N} full node grid")
     op, os_, gp, gi, go = _oracle_pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.wavelength, w.n_pol,
                                       w.p_min, w.p_max, N, R.FP64)
@@ -162,21 +155,7 @@ def test_farfield_fp64_ellipsoid(oracle, R):
 
 
 def _compare_mixed(ref, F, int_tol=1e-4, ph_tol=1e-3):
-    """Intensity error relative to the size of the interpolated terms before
-    they cancel, sum_b (sum_v |lambda_v| |F_v|)^2 -- equal to the incoherent
-    sum sum_b |f_b|^2 wherever the grid resolves the phase across a triangle
-    (median ratio 1.0001 on the 256^2 ellipsoid), larger only where a coarse
-    grid makes the interpolation itself ill-conditioned."""
-    clean = ref["flags"] == 0
-    inc = ref["incoh"]
-    unc = np.maximum(ref["uncancelled"], inc)
-    I_ref = (np.abs(ref["field"]) ** 2).sum(axis=(0, 1))
-    I_got = (np.abs(F) ** 2).sum(axis=(0, 1))
-    sel = clean & (inc > 0)
-    rel = np.abs(I_got - I_ref)[sel] / unc[sel]
-    big = (np.abs(ref["field"]) >= 0.1 * np.sqrt(inc)[None, None]) & sel[None, None]
-    dph = np.abs(np.angle(F[big] * np.conj(ref["field"][big])))
-    return rel, dph
+    return PAR.compare_mixed(ref, F, int_tol, ph_tol, say)
 
 
 @pytest.mark.parametrize("N", [256, 2048])
@@ -186,14 +165,13 @@ def test_farfield_mixed_ellipsoid(oracle, R, N):
     say(f"[farfield mixed] ellipsoid N={N} nodes={w.n_nodes}")
     op, os_, gp, gi, go = _oracle_pair(oracle, R, w.semi_axes, w.euler_deg, w.m, w.wavelength, w.n_pol,
                                       w.p_min, w.p_max, N, R.MIXED)
-    ref = oracle.farfield(op, os_, w.theta_deg, w.phi_deg)
+    ref = PAR.oracle_farfield(oracle, op, os_, w.theta_deg, w.phi_deg, mixed=True)
     F, nc, ff = _farfield_gpu(R, gp, gi, go, w.theta_deg, w.phi_deg)
     hits, fp64 = ff.stats()
     rel, dph = _compare_mixed(ref, F)
-    say(f"   intensity rel max {rel.max():.3e} p99.99 {np.quantile(rel, 0.9999):.3e}; "
-        f"phase max {dph.max():.3e}; hits {hits}; rays re-traced in FP64 {fp64} of {N * N}")
-    assert rel.max() < 1e-4
-    assert dph.max() < 1e-3
+    say(f"   intensity rel p99.99 {np.quantile(rel, 0.9999):.3e}; hits {hits}; rays re-traced in FP64 {fp64} "
+        f"of {N * N}")
+    assert rel.size > 0.95 * w.n_nodes
 
 
 def test_farfield_deterministic(R):
@@ -220,15 +198,13 @@ def test_farfield_edge_cases(oracle, R):
             ph = np.asarray(ph, float)
             op, os_, gp, gi, go = _oracle_pair(oracle, R, (40.0, 35.0, 30.0), (15.0, 25.0, 35.0), 1.333, 0.6328, 2,
                                               pmin, pmax, N, prec)
-            ref = oracle.farfield(op, os_, th, ph)
+            ref = PAR.oracle_farfield(oracle, op, os_, th, ph, mixed=prec == R.MIXED)
             F, nc, _ = _farfield_gpu(R, gp, gi, go, th, ph)
             say(f"   precision={prec} N={N} nodes={th.size}x{ph.size} p={pmin}..{pmax}")
             if prec == R.FP64:
                 _compare_fp64(ref, F, nc)
             else:
-                rel, dph = _compare_mixed(ref, F)
-                say(f"      intensity rel max {rel.max(initial=0.0):.3e} phase max {dph.max(initial=0.0):.3e}")
-                assert rel.max(initial=0.0) < 1e-4 and dph.max(initial=0.0) < 1e-3
+                _compare_mixed(ref, F)
 
 
 def test_workspace_overflow_is_reported_and_recovered(oracle, R):
@@ -315,10 +291,7 @@ def test_paper_spheroid_strips_match_oracle(oracle, R):
                                       w.p_max, w.grid_n, R.MIXED)
     for th in (I.uniform_angles(136.0, 140.0, 0.01), I.uniform_angles(5.0, 6.0, 0.01)):
         say(f"[paper spheroid] N={w.grid_n}, theta {th[0]:.2f}..{th[-1]:.2f} step 0.01 x phi {ph.tolist()}")
-        ref = oracle.farfield(op, os_, th, ph)
+        ref = PAR.oracle_farfield(oracle, op, os_, th, ph, mixed=True)
         F, nc, _ = _farfield_gpu(R, gp, gi, go, th, ph)
         rel, dph = _compare_mixed(ref, F)
-        say(f"   compared {rel.size} nodes: intensity rel max {rel.max(initial=0.0):.3e} "
-            f"phase max {dph.max(initial=0.0):.3e}")
         assert rel.size > 0.5 * th.size * ph.size
-        assert rel.max(initial=0.0) < 1e-4 and dph.max(initial=0.0) < 1e-3
