@@ -28,7 +28,11 @@ class Particle(ctypes.Structure):
 class Setup(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("n_pol", ctypes.c_int), ("p_min", ctypes.c_int),
                 ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int), ("source_distance", ctypes.c_double),
-                ("observation_radius", ctypes.c_double)]
+                ("observation_radius", ctypes.c_double), ("corrections", ctypes.c_int)]
+
+
+CAUSTIC = 1      # uniform Airy form across fold caustics (reading R12)
+DIFFRACTION = 2  # forward Fraunhofer diffraction of the shadow (reading R13)
 
 
 class Emit(ctypes.Structure):
@@ -70,6 +74,9 @@ def lib():
         _lib.rtwo_grid_halfwidth_source.restype = ctypes.c_double
         _lib.rtwo_fresnel.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib.rtwo_set_threads.argtypes = [ctypes.c_int]
+        _lib.rtwo_airy_neg.argtypes = [ctypes.c_double, dp, dp]
+        _lib.rtwo_bessel_j1.argtypes = [ctypes.c_double]
+        _lib.rtwo_bessel_j1.restype = ctypes.c_double
         _lib.rtwo_get_threads.restype = ctypes.c_int
     return _lib
 
@@ -90,10 +97,13 @@ def particle(semi_axes, euler_deg=(0.0, 0.0, 0.0), m=1.333):
     return p
 
 
-def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64, source_distance=0.0, observation_radius=0.0):
+def setup(wavelength=0.6328, n_pol=1, p_min=0, p_max=2, grid_n=64, source_distance=0.0, observation_radius=0.0,
+          corrections=0):
     """Trace settings; source_distance > 0 puts a point source at lab (0, 0, -source_distance);
-    observation_radius > 0 observes on the sphere of that radius instead of the far field."""
+    observation_radius > 0 observes on the sphere of that radius instead of the far field;
+    corrections: CAUSTIC | DIFFRACTION."""
     s = Setup()
+    s.corrections = int(corrections)
     s.source_distance = float(source_distance)
     s.observation_radius = float(observation_radius)
     s.wavelength = float(wavelength)
@@ -126,6 +136,17 @@ def trace_rays(part, st, xy):
     if rc != 0:
         raise ValueError("rtwo_trace_rays rejected its arguments")
     return out
+
+
+def airy_neg(z):
+    """(Ai(-z), Ai'(-z)) for z >= 0."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().rtwo_airy_neg(float(z), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def bessel_j1(x):
+    return lib().rtwo_bessel_j1(float(x))
 
 
 def fresnel(m_rel, ci):

@@ -74,6 +74,31 @@
  *      E(M) tangent to the sphere at M is an output (the radial part, of
  *      relative size |r_exit| / R, is dropped at the vertex); the output is its
  *      projection on the node's (e_theta, e_phi).
+ *  R12 Correction at fold caustics (the wave correction near caustics that the
+ *      paper names without formulas): where an order's two branches coalesce
+ *      at a fold their focal-line counts differ by one.  At a node holding
+ *      exactly two contributions of one order, a with N_f = n and b with
+ *      N_f = n + 1, their geometric-optics sum is replaced by the uniform
+ *      asymptotic (Airy) form of Chester, Friedman and Ursell (1957) in
+ *      Ludwig's (1966) two-ray form: with the branches' interpolated fields
+ *      f_a, f_b and their carried phases phi_a, phi_b (each the barycentric
+ *      mean of its rays' phases carried to the node, focal lines included),
+ *      Delta = (phi_b - phi_a) / 2 + pi / 4 is half their path-phase
+ *      difference, (2/3) zeta^{3/2} = Delta, and
+ *        u = sqrt(pi) e^{-i pi/4} [ (f_a e^{i Delta} + i f_b e^{-i Delta}) zeta^{1/4} Ai(-zeta)
+ *                                - i (f_a e^{i Delta} - i f_b e^{-i Delta}) zeta^{-1/4} Ai'(-zeta) ],
+ *      which tends to f_a + f_b far from the fold (large zeta).  Nodes with
+ *      Delta <= 0 keep the sum; the dark side of the fold gets no field.
+ *  R13 Forward diffraction (not in the paper's ray path; plane wave, far
+ *      field): by Babinet's principle the particle's shadow diffracts like an
+ *      aperture of its shape.  The shadow of the ellipsoid on the plane
+ *      z = 0 is the ellipse rho^T S2^-1 rho <= 1, S2 the x-y block of
+ *      R diag(a^2, b^2, c^2) R^T; its Fraunhofer amplitude in direction n is
+ *      F_d = (i k / 2 pi) pi sqrt(det S2) 2 J1(k s) / (k s), s = sqrt(n_t^T S2 n_t),
+ *      n_t the projection of n on the plane (F_d(0) = i k area / 2 pi, the
+ *      forward amplitude the optical theorem pairs with the shadow), carried
+ *      by the incident polarisation in the frame (e_theta, e_phi) that turns
+ *      with phi: x gives (cos phi, -sin phi), y gives (sin phi, cos phi).
  */
 #include "rtw_oracle.h"
 
@@ -222,6 +247,7 @@ typedef struct {
   double zs;        /* point-source distance (0: plane wave) */
   double robs;      /* observation radius (0: far field) */
   int n_pol, p_min, p_max;
+  int corr;         /* RTWO_CAUSTIC | RTWO_DIFFRACTION */
 } ctx_t;
 
 static void Avec(const ctx_t* c, const double* v, double* o) {
@@ -545,6 +571,11 @@ static int setup_ctx(const rtwo_particle* part, const rtwo_setup* st, ctx_t* c) 
   double amax = fmax(part->semi_axes[0], fmax(part->semi_axes[1], part->semi_axes[2]));
   if (!(st->source_distance == 0.0 || st->source_distance > amax)) return -1;
   if (!(st->observation_radius == 0.0 || st->observation_radius > amax)) return -1;
+  if (st->corrections & ~(RTWO_CAUSTIC | RTWO_DIFFRACTION)) return -1;
+  /* the Fraunhofer term of R13 is that of a plane wave in the far field */
+  if ((st->corrections & RTWO_DIFFRACTION) && (st->source_distance != 0.0 || st->observation_radius != 0.0))
+    return -1;
+  c->corr = st->corrections;
   c->zs = st->source_distance;
   c->robs = st->observation_radius;
   for (int i = 0; i < 3; i++) c->A[i] = 1.0 / (part->semi_axes[i] * part->semi_axes[i]);
@@ -614,6 +645,7 @@ double rtwo_grid_halfwidth_source(const rtwo_particle* part, double source_dista
 typedef struct {
   int valid, nf, det_neg;
   double dir[3], kr[3];
+  double phase;  /* path and focal-line phase at dir (rad), unreduced */
   cplx f[2][3];
 } cray;
 
@@ -736,7 +768,30 @@ typedef struct {
   int* ncontrib;
   double* uncancelled;
   long n_nodes;
+  struct clist* list;    /* R12: contributions kept per node instead of summed (NULL: summed) */
+  int slot;              /* order slot of the triangle */
 } tri_job;
+
+/* One triangle's contribution to one node, kept for the fold-caustic form. */
+typedef struct {
+  long node, seq;
+  int nf;
+  double phi;      /* barycentric mean of the rays' phases carried to the node */
+  cplx f[2][2];    /* [pol][theta|phi] */
+} centry;
+struct clist {
+  centry* e;
+  long n, cap;
+};
+static void clist_push(struct clist* L, const centry* x) {
+  if (L->n == L->cap) {
+    L->cap = L->cap ? 2 * L->cap : 4096;
+    L->e = realloc(L->e, sizeof(centry) * (size_t)L->cap);
+  }
+  L->e[L->n] = *x;
+  L->e[L->n].seq = L->n;
+  L->n++;
+}
 
 /* Edge function of the canonical edge (lower ray id first): (d_i x d_j) . n */
 static double edge_fn(const double* di, const double* dj, const double* n) {
@@ -772,6 +827,26 @@ static void tri_node(int node, void* user) {
   double lam[3] = {w[0] / sw, w[1] / sw, w[2] / sw};
   const double* et = &J->nd->etheta[3 * (long)node];
   const double* ep = &J->nd->ephi[3 * (long)node];
+  centry ce;
+  memset(&ce, 0, sizeof(ce));
+  ce.node = node;
+  ce.nf = J->v[0]->nf;
+  for (int k = 0; k < 3; k++) {
+    /* the ray's phase carried to the node (the argument of its carry) */
+    const cray* v = J->v[k];
+    double dn[3] = {n[0] - v->dir[0], n[1] - v->dir[1], n[2] - v->dir[2]}, carry;
+    if (J->kappa > 0.0) {
+      double a[3], b[3];
+      for (int x = 0; x < 3; x++) {
+        a[x] = J->kappa * n[x] - v->kr[x];
+        b[x] = J->kappa * v->dir[x] - v->kr[x];
+      }
+      carry = -dot3(v->kr, dn) * 2.0 * J->kappa / (norm3(a) + norm3(b));
+    } else {
+      carry = -dot3(v->kr, dn);
+    }
+    ce.phi += lam[k] * (v->phase + carry);
+  }
   for (int p = 0; p < J->n_pol; p++) {
     cplx ft = 0, fp = 0;
     double ut = 0, up = 0; /* magnitudes of the summed terms (before cancellation) */
@@ -801,13 +876,157 @@ static void tri_node(int node, void* user) {
       up += fabs(lam[k]) * cabs(vp);
     }
     if (J->uncancelled) J->uncancelled[node] += ut * ut + up * up;
-    long base_t = ((long)(p * 2 + 0) * J->n_nodes + node) * 2;
-    long base_p = ((long)(p * 2 + 1) * J->n_nodes + node) * 2;
-    J->field[base_t] += creal(ft); J->field[base_t + 1] += cimag(ft);
-    J->field[base_p] += creal(fp); J->field[base_p + 1] += cimag(fp);
+    ce.f[p][0] = ft;
+    ce.f[p][1] = fp;
+    if (!J->list) {
+      long base_t = ((long)(p * 2 + 0) * J->n_nodes + node) * 2;
+      long base_p = ((long)(p * 2 + 1) * J->n_nodes + node) * 2;
+      J->field[base_t] += creal(ft); J->field[base_t + 1] += cimag(ft);
+      J->field[base_p] += creal(fp); J->field[base_p + 1] += cimag(fp);
+    }
     J->incoh[node] += creal(ft * conj(ft)) + creal(fp * conj(fp));
   }
+  if (J->list) clist_push(J->list, &ce);
   J->ncontrib[node] += 1;
+}
+
+/* ---- special functions of the corrections ---- */
+
+/* Ai(-z), Ai'(-z) for z >= 0.  Below z = 10: Taylor steps of the Airy
+ * equation y'' = x y toward x = -z (steps of at most 1/2; at x0 the series
+ * y(x0 + t) = sum c_n t^n has (n + 2)(n + 1) c_{n+2} = x0 c_n + c_{n-1}),
+ * started from Ai(0) = 3^{-2/3} / Gamma(2/3) and Ai'(0) = -3^{-1/3} / Gamma(1/3).
+ * From z = 10 on: the asymptotic expansions of Abramowitz & Stegun 10.4.60 and
+ * 10.4.62 in xi = (2/3) z^{3/2}, twelve terms (their error is below 1e-13 there). */
+void rtwo_airy_neg(double z, double* ai, double* aip) {
+  if (z < 10.0) {
+    double y = 1.0 / (pow(3.0, 2.0 / 3.0) * tgamma(2.0 / 3.0));
+    double yp = -1.0 / (pow(3.0, 1.0 / 3.0) * tgamma(1.0 / 3.0));
+    double x0 = 0.0;
+    int steps = (int)ceil(z / 0.5);
+    double t = steps > 0 ? -z / steps : 0.0;
+    for (int s = 0; s < steps; s++) {
+      double c[64];
+      c[0] = y;
+      c[1] = yp;
+      c[2] = x0 * c[0] / 2.0;
+      for (int n = 1; n + 2 < 64; n++) c[n + 2] = (x0 * c[n] + c[n - 1]) / ((double)(n + 2) * (double)(n + 1));
+      double ny = 0.0, nyp = 0.0, tp = 1.0;
+      for (int n = 0; n < 64; n++) {
+        ny += c[n] * tp;
+        if (n + 1 < 64) nyp += (double)(n + 1) * c[n + 1] * tp;
+        tp *= t;
+      }
+      y = ny;
+      yp = nyp;
+      x0 += t;
+    }
+    *ai = y;
+    *aip = yp;
+    return;
+  }
+  double xi = 2.0 / 3.0 * z * sqrt(z);
+  double u[12], v[12];
+  u[0] = v[0] = 1.0;
+  for (int k = 1; k < 12; k++) {
+    u[k] = u[k - 1] * (6.0 * k - 5.0) * (6.0 * k - 3.0) * (6.0 * k - 1.0) / ((2.0 * k - 1.0) * 216.0 * k);
+    v[k] = -u[k] * (6.0 * k + 1.0) / (6.0 * k - 1.0);
+  }
+  double P = 0, Q = 0, Rr = 0, S = 0, xk = 1.0;
+  for (int k = 0; k < 12; k++) {
+    double sg = ((k / 2) % 2 == 0) ? 1.0 : -1.0;
+    if (k % 2 == 0) { P += sg * u[k] / xk; Rr += sg * v[k] / xk; }
+    else { Q += sg * u[k] / xk; S += sg * v[k] / xk; }
+    xk *= xi;
+  }
+  double sn = sin(xi + PI / 4.0), cs = cos(xi + PI / 4.0);
+  *ai = (sn * P - cs * Q) / (sqrt(PI) * pow(z, 0.25));
+  *aip = -pow(z, 0.25) * (cs * Rr + sn * S) / sqrt(PI);
+}
+
+/* J1(x).  For |x| < 25 Miller's backward recurrence J_{n-1} = (2n / x) J_n -
+ * J_{n+1}, normalised by J_0 + 2 (J_2 + J_4 + ...) = 1; beyond, Hankel's
+ * asymptotic expansion (Abramowitz & Stegun 9.2.5, 9.2.9, 9.2.10) with
+ * fourteen terms. */
+double rtwo_bessel_j1(double x) {
+  double ax = fabs(x), sg = x < 0 ? -1.0 : 1.0;
+  if (ax < 1e-8) return 0.5 * x;
+  if (ax < 25.0) {
+    int M = 2 * ((int)(ax + 15.0 + sqrt(40.0 * ax)) / 2);
+    double jp1 = 0.0, j = 1e-30, j1 = 0.0, norm = 0.0;
+    for (int n = M; n >= 1; n--) {
+      double jm1 = 2.0 * n / ax * j - jp1;
+      jp1 = j;
+      j = jm1;               /* j = J_{n-1} (unnormalised) */
+      if (n - 1 == 1) j1 = j;
+      if ((n - 1) % 2 == 0 && n - 1 > 0) norm += 2.0 * j;
+      if (fabs(j) > 1e250) { j *= 1e-250; jp1 *= 1e-250; j1 *= 1e-250; norm *= 1e-250; }
+    }
+    norm += j;               /* J_0 */
+    return sg * j1 / norm;
+  }
+  double P = 0, Q = 0, a = 1.0, xk = 1.0;
+  for (int k = 0; k < 14; k++) {
+    /* a_k(1) = prod_{j=1..k} (4 - (2j - 1)^2) / (k! 8^k) */
+    if (k > 0) a *= (4.0 - (2.0 * k - 1.0) * (2.0 * k - 1.0)) / (8.0 * k);
+    double sgn = ((k / 2) % 2 == 0) ? 1.0 : -1.0;
+    if (k % 2 == 0) P += sgn * a / xk;
+    else Q += sgn * a / xk;
+    xk *= ax;
+  }
+  double chi = ax - 0.75 * PI;
+  return sg * sqrt(2.0 / (PI * ax)) * (P * cos(chi) - Q * sin(chi));
+}
+
+static int centry_cmp(const void* pa, const void* pb) {
+  const centry *a = pa, *b = pb;
+  if (a->node != b->node) return a->node < b->node ? -1 : 1;
+  return a->seq < b->seq ? -1 : (a->seq > b->seq ? 1 : 0);
+}
+
+/* R12: the kept contributions of one order, node by node: a pair of branches
+ * with focal-line counts n, n + 1 becomes the uniform Airy form, everything
+ * else is summed as it is. */
+static void caustic_combine(struct clist* L, int n_pol, long n_nodes, double* field) {
+  qsort(L->e, (size_t)L->n, sizeof(centry), centry_cmp);
+  for (long i = 0; i < L->n;) {
+    long j = i;
+    while (j < L->n && L->e[j].node == L->e[i].node) j++;
+    const long node = L->e[i].node;
+    cplx out[2][2] = {{0, 0}, {0, 0}};
+    int done = 0;
+    if (j - i == 2 && abs(L->e[i].nf - L->e[i + 1].nf) == 1) {
+      const centry* a = L->e[i].nf < L->e[i + 1].nf ? &L->e[i] : &L->e[i + 1];
+      const centry* b = a == &L->e[i] ? &L->e[i + 1] : &L->e[i];
+      double delta = 0.5 * (b->phi - a->phi) + PI / 4.0;
+      if (delta > 0.0) {
+        double zeta = pow(1.5 * delta, 2.0 / 3.0), ai, aip;
+        rtwo_airy_neg(zeta, &ai, &aip);
+        cplx ea = cexp(I * delta), eb = cexp(-I * delta);
+        double z4 = pow(zeta, 0.25);
+        cplx pre = sqrt(PI) * cexp(-I * PI / 4.0);
+        for (int p = 0; p < n_pol; p++)
+          for (int c = 0; c < 2; c++) {
+            cplx sum = a->f[p][c] * ea + I * b->f[p][c] * eb;
+            cplx dif = a->f[p][c] * ea - I * b->f[p][c] * eb;
+            out[p][c] = pre * (sum * z4 * ai - I * dif * aip / z4);
+          }
+        done = 1;
+      }
+    }
+    if (!done)
+      for (long q = i; q < j; q++)
+        for (int p = 0; p < n_pol; p++)
+          for (int c = 0; c < 2; c++) out[p][c] += L->e[q].f[p][c];
+    for (int p = 0; p < n_pol; p++)
+      for (int c = 0; c < 2; c++) {
+        long base = ((long)(p * 2 + c) * n_nodes + node) * 2;
+        field[base] += creal(out[p][c]);
+        field[base + 1] += cimag(out[p][c]);
+      }
+    i = j;
+  }
+  L->n = 0;
 }
 
 typedef struct { int* nflags; } band_job;
@@ -910,6 +1129,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
         r->valid = ray.active && e->valid;
         if (!r->valid) continue;
         r->nf = e->nf;
+        r->phase = e->phase;
         r->det_neg = e->det_neg;
         for (int x = 0; x < 3; x++) {
           /* node-space direction: the exit direction, or at a finite radius
@@ -930,6 +1150,7 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
   }
 
   /* rasterise every triangle of every order into the node grid */
+  struct clist clist = {NULL, 0, 0};
   for (int o = 0; o < n_ord; o++) {
     for (int iy = 0; iy + 1 < N; iy++)
       for (int ix = 0; ix + 1 < N; ix++) {
@@ -1006,9 +1227,39 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup, int n_thet
           J.ncontrib = nc_buf;
           J.uncancelled = uncancelled;
           J.n_nodes = n_nodes;
+          J.list = (c.corr & RTWO_CAUSTIC) ? &clist : NULL;
+          J.slot = o;
           for_nodes_in_cap(&nd, cen, rho * (1.0 + 1e-9) + 1e-12, tri_node, &J);
         }
       }
+    if (c.corr & RTWO_CAUSTIC) caustic_combine(&clist, n_pol, n_nodes, field);
+  }
+  free(clist.e);
+  if (c.corr & RTWO_DIFFRACTION) {
+    /* R13: the shadow's Fraunhofer amplitude, S2 = x-y block of R diag(a^2) R^T */
+    double S2[2][2];
+    for (int i = 0; i < 2; i++)
+      for (int j = 0; j < 2; j++) {
+        S2[i][j] = 0.0;
+        for (int q = 0; q < 3; q++)
+          S2[i][j] += c.R[i][q] * c.R[j][q] * part->semi_axes[q] * part->semi_axes[q];
+      }
+    double area = PI * sqrt(S2[0][0] * S2[1][1] - S2[0][1] * S2[1][0]);
+    for (long id = 0; id < n_nodes; id++) {
+      double t = th[id / n_phi], f = ph[id % n_phi];
+      double nx = sin(t) * cos(f), ny = sin(t) * sin(f);
+      double s = sqrt(S2[0][0] * nx * nx + 2.0 * S2[0][1] * nx * ny + S2[1][1] * ny * ny);
+      double u = c.k * s;
+      double shape = u < 1e-8 ? 1.0 : 2.0 * rtwo_bessel_j1(u) / u;
+      cplx Fd = I * c.k / (2.0 * PI) * area * shape;
+      double pol[2][2] = {{cos(f), -sin(f)}, {sin(f), cos(f)}};
+      for (int p = 0; p < n_pol; p++)
+        for (int a = 0; a < 2; a++) {
+          long base = ((long)(p * 2 + a) * n_nodes + id) * 2;
+          field[base] += creal(Fd * pol[p][a]);
+          field[base + 1] += cimag(Fd * pol[p][a]);
+        }
+    }
   }
   for (long id = 0; id < n_nodes; id++) {
     double t = th[id / n_phi];

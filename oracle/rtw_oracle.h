@@ -44,7 +44,14 @@ typedef struct {
   double observation_radius; /* 0: far field; > largest semi-axis: the nodes lie on the
                                 sphere of this radius and the output is R e^{-ikR} E(M)
                                 (reading R11) */
+  int corrections;   /* bit 0 (RTWO_CAUSTIC): uniform Airy form across fold caustics
+                        (reading R12); bit 1 (RTWO_DIFFRACTION): forward Fraunhofer
+                        diffraction of the particle's shadow (reading R13); plane wave
+                        and far field only */
 } rtwo_setup;
+
+#define RTWO_CAUSTIC 1
+#define RTWO_DIFFRACTION 2
 
 /* Everything the oracle knows about one emitted order of one ray. */
 typedef struct {
@@ -126,6 +133,14 @@ int rtwo_farfield(const rtwo_particle* part, const rtwo_setup* setup,
                   int n_theta, const double* theta_deg, int n_phi, const double* phi_deg,
                   double band_deg, double edge_band_deg, double* field, double* incoh, int* nflags, int* ncontrib,
                   double* uncancelled);
+
+/* Airy function and its derivative on the negative axis: ai = Ai(-z), aip =
+ * Ai'(-z) for z >= 0 (Taylor stepping of Ai'' = x Ai from the values at 0 below
+ * z = 10, the asymptotic expansion beyond). */
+void rtwo_airy_neg(double z, double* ai, double* aip);
+
+/* Bessel function of the first kind of order one. */
+double rtwo_bessel_j1(double x);
 
 /* Fresnel coefficients of the paper's Eq. 8 for a real relative index m_rel =
  * n_other/n_current and the incidence cosine ci (0 < ci <= 1).  Outputs
