@@ -103,10 +103,36 @@ typedef struct {
   double observation_radius; /* 0: far field; R (um): nodes on the sphere of radius R */
 } rtw_incident;
 
+/* Corrections of the far field beyond the ray sum (rtw_trace_opts.corrections,
+ * bit flags; they change rtw_farfield and rtw_batch, not the per-ray records):
+ *   RTW_CAUSTIC: wave correction at fold caustics (the rainbows), which the
+ *     paper applies near caustics without giving formulas.  Where a node holds
+ *     exactly two contributions of one order whose focal-line counts differ by
+ *     one (the two branches that coalesce at a fold), their sum is replaced by
+ *     the uniform asymptotic Airy form of Chester, Friedman and Ursell (1957),
+ *     in Ludwig's (1966) two-ray form: with the branches' fields f_a (N_f = n),
+ *     f_b (N_f = n + 1) and their phases phi_a, phi_b carried to the node,
+ *     Delta = (phi_b - phi_a) / 2 + pi / 4, (2/3) zeta^{3/2} = Delta,
+ *       u = sqrt(pi) e^{-i pi/4} [ (f_a e^{i Delta} + i f_b e^{-i Delta}) zeta^{1/4} Ai(-zeta)
+ *                               - i (f_a e^{i Delta} - i f_b e^{-i Delta}) zeta^{-1/4} Ai'(-zeta) ]
+ *     (u -> f_a + f_b far from the fold).  Nodes with Delta <= 0 keep the
+ *     sum; the dark side of a fold gets no field.
+ *   RTW_DIFFRACTION: forward Fraunhofer diffraction of the particle's shadow
+ *     (Babinet), added to every node: the shadow on z = 0 is the ellipse
+ *     rho^T S2^-1 rho <= 1 (S2 the x-y block of R diag(a^2, b^2, c^2) R^T),
+ *     F_d = (i k / 2 pi) pi sqrt(det S2) 2 J1(k s) / (k s), s = sqrt(n_t^T S2 n_t)
+ *     with n_t = (sin th cos ph, sin th sin ph), along (cos ph, -sin ph) on
+ *     (e_theta, e_phi) for x polarisation and (sin ph, cos ph) for y.  Plane
+ *     wave and far field only (else RTW_ERR_UNSUPPORTED).
+ * The incoherent sums of rtw_batch (out_incoh) stay those of the ray sum. */
+#define RTW_CAUSTIC 1
+#define RTW_DIFFRACTION 2
+
 typedef struct {
   int p_min, p_max; /* orders emitted, 0 <= p_min <= p_max <= RTW_MAX_ORDER */
   int grid_n;       /* incident rays per side, >= 2 */
   int precision;    /* RTW_FP64 or RTW_MIXED */
+  int corrections;  /* 0, or RTW_CAUSTIC | RTW_DIFFRACTION (far-field calls only) */
 } rtw_trace_opts;
 
 /* Observation grid: sorted node angles, DEVICE pointers (caller-owned),

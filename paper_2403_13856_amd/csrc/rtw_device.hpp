@@ -159,6 +159,92 @@ __device__ __forceinline__ double reduce_2pi(double x) {
   return (x - n * TWO_PI_HI) - n * TWO_PI_LO;
 }
 
+// Ai(-z) and Ai'(-z) for z >= 0 (FP64).  Up to z = 10 the Airy equation
+// y'' = x y is marched from x = 0 (Ai(0) = 3^(-2/3) / Gamma(2/3), Ai'(0) =
+// -3^(-1/3) / Gamma(1/3), Abramowitz & Stegun 10.4.4-5) to x = -z in equal
+// steps of at most 1/2, each by its Taylor series about the current point,
+// whose coefficients follow from (j + 2)(j + 1) a_{j+2} = x0 a_j + a_{j-1};
+// from z = 10 on, the asymptotic expansions A&S 10.4.60 and 10.4.62 in
+// xi = (2/3) z^{3/2} (their twelfth term is below 1e-13 there).
+__device__ inline void airy_neg(double z, double& ai, double& aip) {
+  if (z < 10.0) {
+    double y = 0.35502805388781723926, yp = -0.25881940379280679840;
+    const int n = (int)ceil(2.0 * z);
+    const double h = n > 0 ? -z / n : 0.0;
+    double x0 = 0.0;
+    for (int s = 0; s < n; ++s) {
+      double am1 = 0.0, a0 = y, a1 = yp;  // a_{j-1}, a_j, a_{j+1} for j = 0
+      double py = a0, pyp = a1, hp = 1.0;   // sums of a_j h^j and (j + 1) a_{j+1} h^j
+      for (int j = 0; j < 48; ++j) {
+        const double a2 = (x0 * a0 + am1) / ((double)(j + 2) * (double)(j + 1));
+        hp *= h;
+        py += a1 * hp;
+        pyp += (double)(j + 2) * a2 * hp;
+        am1 = a0; a0 = a1; a1 = a2;
+      }
+      y = py;
+      yp = pyp;
+      x0 += h;
+    }
+    ai = y;
+    aip = yp;
+    return;
+  }
+  const double xi = (2.0 / 3.0) * z * sqrt(z);
+  const double ixi = 1.0 / xi;
+  // c_k of Ai (d_k of Ai' = -(6k + 1) / (6k - 1) c_k), summed as the alternating
+  // even and odd series of both
+  double c = 1.0, pw = 1.0, se = 0.0, so = 0.0, de = 0.0, dd = 0.0;
+  for (int k = 0; k < 12; ++k) {
+    if (k > 0) c *= (6.0 * k - 5.0) * (6.0 * k - 3.0) * (6.0 * k - 1.0) / ((2.0 * k - 1.0) * 216.0 * k);
+    const double d = k > 0 ? -c * (6.0 * k + 1.0) / (6.0 * k - 1.0) : 1.0;
+    const double sg = (k & 2) ? -1.0 : 1.0;
+    if (k & 1) { so += sg * c * pw; dd += sg * d * pw; }
+    else { se += sg * c * pw; de += sg * d * pw; }
+    pw *= ixi;
+  }
+  double sn, cs;
+  sincos(xi + 0.78539816339744830962, &sn, &cs);
+  const double q = sqrt(sqrt(z)), isp = 0.56418958354775628695;  // z^{1/4}, 1/sqrt(pi)
+  ai = isp / q * (sn * se - cs * so);
+  aip = -isp * q * (cs * de + sn * dd);
+}
+
+// J1(x), FP64: below 25, downward recurrence J_{n-1} = (2n / x) J_n - J_{n+1}
+// from a start far above x (Miller), normalised by J_0 + 2 sum J_{2m} = 1;
+// from 25 on, Hankel's asymptotic expansion (A&S 9.2.5 with 9.2.9-10), 14 terms.
+__device__ inline double bessel_j1(double x) {
+  const double ax = fabs(x);
+  if (ax < 1e-8) return 0.5 * x;
+  double r;
+  if (ax < 25.0) {
+    const int top = 2 * ((int)(ax + 15.0 + sqrt(40.0 * ax)) / 2);
+    double jn1 = 0.0, jn = 1e-30, keep1 = 0.0, even = 0.0;
+    for (int nn = top; nn > 0; --nn) {
+      const double jm = 2.0 * nn / ax * jn - jn1;  // J_{nn-1}
+      jn1 = jn;
+      jn = jm;
+      if (nn == 2) keep1 = jn;
+      if (((nn - 1) & 1) == 0 && nn > 1) even += jn;
+      if (fabs(jn) > 1e200) { jn *= 1e-200; jn1 *= 1e-200; keep1 *= 1e-200; even *= 1e-200; }
+    }
+    r = keep1 / (jn + 2.0 * even);
+  } else {
+    double a = 1.0, pw = 1.0, P = 0.0, Q = 0.0;
+    const double ix = 1.0 / ax;
+    for (int k = 0; k < 14; ++k) {
+      if (k > 0) a *= (4.0 - (2.0 * k - 1.0) * (2.0 * k - 1.0)) / (8.0 * k);
+      const double sg = (k & 2) ? -1.0 : 1.0;
+      if (k & 1) Q += sg * a * pw; else P += sg * a * pw;
+      pw *= ix;
+    }
+    double sn, cs;
+    sincos(ax - 2.35619449019234492885, &sn, &cs);
+    r = sqrt(0.63661977236758134308 * ix) * (P * cs - Q * sn);
+  }
+  return x < 0.0 ? -r : r;
+}
+
 // Number of negative eigenvalues of the symmetric matrix [[a, b], [b, c]].
 __device__ __forceinline__ int neg_eigs(double a, double b, double c) {
   double det = a * c - b * b;

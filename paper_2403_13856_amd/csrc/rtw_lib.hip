@@ -111,6 +111,10 @@ int check_particle(const rtw_particle* p, const rtw_incident* inc, const rtw_tra
   if (o->grid_n < 2 || o->grid_n > 16384) return fail(RTW_ERR_INVALID_ARG, "grid_n must be in [2, 16384]");
   if (o->precision != RTW_FP64 && o->precision != RTW_MIXED)
     return fail(RTW_ERR_INVALID_ARG, "precision must be RTW_FP64 or RTW_MIXED");
+  if (o->corrections & ~(RTW_CAUSTIC | RTW_DIFFRACTION))
+    return fail(RTW_ERR_INVALID_ARG, "corrections must be a combination of RTW_CAUSTIC and RTW_DIFFRACTION");
+  if ((o->corrections & RTW_DIFFRACTION) && (inc->source_distance != 0.0 || inc->observation_radius != 0.0))
+    return fail(RTW_ERR_UNSUPPORTED, "RTW_DIFFRACTION is the Fraunhofer term of a plane wave in the far field");
   return RTW_OK;
 }
 
@@ -382,6 +386,38 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
   }
 }
 
+// Forward Fraunhofer diffraction of each particle's shadow (Babinet), added to
+// its far field: the shadow on z = 0 is the ellipse with matrix S2, the x-y
+// block of R diag(a^2, b^2, c^2) R^T, and its amplitude in direction n is
+// (i k / 2 pi) pi sqrt(det S2) 2 J1(k s) / (k s), s = sqrt(n_t^T S2 n_t), carried
+// by the incident polarisation in the frame that turns with phi.
+template <typename G>
+__global__ void __launch_bounds__(256) k_diffraction(const BatchDev B, const NodeGrid ng, int n_nodes, int n_pol,
+                                                     G* out) {
+  const long gn = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gn >= (long)B.n * n_nodes) return;
+  const int pl = (int)(gn / n_nodes);
+  const int node = (int)(gn - (long)pl * n_nodes);
+  const int it = node / ng.n_phi, ip = node - it * ng.n_phi;
+  const ParticleConst& P = B.P[pl];
+  double s00 = 0.0, s01 = 0.0, s11 = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    const double a2 = 1.0 / P.A[q];
+    s00 += P.R[q] * P.R[q] * a2;
+    s01 += P.R[q] * P.R[3 + q] * a2;
+    s11 += P.R[3 + q] * P.R[3 + q] * a2;
+  }
+  const double cp = ng.cph[ip], sp = ng.sph[ip];
+  const double nx = ng.sth[it] * cp, ny = ng.sth[it] * sp;
+  const double u = P.k * sqrt(s00 * nx * nx + 2.0 * s01 * nx * ny + s11 * ny * ny);
+  const double shape = u < 1e-8 ? 1.0 : 2.0 * bessel_j1(u) / u;
+  const double fi = 0.5 * P.k * sqrt(s00 * s11 - s01 * s01) * shape;  // F_d = i fi
+  const double pol[2][2] = {{cp, -sp}, {sp, cp}};
+  G* po = out + (long)B.out_index[pl] * ((long)n_pol * 2 * n_nodes * 2);
+  for (int p = 0; p < n_pol; ++p)
+    for (int a = 0; a < 2; ++a) po[((long)(p * 2 + a) * n_nodes + node) * 2 + 1] += (G)(fi * pol[p][a]);
+}
+
 // Reset of the per-chunk state: node hit counts and per-chunk counters.
 __global__ void k_chunk_reset(int* count, long n_nodes_chunk, unsigned* counter) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -497,8 +533,8 @@ int check_keys(const rtw_trace_opts* o) {
 // Workspace layout (256-byte aligned sections).  Record arrays are sized for
 // the largest chunk; metadata for every particle of the call.
 struct Layout {
-  size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, head, cursor,
-      bsum, redo, rows, link, contrib, desc, total;
+  size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, ph64, head, cursor,
+      bsum, redo, rows, link, contrib, desc, hphi, hnf, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -510,6 +546,7 @@ struct Shape {
   long max_chunk_rays;  // incident rays of the largest chunk
   int max_chunk_parts;  // particles of the largest chunk
   long rows_cap;        // (triangle, row) items of the row list
+  int corr;             // RTW_CAUSTIC | RTW_DIFFRACTION
 };
 
 Layout layout(const Shape& S, long cap_total) {
@@ -534,6 +571,8 @@ Layout layout(const Shape& S, long cap_total) {
   L.rr = take(rr * nrec);
   L.dir = take((S.precision == RTW_FP64 ? sizeof(Dir4<double>) : sizeof(Dir4<float>)) * nrec);
   L.ang = take(sizeof(float2) * nrec);
+  const bool caustic = S.corr & RTW_CAUSTIC;
+  L.ph64 = take(caustic ? sizeof(double) * nrec : 0);
   L.head = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.cursor = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.bsum = take(4 * ((size_t)S.max_chunk_parts * n_nodes / SCAN_BLOCK + 1));
@@ -541,10 +580,12 @@ Layout layout(const Shape& S, long cap_total) {
   L.rows = take(sizeof(int2) * (size_t)S.rows_cap);
   L.fixed = off;
   const size_t ds = S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>);
-  L.bytes_per_hit = sizeof(int) + gs * 4 * S.n_pol + ds;
+  L.bytes_per_hit = sizeof(int) + gs * 4 * S.n_pol + ds + (caustic ? sizeof(double) + sizeof(int) : 0);
   L.link = take(sizeof(int) * (size_t)cap_total);
   L.contrib = take(gs * 4 * S.n_pol * (size_t)cap_total);
   L.desc = take(ds * (size_t)cap_total);
+  L.hphi = take(caustic ? sizeof(double) * (size_t)cap_total : 0);
+  L.hnf = take(caustic ? sizeof(int) * (size_t)cap_total : 0);
   L.total = off;
   return L;
 }
@@ -629,6 +670,7 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   pl.S.max_chunk_rays = 0;
   pl.S.max_chunk_parts = 0;
   pl.S.rows_cap = ROWS_CAP;
+  pl.S.corr = opts->corrections;
   // node indices of a chunk (chunk particle, theta, phi) are 32-bit: a chunk
   // holds at most (2^31 - 1) / n_nodes particles
   const long n_nodes = (long)grid->n_theta * grid->n_phi;
@@ -719,6 +761,8 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   rec.n_pol = S.n_pol;
   rec.n_fp64 = counter + C_REDO;
   rec.redo_list = (int*)(ws + L.redo);
+  const bool caustic = S.corr & RTW_CAUSTIC;
+  rec.ph64 = caustic ? (double*)(ws + L.ph64) : nullptr;
   HitPool<G> pool;
   pool.count = (int*)(ws + L.head);
   pool.cursor = (int*)(ws + L.cursor);
@@ -730,6 +774,8 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   pool.rows = (int2*)(ws + L.rows);
   pool.n_rows = counter + C_ROWS;
   pool.rows_cap = (int)S.rows_cap;
+  pool.phi = caustic ? (double*)(ws + L.hphi) : nullptr;
+  pool.nf = caustic ? (int*)(ws + L.hnf) : nullptr;
 
   ParticleConst* mP = (ParticleConst*)(ws + L.mP);
   long* moff = (long*)(ws + L.moff);
@@ -796,6 +842,11 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
     hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
                        S.n_pol, (G*)out, ncontrib, (G*)incoh); }
+    if (S.corr & RTW_DIFFRACTION) {
+      ProfScope ps("k_diffraction", st);
+      hipLaunchKernelGGL(k_diffraction<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng, n_nodes,
+                         S.n_pol, (G*)out);
+    }
     hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter);
   }
   hipError_t e = hipGetLastError();

@@ -131,6 +131,7 @@ struct Records {
   int n_pol;
   unsigned* n_fp64;  // rays listed for the FP64 re-trace (mixed path)
   int* redo_list;    // their chunk ray indices
+  double* ph64;      // caustic correction only (else NULL): unreduced FP64 phase at the stored direction
 };
 
 // The particles of one launch (a chunk of a batch, or one particle).  Offsets
@@ -189,6 +190,8 @@ struct HitPool {
   int2* rows;         // [rows_cap] (triangle key, theta row) of triangles rasterised row by row
   unsigned* n_rows;   // rows listed
   int rows_cap;
+  double* phi;        // caustic correction only (else NULL): [cap] phase carried to the node
+  int* nf;            // [cap] focal-line count of the contribution's triangle
 };
 
 constexpr int CAND_INLINE = 4096;  // default: triangles with more box candidates go to the row list
@@ -241,6 +244,9 @@ struct RecordSink {
       const double dphi = near_carry(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
                                      (double)e.obs.y, (double)e.obs.z, (double)dv.x, (double)dv.y, (double)dv.z);
       sincos(dphi, &cim, &cre);
+      if (rec.ph64) rec.ph64[at] = e.phase + dphi;
+    } else if (rec.ph64) {
+      rec.ph64[at] = e.phase;
     }
     v3<double> et, ep;
     dir_basis((double)dv.x, (double)dv.y, (double)dv.z, et, ep);
@@ -778,6 +784,7 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
     for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
   const v3<double> n = node_dir(ng, it, ip);
   G lam[3] = {d.lam[0], d.lam[1], d.lam[2]};
+  double lam64[3] = {(double)d.lam[0], (double)d.lam[1], (double)d.lam[2]};
   if (sizeof(G) == 4) {
     // weights of the central projection from the FP64 vertex directions
     // (stored direction plus its rounding residual): (d_a x d_b).n over the
@@ -789,9 +796,11 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
     const double sw = w0 + w1 + w2;
     if (sw != 0.0) {
       const double is = 1.0 / sw;
-      lam[0] = (G)(w0 * is); lam[1] = (G)(w1 * is); lam[2] = (G)(w2 * is);
+      lam64[0] = w0 * is; lam64[1] = w1 * is; lam64[2] = w2 * is;
+      lam[0] = (G)lam64[0]; lam[1] = (G)lam64[1]; lam[2] = (G)lam64[2];
     }
   }
+  double phi_t = 0.0;  // the triangle's phase carried to the node (caustic correction)
   for (int k = 0; k < 3; ++k) {
     const RayRec<G>& vr = rec.rr[rb + vid[k]];
     const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
@@ -799,6 +808,7 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
     // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
     const double psi = near_carry(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dk.x,
                                   (double)dk.y, (double)dk.z, n.x, n.y, n.z);
+    if (pool.phi) phi_t += lam64[k] * (rec.ph64[rb + vid[k]] + psi);
     G s_, c_;
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
     else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
@@ -824,6 +834,10 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
     out[p] = v;
   }
   pool.key[at] = d.key;
+  if (pool.phi) {
+    pool.phi[at] = phi_t;
+    pool.nf[at] = (rec.flags[rb + vid[0]] >> 1) & 127;
+  }
 }
 
 // One thread per pool slot: contributions of every hit the rasterisers found,
@@ -1328,6 +1342,49 @@ __global__ void __launch_bounds__(256) k_scan_add(int* out, long n, const int* b
     if (base + j < n) out[base + j] += add;
 }
 
+// Sum of the fold pair at pool positions a, b (the same order slot): the
+// uniform Airy form of the two branches (focal-line counts n and n + 1) with
+// Delta = (phi_b - phi_a) / 2 + pi / 4 from their phases carried to the node,
+// (2/3) zeta^{3/2} = Delta; the plain sum where the counts do not differ by
+// one or Delta <= 0.  FP64 throughout, rounded to G once.
+template <typename G>
+__device__ inline void add_fold_pair(const HitPool<G>& pool, long a, long b, int n_pol, int w, G* acc, G* inc) {
+  if (pool.nf[a] > pool.nf[b]) { const long t = a; a = b; b = t; }
+  const double delta = 0.5 * (pool.phi[b] - pool.phi[a]) + 0.78539816339744830962;
+  const bool fold = pool.nf[b] - pool.nf[a] == 1 && delta > 0.0;
+  double zeta = 0.0, ai = 0.0, aip = 0.0, z4 = 1.0, ed_r = 1.0, ed_i = 0.0;
+  if (fold) {
+    zeta = pow(1.5 * delta, 2.0 / 3.0);
+    airy_neg(zeta, ai, aip);
+    z4 = sqrt(sqrt(zeta));
+    sincos(delta, &ed_i, &ed_r);
+  }
+  // sqrt(pi) e^{-i pi/4}
+  const double pr = 1.2533141373155002512, pi_ = -1.2533141373155002512;
+  for (int p = 0; p < n_pol; ++p) {
+    const G* fa = pool.contrib + a * w + 4 * p;
+    const G* fb = pool.contrib + b * w + 4 * p;
+    for (int c = 0; c < 2; ++c) {
+      const double ar = fa[2 * c], aI = fa[2 * c + 1], br = fb[2 * c], bI = fb[2 * c + 1];
+      inc[p] += (G)(ar * ar + aI * aI + br * br + bI * bI);
+      double ur = ar + br, ui = aI + bI;
+      if (fold) {
+        // s = f_a e^{i D} + i f_b e^{-i D},  t = f_a e^{i D} - i f_b e^{-i D}
+        const double xr = ar * ed_r - aI * ed_i, xi = ar * ed_i + aI * ed_r;     // f_a e^{iD}
+        const double yr = br * ed_r + bI * ed_i, yi = bI * ed_r - br * ed_i;     // f_b e^{-iD}
+        const double sr = xr - yi, si = xi + yr;                                // + i y
+        const double tr = xr + yi, ti = xi - yr;                                // - i y
+        // v = s z4 Ai - i t Ai' / z4
+        const double vr = sr * z4 * ai + ti * aip / z4, vi = si * z4 * ai - tr * aip / z4;
+        ur = pr * vr - pi_ * vi;
+        ui = pr * vi + pi_ * vr;
+      }
+      acc[4 * p + 2 * c] += (G)ur;
+      acc[4 * p + 2 * c + 1] += (G)ui;
+    }
+  }
+}
+
 // One thread per node of the chunk (particle-major): order the node's
 // contributions (a contiguous range after k_store_hits) by triangle key, sum
 // them in that order and write (F_theta, F_phi) for every polarisation into
@@ -1356,6 +1413,32 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
       inc[p] += c.x * c.x + c.y * c.y + c.z * c.z + c.w * c.w;
     }
   };
+  // Caustic correction: contributions of one order slot arrive together (the
+  // key orders them by slot first); a slot holding exactly two whose focal-line
+  // counts differ by one is a fold pair and is added in the uniform Airy form.
+  const bool caustic = pool.phi != nullptr;
+  long qoff = 0, nq = 1;
+  if (caustic) {
+    const int N = B.P[pl].N;
+    qoff = (long)B.n_ord * (B.quad_off[pl] - B.quad_base);
+    nq = (long)(N - 1) * (N - 1);
+  }
+  long pend[2];
+  int npend = 0, cur_slot = -1;
+  auto flush = [&]() {
+    if (npend == 2) add_fold_pair(pool, pend[0], pend[1], n_pol, w, acc, inc);
+    else if (npend == 1) add(pend[0]);
+    npend = 0;
+  };
+  auto take = [&](long at, int key) {
+    if (!caustic) { add(at); return; }
+    const int slot = (int)(((long)(key >> 1) - qoff) / nq);
+    if (slot != cur_slot) { flush(); cur_slot = slot; }
+    if (npend < 0) { add(at); return; }  // a slot with more than two: plain sum
+    if (npend < 2) { pend[npend++] = at; return; }
+    add(pend[0]); add(pend[1]); add(at);
+    npend = -1;
+  };
   if (cnt <= NODE_SORT_MAX) {
     for (int h = 0; h < cnt; ++h) {  // insertion into the sorted prefix
       const int kk = pool.key[s0 + h];
@@ -1363,7 +1446,7 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
       while (j > 0 && keys[j - 1] > kk) { keys[j] = keys[j - 1]; idxs[j] = idxs[j - 1]; --j; }
       keys[j] = kk; idxs[j] = h;
     }
-    for (int i = 0; i < cnt; ++i) add(s0 + idxs[i]);
+    for (int i = 0; i < cnt; ++i) take(s0 + idxs[i], keys[i]);
   } else {
     // more hits than the register window: repeated minimum search, same order
     long last = -1;
@@ -1375,9 +1458,10 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
         if (kk > last && kk < best) { best = kk; bi = h; }
       }
       last = best;
-      add(s0 + bi);
+      take(s0 + bi, (int)best);
     }
   }
+  if (caustic) flush();
   G* po = out + ob * ((long)n_pol * 2 * n_nodes * 2);
   for (int p = 0; p < n_pol; ++p)
     for (int a = 0; a < 2; ++a) {

@@ -32,7 +32,11 @@ class Incident(ctypes.Structure):
 
 class TraceOpts(ctypes.Structure):
     _fields_ = [("p_min", ctypes.c_int), ("p_max", ctypes.c_int), ("grid_n", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("corrections", ctypes.c_int)]
+
+
+CAUSTIC = 1      # uniform Airy form at fold caustics
+DIFFRACTION = 2  # forward Fraunhofer diffraction of the shadow
 
 
 class Grid(ctypes.Structure):
@@ -151,9 +155,10 @@ def make_incident(wavelength: float = 0.6328, n_pol: int = 1, source_distance: f
     return inc
 
 
-def make_opts(p_min=0, p_max=2, grid_n=64, precision=FP64):
+def make_opts(p_min=0, p_max=2, grid_n=64, precision=FP64, corrections=0):
     o = TraceOpts()
     o.p_min, o.p_max, o.grid_n, o.precision = int(p_min), int(p_max), int(grid_n), int(precision)
+    o.corrections = int(corrections)
     return o
 
 

@@ -42,14 +42,16 @@ def oracle_farfield(oracle, op, os_, th, ph, mixed):
     return oracle.farfield(op, os_, th, ph, edge_band_deg=EDGE_BAND_MIXED if mixed else 0.1)
 
 
-def compare_mixed(ref, F, int_tol=1e-4, ph_tol=1e-3, say=_say, tag="", denominator="incoherent"):
+def compare_mixed(ref, F, int_tol=1e-4, ph_tol=1e-3, say=_say, tag="", denominator="incoherent", extra_incoh=None):
     """Assert the mixed-path bars; returns (intensity errors, phase errors) of the compared nodes.
     denominator="uncancelled" divides by max(uncancelled, incoherent) instead: for
     grids so coarse that a triangle's interpolated terms cancel (the ratio of the
-    two reaches ~100 at 24^2 rays), where FP32 rounding scales with the terms."""
+    two reaches ~100 at 24^2 rays), where FP32 rounding scales with the terms.
+    extra_incoh: a further term's |F|^2 per node (the diffraction term), counted
+    as one more contribution of the incoherent sum."""
     assert ref["edge_band_deg"] <= EDGE_BAND_MIXED, "oracle run with a wide sheet-edge band"
     fl = ref["flags"]
-    inc = ref["incoh"]
+    inc = ref["incoh"] if extra_incoh is None else ref["incoh"] + extra_incoh
     sel = ((fl & 6) == 0) & (((fl & 8) == 0)) & (inc > 0)
     I_ref = (np.abs(ref["field"]) ** 2).sum(axis=(0, 1))
     I_got = (np.abs(F) ** 2).sum(axis=(0, 1))
@@ -118,11 +120,11 @@ def cond_allowance(rec, N, th_deg, ph_deg, tol, robs=0.0, k=2 * np.pi / 0.6328):
     return allow.reshape(n_t, n_p), len(bad)
 
 
-def compare_fp64(ref, F, nc, tol=1e-10, allow=None, say=_say, tag=""):
+def compare_fp64(ref, F, nc, tol=1e-10, allow=None, say=_say, tag="", extra_incoh=None):
     """Assert the FP64 bars; allow (per node) replaces tol where a contributing
     ray is ill-conditioned (cond_allowance).  Returns the fraction compared."""
     fl = ref["flags"]
-    inc = np.sqrt(ref["incoh"])
+    inc = np.sqrt(ref["incoh"] if extra_incoh is None else ref["incoh"] + extra_incoh)
     comp = (fl & 6) == 0
     bound = np.full(inc.shape, tol) if allow is None else np.maximum(allow, tol)
     err = np.abs(F - ref["field"]).max(axis=(0, 1)) / np.maximum(inc, 1e-300)

@@ -65,7 +65,18 @@ def test_argument_validation_without_device():
         (good[0], rtw.make_incident(0.6328, 2, 0.0, -500.0), good[2], rtw.RTW_ERR_INVALID_ARG),
         (good[0], rtw.make_incident(0.6328, 2, 200.0, float("inf")), good[2], rtw.RTW_ERR_INVALID_ARG),
         (good[0], rtw.make_incident(0.6328, 2, 0.0, float("nan")), good[2], rtw.RTW_ERR_INVALID_ARG),
+        # corrections: known bits only; the Fraunhofer term needs a plane wave and the far field
+        (good[0], good[1], rtw.make_opts(0, 3, 64, rtw.FP64, 4), rtw.RTW_ERR_INVALID_ARG),
+        (good[0], rtw.make_incident(0.6328, 2, 60.0), rtw.make_opts(0, 3, 64, rtw.FP64, rtw.DIFFRACTION),
+         rtw.RTW_ERR_UNSUPPORTED),
+        (good[0], rtw.make_incident(0.6328, 2, 0.0, 60.0), rtw.make_opts(0, 3, 64, rtw.FP64, rtw.DIFFRACTION),
+         rtw.RTW_ERR_UNSUPPORTED),
     ]
+    for corr in (rtw.CAUSTIC, rtw.DIFFRACTION, rtw.CAUSTIC | rtw.DIFFRACTION):
+        rc, n_c = _ws(good[0], good[1], rtw.make_opts(0, 3, 64, rtw.FP64, corr))
+        assert rc == rtw.RTW_OK and n_c >= n  # the caustic form keeps phases per record and per hit
+    rc, n_pc = _ws(good[0], rtw.make_incident(0.6328, 2, 60.0), rtw.make_opts(0, 3, 64, rtw.FP64, rtw.CAUSTIC))
+    assert rc == rtw.RTW_OK
     rc, n_obs = _ws(good[0], rtw.make_incident(0.6328, 2, 0.0, 50.5), good[2])
     assert rc == rtw.RTW_OK and n_obs == n
     rc, n_src = _ws(good[0], rtw.make_incident(0.6328, 2, 50.5), good[2])
