@@ -58,11 +58,16 @@ extern "C" {
 
 #define RTW_MAX_ORDER 15
 
-/* One ellipsoid r^T diag(a^-2, b^-2, c^-2) r = 1 in its body frame. */
+/* One ellipsoid r^T diag(a^-2, b^-2, c^-2) r = 1 in its body frame.
+ * Absorbing particles (m_im > 0; not in the paper): the weak-absorption form
+ * of geometric optics -- Snell, Eq. 8 and Eq. 3 use m, and every internal
+ * segment of length L scales the carried field by exp(-k m_im L) (the per-ray
+ * amplitude record excludes it, the field record includes it). */
 typedef struct {
   double semi_axes[3]; /* a, b, c > 0 (um) */
   double euler_deg[3]; /* Z-Y-Z Euler angles (deg), body -> lab */
-  double m;            /* real relative refractive index, m > 0, m != 1 */
+  double m;            /* real part of the relative refractive index, m > 0, m != 1 */
+  double m_im;         /* imaginary part, >= 0 (0: no absorption) */
 } rtw_particle;
 
 /* Incident wave (the paper's problem statement: wavelength and polarisation

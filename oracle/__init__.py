@@ -22,7 +22,8 @@ MAX_ORDER = 15
 
 
 class Particle(ctypes.Structure):
-    _fields_ = [("semi_axes", ctypes.c_double * 3), ("euler_deg", ctypes.c_double * 3), ("m", ctypes.c_double)]
+    _fields_ = [("semi_axes", ctypes.c_double * 3), ("euler_deg", ctypes.c_double * 3), ("m", ctypes.c_double),
+                ("m_im", ctypes.c_double)]
 
 
 class Setup(ctypes.Structure):
@@ -89,8 +90,10 @@ def _ip(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if a is not None else None
 
 
-def particle(semi_axes, euler_deg=(0.0, 0.0, 0.0), m=1.333):
+def particle(semi_axes, euler_deg=(0.0, 0.0, 0.0), m=1.333, m_im=0.0):
+    """m: real part of the index; m_im >= 0 its imaginary part (weak absorption, reading R14)."""
     p = Particle()
+    p.m_im = float(m_im)
     p.semi_axes[:] = [float(v) for v in semi_axes]
     p.euler_deg[:] = [float(v) for v in euler_deg]
     p.m = float(m)

@@ -99,6 +99,13 @@
  *      forward amplitude the optical theorem pairs with the shadow), carried
  *      by the incident polarisation in the frame (e_theta, e_phi) that turns
  *      with phi: x gives (cos phi, -sin phi), y gives (sin phi, cos phi).
+ *  R14 Absorbing particles (not in the paper): for m = m_r + i m_im with
+ *      m_im << m_r, the weak-absorption reading of geometric optics: Snell,
+ *      Eq. 8 and Eq. 3 use m_r, and every internal segment of length L
+ *      scales the carried field by exp(-k m_im L) (a homogeneous wave of index
+ *      m_r + i m_im; the inhomogeneous-wave corrections of strong absorption
+ *      are left out).  Parity unpinned against the paper; pinned to the
+ *      chord lengths of the sphere.
  */
 #include "rtw_oracle.h"
 
@@ -244,6 +251,7 @@ typedef struct {
   double R[3][3];   /* body -> lab */
   double k;         /* 2 pi / lambda */
   double m;
+  double m_im;      /* imaginary part of the index (R14) */
   double zs;        /* point-source distance (0: plane wave) */
   double robs;      /* observation radius (0: far field) */
   int n_pol, p_min, p_max;
@@ -556,6 +564,12 @@ static void trace_one(const ctx_t* c, double x, double y, rtwo_ray* out) {
     s.nf += m2neg(G);              /* focal lines crossed on this segment */
     s.Q = m2mul(s.Q, m2inv(G));    /* Q(L) = Q (I + L Q)^{-1} */
     s.opl += s.n_cur * c->k * L;   /* Eq. 9 path term */
+    if (s.n_cur != 1.0 && c->m_im > 0.0) {
+      /* R14: attenuation along an internal segment */
+      double att = exp(-c->k * c->m_im * L);
+      for (int a = 0; a < 2; a++)
+        for (int p = 0; p < 2; p++) s.J[a][p] *= att;
+    }
     for (int i = 0; i < 3; i++) s.r[i] += L * s.d[i];
   }
 }
@@ -565,6 +579,7 @@ static int setup_ctx(const rtwo_particle* part, const rtwo_setup* st, ctx_t* c) 
   for (int i = 0; i < 3; i++)
     if (!(part->semi_axes[i] > 0.0)) return -1;
   if (!(part->m > 0.0) || part->m == 1.0) return -1;
+  if (!(part->m_im >= 0.0) || !isfinite(part->m_im)) return -1;
   if (!(st->wavelength > 0.0)) return -1;
   if (st->n_pol < 1 || st->n_pol > 2) return -1;
   if (st->p_min < 0 || st->p_max < st->p_min || st->p_max > RTWO_MAX_ORDER) return -1;
@@ -582,6 +597,7 @@ static int setup_ctx(const rtwo_particle* part, const rtwo_setup* st, ctx_t* c) 
   euler_zyz(part->euler_deg, c->R);
   c->k = 2.0 * PI / st->wavelength;
   c->m = part->m;
+  c->m_im = part->m_im;
   c->n_pol = st->n_pol;
   c->p_min = st->p_min;
   c->p_max = st->p_max;

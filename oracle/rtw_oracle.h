@@ -31,7 +31,8 @@ extern "C" {
 typedef struct {
   double semi_axes[3]; /* a, b, c > 0 along body x, y, z (um) */
   double euler_deg[3]; /* Z-Y-Z Euler angles (deg), body -> lab */
-  double m;            /* real relative refractive index, m > 0, m != 1 */
+  double m;            /* real part of the relative refractive index, m > 0, m != 1 */
+  double m_im;         /* its imaginary part, >= 0: weak absorption (reading R14) */
 } rtwo_particle;
 
 typedef struct {

@@ -119,7 +119,8 @@ struct ParticleConst {
   double A[3];   // 1/a^2, 1/b^2, 1/c^2
   double R[9];   // body -> lab rotation, row-major
   double k;      // 2 pi / lambda
-  double m;      // relative index
+  double m;      // relative index (real part)
+  double m_im;   // its imaginary part: attenuation exp(-k m_im L) per internal segment
   double L, h;   // grid half-width and ray spacing (um)
   int N;         // rays per side
   int p_min, p_max, n_pol;
@@ -575,6 +576,12 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
     q11 = (G)n11; q12 = (G)n12; q22 = (G)n22;
     opl += n_cur * P.k * L;
+    if (n_cur != 1.0 && P.m_im > 0.0) {
+      // weak absorption along the internal segment
+      const G att = (G)exp(-P.k * P.m_im * L);
+      for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 2; ++a) { J[a][k].re *= att; J[a][k].im *= att; }
+    }
     r = axpy(L, d, r);
   }
 }

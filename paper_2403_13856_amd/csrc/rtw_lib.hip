@@ -96,6 +96,8 @@ int check_particle(const rtw_particle* p, const rtw_incident* inc, const rtw_tra
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(p->euler_deg[i])) return fail(RTW_ERR_INVALID_ARG, "Euler angle %d is not finite", i);
   if (!(p->m > 0.0) || !std::isfinite(p->m)) return fail(RTW_ERR_INVALID_ARG, "refractive index must be positive");
+  if (!(p->m_im >= 0.0) || !std::isfinite(p->m_im))
+    return fail(RTW_ERR_INVALID_ARG, "imaginary part of the index must be finite and >= 0");
   if (p->m == 1.0) return fail(RTW_ERR_UNSUPPORTED, "m = 1: no interface");
   if (!(inc->wavelength > 0.0) || !std::isfinite(inc->wavelength))
     return fail(RTW_ERR_INVALID_ARG, "wavelength must be positive");
@@ -172,6 +174,7 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   P.h = 2.0 * P.L / P.N;
   P.k = 2.0 * PI_H / inc->wavelength;
   P.m = p->m;
+  P.m_im = p->m_im;
   P.p_min = o->p_min;
   P.p_max = o->p_max;
   P.n_pol = inc->n_pol;

@@ -829,6 +829,7 @@ int rtw_surrogate_features(int n_part, const rtw_particle* parts, const rtw_inci
   for (int p = 0; p < n_part; ++p) {
     const double* s = parts[p].semi_axes;
     if (!(s[0] > 0 && s[1] > 0 && s[2] > 0)) return mfail(RTW_ERR_INVALID_ARG, "particle %d: bad semi-axes", p);
+    if (parts[p].m_im != 0.0) return mfail(RTW_ERR_UNSUPPORTED, "particle %d: the surrogate models real indices", p);
     const double rbar = std::cbrt(s[0] * s[1] * s[2]);
     for (int c = 0; c < n_cell; ++c) {
       float* f = feats + ((size_t)p * n_cell + c) * IN_RAW;

@@ -22,7 +22,8 @@ MAX_ORDER = 15
 
 
 class Particle(ctypes.Structure):
-    _fields_ = [("semi_axes", ctypes.c_double * 3), ("euler_deg", ctypes.c_double * 3), ("m", ctypes.c_double)]
+    _fields_ = [("semi_axes", ctypes.c_double * 3), ("euler_deg", ctypes.c_double * 3), ("m", ctypes.c_double),
+                ("m_im", ctypes.c_double)]
 
 
 class Incident(ctypes.Structure):
@@ -135,8 +136,11 @@ def profile_read(max_kernels: int = 32):
     return out
 
 
-def make_particle(semi_axes: Sequence[float], euler_deg: Sequence[float] = (0, 0, 0), m: float = 1.333):
+def make_particle(semi_axes: Sequence[float], euler_deg: Sequence[float] = (0, 0, 0), m: float = 1.333,
+                  m_im: float = 0.0):
+    """m: real part of the index; m_im >= 0 its imaginary part (weak absorption)."""
     p = Particle()
+    p.m_im = float(m_im)
     p.semi_axes[:] = [float(v) for v in semi_axes]
     p.euler_deg[:] = [float(v) for v in euler_deg]
     p.m = float(m)
@@ -292,12 +296,14 @@ class Batch:
     device: str = "cuda"
     allocate: bool = True  # False: describe the particles only (no workspace or output)
     incoherent: bool = False  # also return per-node incoherent intensities (self.incoh)
+    m_im: Optional[Sequence[float]] = None  # imaginary parts of the indices (None: all 0)
 
     def __post_init__(self):
         import torch
         n = len(self.particles)
         self.n = n
-        self.parts = (Particle * n)(*[make_particle(a, e, m) for (a, e, m) in self.particles])
+        mi = [0.0] * n if self.m_im is None else [float(x) for x in self.m_im]
+        self.parts = (Particle * n)(*[make_particle(a, e, m, mi[i]) for i, (a, e, m) in enumerate(self.particles)])
         self.gn = (ctypes.c_int * n)(*[int(g) for g in self.grid_n])
         self.bopts = BatchOpts(int(self.rays_per_chunk), float(self.hits_per_node))
         self.theta = torch.as_tensor(self.theta_deg, dtype=torch.float64, device=self.device).contiguous()

@@ -112,3 +112,50 @@ def test_batch_with_corrections_equals_single_calls(R, prec_name):
     for i, part in enumerate(parts):
         ff = R.FarField(R.make_particle(*part), R.make_incident(LAM, 2), R.make_opts(0, 3, sides[i], P, 3), th, ph)
         assert torch.equal(torch.view_as_real(ff()), torch.view_as_real(Fb[i])), i
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_absorbing_particles(oracle, R, prec_name):
+    """Weak absorption (exp(-k m_im L) per internal segment): per-ray fields,
+    the far field of an absorbing ellipsoid against the oracle, and a batch
+    of absorbing particles bitwise equal to single calls."""
+    P = R.FP64 if prec_name == "fp64" else R.MIXED
+    axes, euler, m, m_im = (40.0, 35.0, 30.0), (15.0, 25.0, 35.0), 1.40, 3e-4
+    N = 128
+    op = oracle.particle(axes, euler, m, m_im)
+    ref = oracle.trace_grid(op, oracle.setup(LAM, 2, 0, 3, 48))
+    got = {k: v.cpu().numpy() for k, v in R.trace(R.make_particle(axes, euler, m, m_im), R.make_incident(LAM, 2),
+                                                   R.make_opts(0, 3, 48, P)).items()}
+    v = ((ref["flags"] & 1) == 1) & (got["flags"] == ref["flags"])
+    F = ref["field"][..., 0, :] + 1j * ref["field"][..., 1, :]
+    Fg = got["field"][..., 0, :] + 1j * got["field"][..., 1, :]
+    mag = np.sqrt((np.abs(F) ** 2).sum(axis=(1, 2), keepdims=True))
+    if prec_name == "mixed":  # compare at the oracle's direction (the mixed record refers to its FP32 one)
+        k = 2 * np.pi / LAM
+        Fg = Fg * np.exp(1j * k * (got["rexit"] * (got["dir"] - ref["dir"])).sum(axis=1))[:, None, None, :]
+    err = (np.abs(Fg - F) / np.maximum(mag, 1e-300)).max(axis=(1, 2))[v]
+    say(f"[absorbing {prec_name}] per-ray field worst {err.max():.2e} over {v.sum()} emissions")
+    assert err.max() < (1e-10 if prec_name == "fp64" else 2e-4)
+    w = I.ellipsoid_mixed()
+    refF = PAR.oracle_farfield(oracle, op, oracle.setup(LAM, 2, 0, 3, N), w.theta_deg, w.phi_deg, mixed=True)
+    Fg, nc = _gpu_m(R, axes, euler, m, m_im, N, P, w.theta_deg, w.phi_deg)
+    if prec_name == "fp64":
+        PAR.compare_fp64(refF, Fg, nc, 1e-10, None, say)
+    else:
+        PAR.compare_mixed(refF, Fg, say=say)
+    rng = np.random.default_rng(5)
+    parts = [I.random_ellipsoid(rng, 15.0, 50.0) for _ in range(4)]
+    th, ph = I.batch_node_grid()
+    sides = [40, 56, 48, 32]
+    parts_abs = [(a, e, mm) for (a, e, mm) in parts]
+    b = R.Batch(parts_abs, sides, R.make_incident(LAM, 2), R.make_opts(0, 3, 2, P), th, ph, m_im=[1e-4, 0.0, 5e-4, 2e-3])
+    Fb = b().clone()
+    for i, (a, e, mm) in enumerate(parts_abs):
+        ff = R.FarField(R.make_particle(a, e, mm, [1e-4, 0.0, 5e-4, 2e-3][i]), R.make_incident(LAM, 2),
+                        R.make_opts(0, 3, sides[i], P), th, ph)
+        assert torch.equal(torch.view_as_real(ff()), torch.view_as_real(Fb[i])), i
+
+
+def _gpu_m(R, axes, euler, m, m_im, N, prec, th, ph):
+    ff = R.FarField(R.make_particle(axes, euler, m, m_im), R.make_incident(LAM, 2), R.make_opts(0, 3, N, prec), th, ph)
+    return ff().cpu().numpy(), ff.ncontrib.cpu().numpy()
