@@ -362,17 +362,20 @@ def bench_large(args, rtw, inputs):
 def bench_surrogate(args, rtw, inputs):
     """Surrogate of the batched workload: train the BF16 MLP on cell-averaged
     ln-intensities that rtw_batch computes for seeded particles (cells 5 x 10
-    deg over theta 120-170 deg), calibrate sigma's threshold tau on held-out
-    particles so that accepted answers are within 1% (|d ln I| <= 0.01 for
-    99% of them), then time 1,048,576 queries (128 random cells of each of
-    8192 new particles) answered with RTW fallback, against RTW alone; the
-    same queries are also timed at the 2%, 5% and 10% bars.  A particle with
-    any rejected query is traced whole, so the gain follows the fraction of
-    particles whose queries are all accepted."""
+    deg over theta 120-170 deg; both paths compute the cells' band of nodes
+    only), calibrate sigma's threshold tau on held-out particles so that
+    accepted answers are within 1% (|d ln I| <= 0.01 for 99% of them), then
+    time 1,048,576 queries (128 random cells of each of 8192 new particles)
+    answered with RTW fallback, against RTW alone; the same queries, and a
+    sparse set (one random cell of each of 16384 particles), are also timed at
+    the 2%, 5% and 10% bars.  A particle with any rejected query is traced
+    whole, so the gain follows the fraction of particles whose queries are all
+    accepted."""
     import numpy as np
     import torch
     rtw.sload()
-    th, ph = inputs.batch_node_grid()
+    _, ph = inputs.batch_node_grid()
+    th = inputs.uniform_angles(120.0, 169.5, 0.5)  # the nodes of the cells' band
     cells = rtw.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
     n_cells = 360
     inc = rtw.make_incident(inputs.WAVELENGTH, 2)
@@ -497,27 +500,42 @@ def bench_surrogate(args, rtw, inputs):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    # context: every bar, on this query set and on a sparse one (8 random cells
-    # of each of the same particles; RTW alone costs the same trace)
-    k_s = 8
-    qc_s = rng.integers(0, n_cells, size=(n_qp, k_s)).astype(np.int32)
-    qp_s = np.repeat(np.arange(n_qp, dtype=np.int32), k_s)
-    sparse = (torch.from_numpy(np.ascontiguousarray(allf[qp_s, qc_s.ravel()])).cuda(), torch.from_numpy(qp_s).cuda(),
-              torch.from_numpy(qc_s.ravel().copy()).cuda())
-    truth_s = cI_all[sparse[1].long(), sparse[2].long()]
+    # context: every bar, on this query set and on a sparse one (one random
+    # cell of each of 16384 other particles, with its own RTW-alone time)
+    n_sp = 16384
+    bps = inputs.batch_particles(n_sp, seed=18)
+    parts_s = [(p.semi_axes, p.euler_deg, p.m) for p in bps]
+    sides_s = [p.grid_n for p in bps]
+    qc_s = rng.integers(0, n_cells, size=n_sp).astype(np.int32)
+    qp_s = np.arange(n_sp, dtype=np.int32)
+    allf_s = rtw.surrogate_features(parts_s, inc, cells).reshape(n_sp, n_cells, 9)
+    sparse = (torch.from_numpy(np.ascontiguousarray(allf_s[qp_s, qc_s])).cuda(), torch.from_numpy(qp_s).cuda(),
+              torch.from_numpy(qc_s.copy()).cuda())
+    b = rtw.Batch(parts_s, sides_s, inc, opts, th, ph, tune=tune, incoherent=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.launch(with_counts=False)
+    truth_s = rtw.cell_log_intensity(b, cells)[sparse[1].long(), sparse[2].long()]
+    torch.cuda.synchronize()
+    t_rtw_s = time.perf_counter() - t0
+    del b
+    torch.cuda.empty_cache()
+    desc_s = rtw.Batch(parts_s, sides_s, inc, opts, th, ph, allocate=False)
 
     def timed_query(t, qs=None):
-        f_, p_, c_ = qs if qs is not None else (qf, qp, qc)
+        f_, p_, c_, d_ = qs if qs is not None else (qf, qp, qc, desc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = net.query(f_, p_, c_, t, desc, cells, tune)
+        r = net.query(f_, p_, c_, t, d_, cells, tune)
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
+    net.query(sparse[0][:1024], sparse[1][:1024], sparse[2][:1024], 1e30, desc_s, cells, tune)  # scratch
     at_bars = {}
     for b, tb in [(0.01, tau)] + [(b, t[0]) for b, t in taus.items()]:
         row = dict(tau=tb)
-        for name, qs, tr, nq_ in (("dense", None, truth, n_q), ("sparse", sparse, truth_s, n_qp * k_s)):
+        for name, qs, tr, nq_, t_ref in (("dense", None, truth, n_q, t_rtw),
+                                         ("sparse", sparse + (desc_s,), truth_s, n_sp, t_rtw_s)):
             if name == "dense" and b == 0.01:
                 continue  # the headline run below
             (ans_b, _, used_b, nrec_b), t_b = timed_query(tb, qs)
@@ -525,12 +543,12 @@ def bench_surrogate(args, rtw, inputs):
             e_b = (ans_b - tr).abs().max(dim=1).values[acc_b]
             row[name] = dict(queries=nq_, accepted_fraction=round(float(acc_b.float().mean().item()), 4),
                              particles_retraced=nrec_b, queries_per_s=round(nq_ / t_b, 1),
-                             gain_over_rtw_only=round(t_rtw / t_b, 3),
+                             gain_over_rtw_only=round(t_ref / t_b, 3),
                              accepted_err_p99=round(float(torch.quantile(e_b[:1000000].float(), 0.99).item()), 4)
                              if e_b.numel() else 0.0)
             log(f"[surrogate] bar {b:g} {name} ({nq_} queries): tau {tb:.4g}, accepted "
-                f"{row[name]['accepted_fraction']:.2%}, particles re-traced {nrec_b}/{n_qp}, "
-                f"{nq_ / t_b:.0f} queries/s (gain {t_rtw / t_b:.2f})")
+                f"{row[name]['accepted_fraction']:.2%}, particles re-traced {nrec_b}, "
+                f"{nq_ / t_b:.0f} queries/s (gain {t_ref / t_b:.2f})")
             del ans_b, used_b, e_b
         at_bars[f"{b:g}"] = row
     (ans, pred, used, nrec), t_q = timed_query(tau)
@@ -549,6 +567,9 @@ def bench_surrogate(args, rtw, inputs):
         f"p99 {p99:.4f}, >1%: {frac_bad:.2%}; time {t_q:.2f} s vs RTW alone {t_rtw:.2f} s; network alone "
         f"{t_fwd * 1e3:.1f} ms")
     value = n_q / t_q
+    # the network's own share: at the 1% bar it may answer nothing, and the
+    # value is then the rate of RTW answering through the query path
+    answered_by = "network and RTW fallback" if frac_acc > 0 else "RTW fallback only (the network met the 1% bar nowhere)"
     out = {
         "metric": "surrogate queries/s at 1% err",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -557,6 +578,7 @@ def bench_surrogate(args, rtw, inputs):
         "config": {"workload": f"{n_q} queries: {k_q} random 5x10 deg cells (theta 120-170) of each of {n_qp} seeded "
                                f"ellipsoids (batched-workload distribution); MLP 9-512x6-4 trained "
                                f"{args.train_steps} steps on {n} cell samples of {4096 * len(TRAIN_SEEDS)} other ellipsoids",
+                   "answered_by": answered_by,
                    "tau": tau, "accepted_fraction": frac_acc, "particles_retraced": nrec,
                    "accepted_err_p99": p99, "accepted_err_gt_1pct": frac_bad,
                    "rtw_only_queries_per_s": round(n_q / t_rtw, 1), "gain_over_rtw_only": round(t_rtw / t_q, 3),
@@ -585,7 +607,7 @@ def main():
                          "surrogate: train the MLP on rtw_batch data, then time 1M queries with RTW fallback; "
                          "paper_spheroid: the paper's spheroid on the whole sphere at 0.01 deg; "
                          "large: the 1000 um ellipsoid, p<=5, 8192^2 rays")
-    ap.add_argument("--train-steps", type=int, default=40000)
+    ap.add_argument("--train-steps", type=int, default=120000)
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--spheroid-grid-n", type=int, default=3456)
     ap.add_argument("--spheroid-bands", type=int, default=16)

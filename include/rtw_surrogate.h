@@ -89,6 +89,15 @@ int rtw_surrogate_set_normalization(rtw_surrogate* h, const float* feat_shift, c
 int rtw_surrogate_get_params(rtw_surrogate* h, float* host, size_t n);
 int rtw_surrogate_set_params(rtw_surrogate* h, const float* host, size_t n);
 
+/* A trained network to / from a file (synchronous): parameters and
+ * normalisation, in this library's own format (magic "RTWS", version 1, the
+ * parameter count, 22 normalisation floats -- 9 feature shifts, 9 feature
+ * scales, 2 target shifts, 2 target scales -- then the FP32 parameters in the
+ * order of get/set_params, host byte order).  Loading a file of another
+ * network shape or format gives RTW_ERR_INVALID_ARG and leaves h unchanged. */
+int rtw_surrogate_save(rtw_surrogate* h, const char* path);
+int rtw_surrogate_load(rtw_surrogate* h, const char* path);
+
 /* Predictions for n feature rows (DEVICE feats [n][9] FP32) into DEVICE pred
  * [n][4] FP32: ln I_x, ln I_y, ln sigma_x, ln sigma_y.  n <= max_rows. */
 int rtw_surrogate_forward(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream);

@@ -660,6 +660,53 @@ int rtw_surrogate_set_normalization(rtw_surrogate* h, const float* feat_shift, c
   return RTW_OK;
 }
 
+// Trained network to and from a file: magic "RTWS", format version, parameter
+// count, the 22 normalisation floats, then the FP32 parameters (host byte order).
+namespace {
+constexpr uint32_t WEIGHTS_MAGIC = 0x53575452u;  // "RTWS"
+constexpr uint32_t WEIGHTS_VERSION = 1;
+}  // namespace
+
+int rtw_surrogate_save(rtw_surrogate* h, const char* path) {
+  if (!h || !path) return mfail(RTW_ERR_INVALID_ARG, "NULL argument");
+  size_t n = 0;
+  rtw_surrogate_param_count(&n);
+  std::vector<float> par(n);
+  int rc = rtw_surrogate_get_params(h, par.data(), n);
+  if (rc) return rc;
+  float norm[22];
+  if (hipMemcpy(norm, h->norm, sizeof(norm), hipMemcpyDeviceToHost) != hipSuccess)
+    return mfail(RTW_ERR_DEVICE, "normalisation read failed");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return mfail(RTW_ERR_INVALID_ARG, "cannot open %s for writing", path);
+  const uint32_t head[2] = {WEIGHTS_MAGIC, WEIGHTS_VERSION};
+  const uint64_t cnt = n;
+  bool ok = std::fwrite(head, sizeof(head), 1, f) == 1 && std::fwrite(&cnt, sizeof(cnt), 1, f) == 1 &&
+            std::fwrite(norm, sizeof(norm), 1, f) == 1 && std::fwrite(par.data(), sizeof(float), n, f) == n;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? RTW_OK : mfail(RTW_ERR_INVALID_ARG, "write to %s failed", path);
+}
+
+int rtw_surrogate_load(rtw_surrogate* h, const char* path) {
+  if (!h || !path) return mfail(RTW_ERR_INVALID_ARG, "NULL argument");
+  size_t n = 0;
+  rtw_surrogate_param_count(&n);
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return mfail(RTW_ERR_INVALID_ARG, "cannot open %s", path);
+  uint32_t head[2] = {0, 0};
+  uint64_t cnt = 0;
+  float norm[22];
+  std::vector<float> par(n);
+  const bool ok = std::fread(head, sizeof(head), 1, f) == 1 && std::fread(&cnt, sizeof(cnt), 1, f) == 1 &&
+                  head[0] == WEIGHTS_MAGIC && head[1] == WEIGHTS_VERSION && cnt == n &&
+                  std::fread(norm, sizeof(norm), 1, f) == 1 && std::fread(par.data(), sizeof(float), n, f) == n;
+  std::fclose(f);
+  if (!ok) return mfail(RTW_ERR_INVALID_ARG, "%s is not a weights file of this network", path);
+  int rc = rtw_surrogate_set_normalization(h, norm, norm + IN_RAW, norm + 18, norm + 20);
+  if (rc) return rc;
+  return rtw_surrogate_set_params(h, par.data(), n);
+}
+
 // Parameters in a fixed order, FP32: for each layer l = 0..6, W[in][out] then
 // bias[out], with in = 128 for layer 0 (rows >= 23 unused) and out = 128 for
 // the last layer (columns >= 4 unused).

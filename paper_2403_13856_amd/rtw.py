@@ -415,6 +415,8 @@ def sload():
     L.rtw_surrogate_get_params.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
     L.rtw_surrogate_set_params.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
     L.rtw_surrogate_get_grads.argtypes = [vp, P(ctypes.c_float), ctypes.c_size_t]
+    L.rtw_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.rtw_surrogate_load.argtypes = [vp, ctypes.c_char_p]
     L.rtw_surrogate_forward.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.rtw_surrogate_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.rtw_surrogate_train_step.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_float, vp, vp]
@@ -505,6 +507,14 @@ class Surrogate:
         import numpy as np
         p = np.ascontiguousarray(p, dtype=np.float32)
         _scheck(sload().rtw_surrogate_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def save(self, path):
+        """Write the trained network (parameters and normalisation) to a file."""
+        _scheck(sload().rtw_surrogate_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        """Read a network written by save()."""
+        _scheck(sload().rtw_surrogate_load(self.h, str(path).encode()))
 
     def get_grads(self):
         import numpy as np

@@ -2,8 +2,10 @@
 
 * Forward and gradients of the BF16 MFMA network against the FP64 CPU
   reference (oracle/mlp_ref.py) evaluated on the same BF16-rounded operands:
-  predictions within 2e-2 (1 + |value|), per-layer weight gradients within
-  5e-2 relative L2 with cosine > 0.995.  The reference's own gradients are
+  predictions within 5e-3 (1 + |value|), per-layer weight gradients within
+  1e-2 relative L2 with cosine > 0.9999 (about five times the measured
+  9.7e-4 and 1.3e-3: the FP32 accumulation order and the BF16 rounding of
+  intermediate activations differ from the reference's).  The reference's own gradients are
   pinned against central differences by tests/test_oracle_mlp.py.
 * Training fits the means of a smooth synthetic target, and the sigma head
   tracks the squared error.
@@ -12,6 +14,7 @@
   sigma all answers are the surrogate's predictions.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -75,7 +78,7 @@ def test_forward_matches_reference(R):
     ref = M.predict(s.get_params(), f, NORM, bf16_ops=True)
     err = np.abs(got - ref) / (1.0 + np.abs(ref))
     say(f"   max scaled error {err.max():.3e}")
-    assert err.max() < 2e-2
+    assert err.max() < 5e-3
 
 
 def test_gradients_match_reference(R):
@@ -98,7 +101,7 @@ def test_gradients_match_reference(R):
             rel = np.linalg.norm(a - b) / nb
             cos = float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * nb))
             say(f"   layer {l} {name}: rel {rel:.2e} cos {cos:.6f}")
-            assert rel < 5e-2 and cos > 0.995
+            assert rel < 1e-2 and cos > 0.9999
 
 
 def test_training_fits_means_and_sigma(R):
@@ -211,3 +214,116 @@ def test_query_partial_fallback_larger_than_whole_set(R):
                                     desc, cells)
     assert nrec == len(S) and int(used.sum()) == q_part.size
     assert np.array_equal(ans.cpu().numpy(), cellI[q_part, q_cell])
+
+
+def test_trained_network_gains_over_rtw_alone(R, tmp_path):
+    """What the trained network gains over the method without it.  The network
+    is trained (30 000 Adam steps) on RTW cell values of 8192 seeded particles,
+    saved and re-loaded, its sigma threshold calibrated on 1024 held-out
+    particles for the 10% bar (|d ln I| <= 0.1 for 99% of accepted answers),
+    then 2048 new particles are queried at one random cell each: the network
+    answers where sigma <= tau, RTW the rest.  Against RTW alone on the same
+    queries: accepted answers within the bar, fewer particles traced, less
+    time.  At the 1% bar this network accepts nothing (its held-out median
+    error is several per cent), which bench.py reports."""
+    th = I.uniform_angles(120.0, 169.5, 0.5)  # the cells' band only, for both paths
+    _, ph = I.batch_node_grid()
+    cells = R.Cells(10, 120.0, 5.0, 36, 0.0, 10.0)
+    inc = R.make_incident(0.6328, 2)
+    opts = R.make_opts(0, 3, 2, R.MIXED)
+
+    def traced(seed, n, tune=None):
+        bp = I.batch_particles(n, seed=seed)
+        parts = [(p.semi_axes, p.euler_deg, p.m) for p in bp]
+        sides = [p.grid_n for p in bp]
+        b = R.Batch(parts, sides, inc, opts, th, ph, incoherent=True, tune=tune)
+        b.launch(with_counts=False)
+        cI = R.cell_log_intensity(b, cells)
+        assert b.status()[0] == R.RTW_OK
+        del b
+        return parts, sides, cI
+
+    F, Y = [], []
+    for seed in (11, 12):
+        parts, _, cI = traced(seed, 4096)
+        F.append(torch.from_numpy(R.surrogate_features(parts, inc, cells)).cuda())
+        Y.append(cI.reshape(-1, 2))
+    F, Y = torch.cat(F), torch.cat(Y)
+    ok = (Y > -50.0).all(dim=1)
+    F, Y = F[ok].contiguous(), Y[ok].contiguous()
+    s = R.Surrogate(seed=0, max_rows=16384)
+    s.set_normalization(np.array([1.0, 1.0, 7.0, 1.4, 0.0, 90.0, 0.0, 145.0, 180.0], np.float32),
+                        np.array([0.2, 0.2, 1.0, 0.1, 180.0, 90.0, 180.0, 25.0, 180.0], np.float32),
+                        Y.mean(0).cpu().numpy(), Y.std(0).cpu().numpy())
+    g = torch.Generator(device=F.device)
+    g.manual_seed(0)
+    steps, bs, n = 30000, 8192, F.shape[0]
+    say(f"[surrogate gain] training {steps} steps on {n} cell samples")
+    perm = torch.randperm(n, device=F.device, generator=g)
+    for it in range(steps):
+        a = (it * bs) % (n - bs)
+        if a < bs:
+            perm = torch.randperm(n, device=F.device, generator=g)
+        idx = perm[a:a + bs]
+        s.train_step(F[idx], Y[idx], 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + np.cos(np.pi * it / steps)))
+    # the trained network survives a save / load round trip bit for bit
+    path = tmp_path / "surrogate.rtws"
+    s.save(path)
+    s2 = R.Surrogate(seed=99, max_rows=16384)
+    s2.load(path)
+    probe = F[:4096]
+    assert torch.equal(s.forward(probe), s2.forward(probe))
+    del s
+    s = s2
+    # calibration of tau on held-out particles
+    parts, _, cI = traced(13, 1024)
+    fc = torch.from_numpy(R.surrogate_features(parts, inc, cells)).cuda()
+    yc = cI.reshape(-1, 2)
+    keep = (yc > -50.0).all(dim=1)
+    pred = s.forward(fc)[keep]
+    err = (pred[:, :2] - yc[keep]).abs().max(dim=1).values
+    sig = pred[:, 2:].max(dim=1).values.exp()
+    order = torch.argsort(sig)
+    bad = torch.cumsum((err[order] > 0.1).int(), 0).float()
+    okk = bad <= 0.01 * torch.arange(1, err.numel() + 1, device=err.device).float()
+    k = int(torch.nonzero(okk).max().item()) + 1
+    tau = float(sig[order[k - 1]].item())
+    say(f"[surrogate gain] held-out median |d ln I| {err.median().item():.4f}; tau {tau:.4g} accepts "
+        f"{k / err.numel():.2%} at the 10% bar")
+    # queries: one random cell of each of 2048 new particles
+    bp = I.batch_particles(2048, seed=17)
+    parts = [(p.semi_axes, p.euler_deg, p.m) for p in bp]
+    sides = [p.grid_n for p in bp]
+    rng = np.random.default_rng(17)
+    q_cell = rng.integers(0, 360, size=2048).astype(np.int32)
+    q_part = np.arange(2048, dtype=np.int32)
+    allf = R.surrogate_features(parts, inc, cells).reshape(2048, 360, 9)
+    qf = torch.from_numpy(np.ascontiguousarray(allf[q_part, q_cell])).cuda()
+    qp, qc = torch.from_numpy(q_part).cuda(), torch.from_numpy(q_cell).cuda()
+    b = R.Batch(parts, sides, inc, opts, th, ph, incoherent=True)
+    b.launch(with_counts=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.launch(with_counts=False)
+    truth = R.cell_log_intensity(b, cells)[qp.long(), qc.long()]
+    torch.cuda.synchronize()
+    t_rtw = time.perf_counter() - t0
+    del b
+    torch.cuda.empty_cache()
+    desc = R.Batch(parts, sides, inc, opts, th, ph, allocate=False)
+    s.query(qf, qp, qc, tau, desc, cells)  # warm-up (allocates the scratch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ans, _, used, nrec = s.query(qf, qp, qc, tau, desc, cells)
+    torch.cuda.synchronize()
+    t_q = time.perf_counter() - t0
+    acc = used == 0
+    live = (truth > -50.0).all(dim=1)
+    e = (ans - truth).abs().max(dim=1).values[acc & live]
+    frac_bad = float((e > 0.1).float().mean().item()) if e.numel() else 0.0
+    say(f"[surrogate gain] 2048 queries: network answered {acc.float().mean().item():.2%}, particles traced "
+        f"{nrec}/2048, accepted answers above the bar {frac_bad:.2%}; {t_q * 1e3:.0f} ms against RTW alone "
+        f"{t_rtw * 1e3:.0f} ms (gain {t_rtw / t_q:.2f})")
+    assert acc.float().mean().item() > 0.15 and nrec < 2048
+    assert frac_bad <= 0.03
+    assert t_rtw / t_q > 1.0
