@@ -28,20 +28,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic floating-point work (adds, multiplies, divides and square roots
-# counted once each, an FMA as two, an elementary function as one), per unit
-# of the method:
-#   rasteriser: per valid triangle, orientation triple product (20) and
-#   angular bounds (40); per node hit, membership and barycentric weights (58)
-#   hit store: per node hit, carrying and projecting the three vertex fields
-#   for two polarisations (180)
-#   node sum: per hit, 8 accumulations
-FLOP_RASTER_PER_TRIANGLE = 60
-FLOP_RASTER_PER_HIT = 58
-FLOP_STORE_PER_HIT = 180
-# per active ray, p = 0..3: four interactions (both branches), three
-# propagations, four emissions
-FLOP_TRACE_PER_RAY = 4 * 300 + 3 * 60 + 4 * 200
+# Algorithmic floating-point work per unit of the method (an FMA as two, an
+# elementary function as one), in the units of the method's work estimate:
+#   per surface interaction, both branches and the propagation after it: 300
+#   per emitted order (amplitude, phase, field vectors, direction): 200
+#   per valid triangle (orientation and bounds; two per quad and order): 25
+#   per node hit, membership, weights, carrying the three vertex fields,
+#   projecting them and the ordered sum together: 150
+#   whole step, p <= 3, per active incident ray: 2400
+FLOP_PER_INTERACTION = 300
+FLOP_PER_EMISSION = 200
+FLOP_PER_TRIANGLE = 25
+FLOP_PER_HIT = 150
+FLOP_PER_RAY_STEP = 2400
+# a finer build-side count of the same kernels, reported beside it:
+# rasteriser 60 per triangle and 58 per hit, hit store 180 per hit, trace
+# 4 x 300 + 3 x 60 + 4 x 200 per ray
+FINE_RASTER_PER_TRIANGLE = 60
+FINE_RASTER_PER_HIT = 58
+FINE_STORE_PER_HIT = 180
+FINE_TRACE_PER_RAY = 4 * 300 + 3 * 60 + 4 * 200
 PEAK_VALU_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, one per 4 cycles
 TRAIN_SEEDS = (11, 12, 15, 16)  # surrogate training particles: 4 x 4096 seeded ellipsoids
@@ -77,9 +83,19 @@ def measured_counters():
     if kv.get("source_hash") != source_hash():
         return None
     try:
+        per_kernel = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) >= 3 and parts[0].startswith(("k_", "rtw::k_")):
+                    try:
+                        per_kernel[parts[0]] = (float(parts[1]) + float(parts[2])) * 1e6
+                    except ValueError:
+                        pass
         return dict(traffic=float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]),
                     valu_busy_pct=float(kv["valu_busy_pct"]), valu_utilization_pct=float(kv["valu_utilization_pct"]),
-                    valu_insts=float(kv["valu_insts_per_launch"]))
+                    valu_insts=float(kv["valu_insts_per_launch"]), per_kernel_bytes=per_kernel,
+                    kernel=kv.get("kernel"))
     except (KeyError, ValueError):
         return None
 
@@ -670,31 +686,51 @@ def main():
                     kernels_ms={k: round(t / n, 5) for k, (t, n) in prof64.items()})
 
     value = n_active / (ms_mixed * 1e-3)
-    # roofline of the dominant kernel (plain VALU arithmetic: "alu")
+    # roofline of the dominant kernel (plain VALU arithmetic: "alu"), in the
+    # method's work units; the finer build-side count beside it
     dom, (tot, cnt) = max(prof_mixed.items(), key=lambda kv: kv[1][0])
     avg_s = tot / cnt * 1e-3
+    n_ord = w.p_max - w.p_min + 1
     if dom.startswith("k_trace"):
-        flops = FLOP_TRACE_PER_RAY * n_active
+        flops = n_active * ((w.p_max + 1) * FLOP_PER_INTERACTION + n_ord * FLOP_PER_EMISSION)
+        fine = FINE_TRACE_PER_RAY * n_active
     elif dom.startswith("k_raster_rows"):
-        flops = FLOP_RASTER_PER_HIT * hits  # share of hits unknown per kernel: upper bound
+        flops = FLOP_PER_HIT * hits  # share of hits unknown per kernel: upper bound
+        fine = FINE_RASTER_PER_HIT * hits
     elif dom.startswith("k_raster"):
-        flops = FLOP_RASTER_PER_TRIANGLE * n_tri + FLOP_RASTER_PER_HIT * hits
-    elif dom.startswith("k_store_hits"):
-        flops = FLOP_STORE_PER_HIT * hits
+        # every per-hit unit is counted here (membership, weights, carry, sum): an upper bound of the kernel's own
+        flops = FLOP_PER_TRIANGLE * n_tri + FLOP_PER_HIT * hits
+        fine = FINE_RASTER_PER_TRIANGLE * n_tri + FINE_RASTER_PER_HIT * hits
     else:
-        flops = 8 * hits
+        flops = FLOP_PER_HIT * hits
+        fine = FINE_STORE_PER_HIT * hits
     achieved = flops / avg_s / 1e12
     # the counters are of the plane wave observed in the far field
-    ctr = measured_counters() if dom == "k_raster_mixed" and zs == 0 and robs == 0 else None
-    traffic = ctr["traffic"] if ctr else None
+    ctr = measured_counters() if zs == 0 and robs == 0 else None
+    dom_ctr = ctr if ctr and ctr.get("kernel") and dom.replace("_mixed", "") in ctr["kernel"].replace("<float>", "") \
+        else None
+    traffic = dom_ctr["traffic"] if dom_ctr else None
+    step_flop = FLOP_PER_RAY_STEP * n_active
+    # the method's HBM budget per step: inputs (~100 B), the output field and
+    # two passes of 36 B over every contribution
+    budget = 100 + w.n_nodes * w.n_pol * 2 * 2 * 4 + 2 * 36 * hits
+    step_bytes = sum(ctr["per_kernel_bytes"].values()) if ctr else None
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
                     traffic=round(traffic) if traffic is not None else None, kernel=dom,
                     kernel_ms=round(avg_s * 1e3, 4), flop_per_launch=flops,
+                    flop_units="interaction 300, emission 200, triangle 25, hit 150 (all per-hit work)",
+                    fine_count=dict(flop_per_launch=fine, achieved=round(fine / avg_s / 1e12, 4),
+                                    frac=round(fine / avg_s / 1e12 / PEAK_VALU_FP32_TFLOPS, 5)),
+                    whole_step=dict(flop=step_flop, flop_per_ray=FLOP_PER_RAY_STEP,
+                                    achieved=round(step_flop / (ms_mixed * 1e-3) / 1e12, 4),
+                                    frac=round(step_flop / (ms_mixed * 1e-3) / 1e12 / PEAK_VALU_FP32_TFLOPS, 5),
+                                    counter_bytes=round(step_bytes) if step_bytes else None,
+                                    algorithmic_bytes=budget),
                     traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic is not None else None,
-                    valu_busy_pct=ctr["valu_busy_pct"] if ctr else None,
-                    valu_utilization_pct=ctr["valu_utilization_pct"] if ctr else None,
-                    valu_issue_frac=round(ctr["valu_insts"] / avg_s / VALU_ISSUE_PEAK, 4) if ctr else None)
+                    valu_busy_pct=dom_ctr["valu_busy_pct"] if dom_ctr else None,
+                    valu_utilization_pct=dom_ctr["valu_utilization_pct"] if dom_ctr else None,
+                    valu_issue_frac=round(dom_ctr["valu_insts"] / avg_s / VALU_ISSUE_PEAK, 4) if dom_ctr else None)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -706,7 +742,9 @@ def main():
                         w.theta_deg, w.phi_deg)
         dt = time.perf_counter() - t0
         cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
-                   sample=f"full workload ({args.grid_n}^2 rays, all {w.n_nodes} nodes), one run, {dt:.1f} s")
+                   sample=f"full workload ({args.grid_n}^2 rays, all {w.n_nodes} nodes), one run, {dt:.1f} s; "
+                          f"the trace runs on the {oracle.get_threads()} threads, the rasterisation (assembly) "
+                          f"on one")
         log(f"[bench] cpu oracle: {dt:.1f} s on {oracle.get_threads()} threads")
         # the same oracle on one thread, over a bounded sample: the same
         # particle and node grid at 512^2 rays (its active rays counted from

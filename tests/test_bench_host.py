@@ -26,7 +26,13 @@ def test_counter_summary_matches_or_is_dropped(tmp_path, monkeypatch):
     f.write_text(f"kernel: k\nsource_hash: {bench.source_hash()}\n" + COUNTER_LINES)
     monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
     c = bench.measured_counters()
-    assert c == dict(traffic=123.0, valu_busy_pct=55.5, valu_utilization_pct=40.25, valu_insts=7.0)
+    assert c == dict(traffic=123.0, valu_busy_pct=55.5, valu_utilization_pct=40.25, valu_insts=7.0,
+                     per_kernel_bytes={}, kernel="k")
+    # per-kernel rows of the table (MB fetched, MB written) are summed per kernel
+    f.write_text(f"kernel: k\nsource_hash: {bench.source_hash()}\n" + COUNTER_LINES +
+                 "k_trace_tiles<float>  1.5  2.5  80.0\nrtw::k_raster<float>  10.0  0.5  50.0\n")
+    c = bench.measured_counters()
+    assert c["per_kernel_bytes"] == {"k_trace_tiles<float>": 4.0e6, "rtw::k_raster<float>": 10.5e6}
     f.write_text("source_hash: 0000\n" + COUNTER_LINES)
     assert bench.measured_counters() is None  # kernel changed since the counters were taken
 
