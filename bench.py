@@ -16,7 +16,9 @@ the FP64 oracle on the full workload, timed on the host cores.
 Other modes, each printing its own JSON line: --workload batch | surrogate |
 paper_spheroid | large; --source-distance Z (the ellipsoid lit by a point
 source at lab (0, 0, -Z)); --observation-radius R (the ellipsoid's field on
-the sphere of radius R instead of the far field).
+the sphere of radius R instead of the far field); --corrections caustic |
+diffraction | both (the fold-caustic and forward-diffraction terms);
+--m-im K (a weakly absorbing ellipsoid, m = 1.333 + iK).
 """
 import argparse
 import json
@@ -53,6 +55,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 256 CUs x 4
 TRAIN_SEEDS = (11, 12, 15, 16)  # surrogate training particles: 4 x 4096 seeded ellipsoids
 LR_PEAK = 1e-3                  # surrogate Adam learning rate at the start of the cosine schedule
 PEAK_HBM_GBS = 8000.0
+CORRECTIONS = {"none": 0, "caustic": 1, "diffraction": 2, "both": 3}  # rtw_trace_opts.corrections bits
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_raster_mixed_c2_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_13856_amd", "csrc", f)
                   for f in ("rtw_lib.hip", "rtw_device.hpp", "rtw_raster.hpp")]
@@ -147,11 +150,11 @@ def count_units(rtw, w, grid_n, zs=0.0, robs=0.0):
     return n_active, n_tri
 
 
-def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0, robs=0.0):
+def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0, robs=0.0, corr=0, m_im=0.0):
     import torch
-    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m),
+    ff = rtw.FarField(rtw.make_particle(w.semi_axes, w.euler_deg, w.m, m_im=m_im),
                       rtw.make_incident(w.wavelength, w.n_pol, zs, robs),
-                      rtw.make_opts(w.p_min, w.p_max, grid_n, precision), w.theta_deg, w.phi_deg)
+                      rtw.make_opts(w.p_min, w.p_max, grid_n, precision, corrections=corr), w.theta_deg, w.phi_deg)
     ff()  # sizes the workspace (grows it if the hit pool overflowed)
     for _ in range(warmup):
         ff.launch(with_counts=False)
@@ -630,6 +633,10 @@ def main():
     ap.add_argument("--large-grid-n", type=int, default=8192)
     ap.add_argument("--source-distance", type=float, default=0.0,
                     help="ellipsoid workload lit by a point source at lab (0, 0, -z) instead of the plane wave (um)")
+    ap.add_argument("--corrections", choices=sorted(CORRECTIONS), default="none",
+                    help="ellipsoid workload: fold-caustic and/or forward-diffraction corrections")
+    ap.add_argument("--m-im", type=float, default=0.0,
+                    help="ellipsoid workload: imaginary part of the refractive index (weak absorption)")
     ap.add_argument("--observation-radius", type=float, default=0.0,
                     help="ellipsoid workload observed on the sphere of this radius instead of the far field (um)")
     args = ap.parse_args()
@@ -667,18 +674,21 @@ def main():
     w = inputs.ellipsoid_mixed(args.grid_n)
     zs = args.source_distance
     robs = args.observation_radius
+    corr = CORRECTIONS[args.corrections]
+    m_im = args.m_im
     n_active, n_tri = count_units(rtw, w, args.grid_n, zs, robs)
     log(f"[bench] workload {w.name}: {args.grid_n}^2 rays ({n_active} active), {w.theta_deg.size}x{w.phi_deg.size} "
         f"nodes, p={w.p_min}..{w.p_max}, n_pol={w.n_pol}, {n_tri} valid triangles")
 
-    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup, zs, robs)
+    ms_mixed, prof_mixed, hits, fp64_rays = time_path(rtw, w, args.grid_n, rtw.MIXED, args.steps, args.warmup, zs, robs,
+                                                      corr, m_im)
     log(f"[bench] mixed: {ms_mixed:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
     for k, (t, n) in sorted(prof_mixed.items(), key=lambda kv: -kv[1][0]):
         log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
     fp64 = None
     if not args.no_fp64:
         ms64, prof64, hits64, _ = time_path(rtw, w, args.grid_n, rtw.FP64, max(2, args.steps // 2),
-                                            max(1, args.warmup // 2), zs, robs)
+                                            max(1, args.warmup // 2), zs, robs, corr, m_im)
         log(f"[bench] fp64: {ms64:.3f} ms/step")
         for k, (t, n) in sorted(prof64.items(), key=lambda kv: -kv[1][0]):
             log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
@@ -705,8 +715,8 @@ def main():
         flops = FLOP_PER_HIT * hits
         fine = FINE_STORE_PER_HIT * hits
     achieved = flops / avg_s / 1e12
-    # the counters are of the plane wave observed in the far field
-    ctr = measured_counters() if zs == 0 and robs == 0 else None
+    # the counters are of the plane wave observed in the far field, without corrections
+    ctr = measured_counters() if zs == 0 and robs == 0 and corr == 0 and m_im == 0 else None
     dom_ctr = ctr if ctr and ctr.get("kernel") and dom.replace("_mixed", "") in ctr["kernel"].replace("<float>", "") \
         else None
     traffic = dom_ctr["traffic"] if dom_ctr else None
@@ -736,9 +746,9 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
-        oracle.farfield(oracle.particle(w.semi_axes, w.euler_deg, w.m),
+        oracle.farfield(oracle.particle(w.semi_axes, w.euler_deg, w.m, m_im=m_im),
                         oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, args.grid_n, source_distance=zs,
-                                     observation_radius=robs),
+                                     observation_radius=robs, corrections=corr),
                         w.theta_deg, w.phi_deg)
         dt = time.perf_counter() - t0
         cpu = dict(value=round(n_active / dt, 1), unit="rays/s", cores=oracle.get_threads(), kind="oracle",
@@ -753,9 +763,9 @@ def main():
         cores = oracle.get_threads()
         oracle.set_threads(1)
         try:
-            op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
+            op = oracle.particle(w.semi_axes, w.euler_deg, w.m, m_im=m_im)
             st1 = oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, n1, source_distance=zs,
-                               observation_radius=robs)
+                               observation_radius=robs, corrections=corr)
             act1 = int((oracle.trace_grid(op, oracle.setup(w.wavelength, 1, 0, 0, n1, source_distance=zs))["flags"][0]
                         & 1).sum())
             t0 = time.perf_counter()
@@ -783,7 +793,9 @@ def main():
         "config": {"workload": f"ellipsoid 60/50/40 um, Euler (30,20,10) deg, m=1.333, lambda=0.6328 um, "
                                f"p=0..3, {args.grid_n}x{args.grid_n} rays, 1801x720 nodes, 2 polarisations, mixed"
                                + (f", point source at {zs:g} um" if zs > 0 else "")
-                               + (f", nodes on the sphere of radius {robs:g} um" if robs > 0 else ""),
+                               + (f", nodes on the sphere of radius {robs:g} um" if robs > 0 else "")
+                               + (f", {args.corrections} correction" if corr else "")
+                               + (f", m_im={m_im:g}" if m_im > 0 else ""),
                    "active_rays": n_active, "valid_triangles": n_tri, "source_hash": source_hash(), "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(w.n_nodes * w.n_pol / (ms_mixed * 1e-3), 1),
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},

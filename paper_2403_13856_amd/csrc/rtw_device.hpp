@@ -285,7 +285,12 @@ struct Emission {
 // interpolation by ~1e-4; FP64 multiply-adds cost the same as FP32 ones on
 // this chip, so the polyline stays FP64.
 // ---------------------------------------------------------------------------
-template <typename G, typename Sink>
+// GEN = false compiles out the finite observation radius and absorption (for
+// particles with !needs_general_trace): the plain far field then fits three
+// waves per SIMD without spilling.
+__host__ __device__ inline bool needs_general_trace(const ParticleConst& P) { return P.robs > 0.0 || P.m_im > 0.0; }
+
+template <typename G, bool GEN = true, typename Sink>
 __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   typedef v3<double> V;
   const double* R = P.R;
@@ -464,7 +469,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
                      R[6] * r.x + R[7] * r.y + R[8] * r.z);
       double phase = opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
       ul = dl;
-      if (P.robs > 0.0) {
+      if (GEN && P.robs > 0.0) {
         // finite observation radius: continue the ray by d_M to M on the
         // sphere; the last leg's divergence factor is 1 / det(I + d_M Q')
         // d_M - R without the cancellation of the plain difference at large R
@@ -576,7 +581,7 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
     double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
     q11 = (G)n11; q12 = (G)n12; q22 = (G)n22;
     opl += n_cur * P.k * L;
-    if (n_cur != 1.0 && P.m_im > 0.0) {
+    if (GEN && n_cur != 1.0 && P.m_im > 0.0) {
       // weak absorption along the internal segment
       const G att = (G)exp(-P.k * P.m_im * L);
       for (int k = 0; k < 2; ++k)

@@ -197,10 +197,10 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
 enum : int {
   C_REDO = NPART,  // rays listed for the FP64 re-trace in the current chunk
   C_ROWS,          // row-list items of the current chunk
-  C_QUEUE,         // trace work items taken in the current chunk
+  C_QUEUE,         // trace work items taken in the current chunk (plain particles)
+  C_QUEUE_GEN,     // the same for the particles that need the general trace
   C_NEED,          // fullest hit-pool partition over the chunks of the call
   C_FP64_TOTAL,    // rays re-traced in FP64 over the call
-  C_PAD,
   C_HITS,          // node hits over the call (64-bit, two slots: must be 8-byte aligned)
   C_HITS_HI,
   C_COUNT
@@ -222,9 +222,13 @@ __device__ __forceinline__ ParticleConst load_uniform(const ParticleConst* src) 
 // Persistent trace: every block takes work items (a tile of `tile` incident
 // rays of one particle) from the chunk's queue until it is empty.  Items are
 // numbered particle by particle in launch order (largest particles first),
-// so the cheap items of small particles fill the tail.
-template <typename G>
-__global__ void __launch_bounds__(256, sizeof(G) == 8 ? 2 : 3) k_trace_tiles(const BatchDev B, const Records<G> rec, unsigned* queue) {
+// so the cheap items of small particles fill the tail.  The GEN instance
+// traces the particles observed at a finite radius or absorbing (see
+// trace_ray), the other one the rest; each skips the other's items, so a
+// particle's result never depends on the particles it is batched with.
+template <typename G, bool GEN>
+__global__ void __launch_bounds__(256, (sizeof(G) == 8 || GEN) ? 2 : 3)
+    k_trace_tiles(const BatchDev B, const Records<G> rec, unsigned* queue) {
   __shared__ long s_item;
   const long n_items = B.tile_off[B.n] - B.tile_base;
   for (;;) {
@@ -235,6 +239,7 @@ __global__ void __launch_bounds__(256, sizeof(G) == 8 ? 2 : 3) k_trace_tiles(con
     if (item >= n_items) break;
     const int p = __builtin_amdgcn_readfirstlane(find_part(B.tile_off, B.n, B.tile_base, item));
     const ParticleConst P = load_uniform(B.P + p);
+    if (GEN != needs_general_trace(P)) continue;
     const long NN = (long)P.N * P.N;
     const long first = (item - (B.tile_off[p] - B.tile_base)) * B.tile;
     const long last = min(first + (long)B.tile, NN);
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(256, sizeof(G) == 8 ? 2 : 3) k_trace_tiles(con
         for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
         RecordSink<G> sink{rec, rbase, NN, id, P.k, P.amplif_limit, false, P.k * P.robs};
         const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
-        trace_ray<G>(P, ix, iy, sink);
+        trace_ray<G, GEN>(P, ix, iy, sink);
         redo = sink.need64;
       }
       if (sizeof(G) == 4) {
@@ -425,7 +430,7 @@ __global__ void __launch_bounds__(256) k_diffraction(const BatchDev B, const Nod
 __global__ void k_chunk_reset(int* count, long n_nodes_chunk, unsigned* counter) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_nodes_chunk) count[i] = 0;
-  if (i <= C_QUEUE) counter[i] = 0u;
+  if (i <= C_QUEUE_GEN) counter[i] = 0u;
 }
 
 // End of a chunk: fullest partition (overflow check), hit and FP64 totals.
@@ -822,7 +827,14 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
                        0, st, pool.count, n_cnodes, counter);
     { ProfScope ps(fp64 ? "k_trace_fp64" : "k_trace_mixed", st);
     const long grid_t = std::min<long>(items, (long)cu * tu.blocks_per_cu);
-    hipLaunchKernelGGL(k_trace_tiles<G>, dim3((unsigned)grid_t), dim3(256), 0, st, B, rec, counter + C_QUEUE); }
+    bool any_gen = false, any_plain = false;
+    for (int c = c0; c < c1; ++c) (needs_general_trace(pl.P[c]) ? any_gen : any_plain) = true;
+    if (any_plain)
+      hipLaunchKernelGGL((k_trace_tiles<G, false>), dim3((unsigned)grid_t), dim3(256), 0, st, B, rec,
+                         counter + C_QUEUE);
+    if (any_gen)
+      hipLaunchKernelGGL((k_trace_tiles<G, true>), dim3((unsigned)grid_t), dim3(256), 0, st, B, rec,
+                         counter + C_QUEUE_GEN); }
     if (!fp64) {
       ProfScope ps("k_retrace64", st);
       hipLaunchKernelGGL(k_retrace64, dim3((unsigned)std::min<long>(2048, (rays + 255) / 256)), dim3(256), 0, st, B,
@@ -843,8 +855,12 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     const long slots = (long)NPART * cap_part;
     hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, B, rec, ng, pool); }
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
-    hipLaunchKernelGGL(k_node_sum<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool, n_nodes,
-                       S.n_pol, (G*)out, ncontrib, (G*)incoh); }
+    if (pool.phi)
+      hipLaunchKernelGGL((k_node_sum<G, true>), dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool,
+                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh);
+    else
+      hipLaunchKernelGGL((k_node_sum<G, false>), dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool,
+                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh); }
     if (S.corr & RTW_DIFFRACTION) {
       ProfScope ps("k_diffraction", st);
       hipLaunchKernelGGL(k_diffraction<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng, n_nodes,

@@ -1390,8 +1390,9 @@ __device__ inline void add_fold_pair(const HitPool<G>& pool, long a, long b, int
 // them in that order and write (F_theta, F_phi) for every polarisation into
 // the particle's output block; optionally also the incoherent intensity
 // sum_b (|f_b,theta|^2 + |f_b,phi|^2) of the node's contributions per
-// polarisation.
-template <typename G>
+// polarisation.  CAUSTIC (pool.phi and pool.nf set) adds fold pairs in the
+// uniform Airy form; the plain instantiation keeps its arrays in registers.
+template <typename G, bool CAUSTIC>
 __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPool<G> pool, int n_nodes, int n_pol,
                                                   G* out, int32_t* ncontrib, G* incoh) {
   const long gn = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1416,9 +1417,8 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
   // Caustic correction: contributions of one order slot arrive together (the
   // key orders them by slot first); a slot holding exactly two whose focal-line
   // counts differ by one is a fold pair and is added in the uniform Airy form.
-  const bool caustic = pool.phi != nullptr;
   long qoff = 0, nq = 1;
-  if (caustic) {
+  if constexpr (CAUSTIC) {
     const int N = B.P[pl].N;
     qoff = (long)B.n_ord * (B.quad_off[pl] - B.quad_base);
     nq = (long)(N - 1) * (N - 1);
@@ -1431,7 +1431,11 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
     npend = 0;
   };
   auto take = [&](long at, int key) {
-    if (!caustic) { add(at); return; }
+    if constexpr (!CAUSTIC) {
+      (void)key;
+      add(at);
+      return;
+    }
     const int slot = (int)(((long)(key >> 1) - qoff) / nq);
     if (slot != cur_slot) { flush(); cur_slot = slot; }
     if (npend < 0) { add(at); return; }  // a slot with more than two: plain sum
@@ -1461,7 +1465,7 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
       take(s0 + bi, (int)best);
     }
   }
-  if (caustic) flush();
+  if constexpr (CAUSTIC) flush();
   G* po = out + ob * ((long)n_pol * 2 * n_nodes * 2);
   for (int p = 0; p < n_pol; ++p)
     for (int a = 0; a < 2; ++a) {
