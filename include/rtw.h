@@ -238,7 +238,12 @@ int rtw_farfield_static(const rtw_particle* part, const rtw_incident* inc, const
  * rays; each chunk is traced by one persistent kernel whose blocks take work
  * items (tiles of tile_rays rays of one particle) from a queue, then
  * rasterised and summed like rtw_farfield.  Results are bitwise identical to
- * rtw_farfield of each particle alone with the same tuning. */
+ * rtw_farfield of each particle alone with the same tuning.
+ * With rtw_batch_opts.fused (RTW_MIXED, at most 6 orders, no RTW_CAUSTIC) one
+ * persistent kernel traces, rasterises and forms the hit contributions of
+ * 64 x (tile_rays / 64)-ray tiles in LDS (no per-ray records in the
+ * workspace); its results are bitwise independent of the tuning and agree
+ * with the staged pipeline's within the mixed path's rounding. */
 typedef struct {
   int tile_rays;     /* incident rays per trace work item, multiple of 256 (0 = 1024) */
   int blocks_per_cu; /* persistent trace blocks per compute unit (0 = 8) */
@@ -250,6 +255,11 @@ typedef struct {
   long long rays_per_chunk; /* incident rays per chunk; the workspace scales with it
                                (0 = 2^26; a larger particle is a chunk of its own) */
   double hits_per_node;     /* hit-pool sizing per node of a chunk (0 = 6) */
+  int fused;                /* 1: the fused kernel where it applies (RTW_MIXED, at most 6
+                               orders, no RTW_CAUSTIC): trace, rasterisation and hit
+                               contributions per ray tile in one persistent kernel, with no
+                               per-ray records in the workspace (about a third of the
+                               workspace; slower on MI355X); 0: the staged pipeline */
 } rtw_batch_opts;
 
 /* Workspace bytes for rtw_batch with these arguments (bopts may be NULL). */

@@ -290,8 +290,24 @@ struct Emission {
 // waves per SIMD without spilling.
 __host__ __device__ inline bool needs_general_trace(const ParticleConst& P) { return P.robs > 0.0 || P.m_im > 0.0; }
 
-template <typename G, bool GEN = true, typename Sink>
-__device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
+// The state a ray carries between interactions.
+template <typename G>
+struct RayState {
+  v3<double> r, d, u1, u2;  // position on the surface, direction, polarisation basis (u2 = d x u1)
+  G q11, q12, q22;          // WFC in (u1, u2)
+  cx<G> J[2][2];            // J[component along u_a][incident pol]
+  double D;                 // divergence product of the internal segments
+  double opl;               // optical path (phase), referenced to the particle centre
+  double amplif;            // largest error amplification of the divergence factor so far
+  double drift;             // growth of a direction perturbation so far
+  double n_cur, n_oth;      // index of the current and of the other medium
+  int nf;                   // focal lines crossed so far
+};
+
+// Entry of the incident ray of grid cell (ix, iy) into the particle (the
+// initial state at its first interaction); false if the ray misses.
+template <typename G>
+__device__ __forceinline__ bool ray_init(const ParticleConst& P, int ix, int iy, RayState<G>& s) {
   typedef v3<double> V;
   const double* R = P.R;
   const double x = -P.L + (ix + 0.5) * P.h;
@@ -322,273 +338,297 @@ __device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
   const V Ao = mk3(P.A[0] * o.x, P.A[1] * o.y, P.A[2] * o.z);
   double qa = dot(d, Ad0), qb = 2.0 * dot(d, Ao), qc = dot(o, Ao) - 1.0;
   double disc = qb * qb - 4.0 * qa * qc;
-  if (!(disc > 0.0)) return;
+  if (!(disc > 0.0)) return false;
   double qq = -0.5 * (qb + copysign(sqrt_d(disc), qb));
-  if (qq == 0.0) return;
+  if (qq == 0.0) return false;
   double t = fmin(qq / qa, qc / qq);
 
-  V r = axpy(t, d, o);
-  G q11 = 0, q12 = 0, q22 = 0;   // plane wave
-  cx<G> J[2][2];                 // J[component along u_a][incident pol]
-  J[0][0].re = 1; J[0][0].im = 0; J[0][1].re = 0; J[0][1].im = 0;
-  J[1][0].re = 0; J[1][0].im = 0; J[1][1].re = 1; J[1][1].im = 0;
-  double D = 1.0;
-  int nf = 0;
-  double opl = P.k * dot(d, r);  // incident phase, referenced to the particle centre
+  s.r = axpy(t, d, o);
+  s.d = d;
+  s.u1 = u1;
+  s.u2 = u2;
+  s.q11 = s.q12 = s.q22 = 0;   // plane wave
+  s.J[0][0].re = 1; s.J[0][0].im = 0; s.J[0][1].re = 0; s.J[0][1].im = 0;
+  s.J[1][0].re = 0; s.J[1][0].im = 0; s.J[1][1].re = 1; s.J[1][1].im = 0;
+  s.D = 1.0;
+  s.nf = 0;
+  s.opl = P.k * dot(d, s.r);  // incident phase, referenced to the particle centre
   if (P.zs > 0.0) {
     // spherical wave rho = t0 + t from the source: WFC I / rho, amplitude
     // zs / rho, phase k (rho - zs) (both referenced to the particle centre)
     const double rho = t0 + t;
     const double irho = rcp_d(rho);
-    q11 = q22 = (G)irho;
-    J[0][0].re = J[1][1].re = (G)(P.zs * irho);
-    opl = P.k * (rho - P.zs);
+    s.q11 = s.q22 = (G)irho;
+    s.J[0][0].re = s.J[1][1].re = (G)(P.zs * irho);
+    s.opl = P.k * (rho - P.zs);
   }
   // Largest relative-error amplification met so far by the divergence factor:
   // the cancellation in det(I + L Q) per propagation (a focal line close to an
   // interface).  Each emission adds the cancellation of its own exit wavefront
   // equation (a flat exit wavefront: a far-field caustic).
-  double amplif = 1.0;
-  double drift = 1.0;
-  double n_cur = 1.0, n_oth = P.m;
+  s.amplif = 1.0;
+  s.drift = 1.0;
+  s.n_cur = 1.0;
+  s.n_oth = P.m;
+  return true;
+}
+
+// Interaction q (1 = entry) of a ray in state s.  An order in [p_min, p_max]
+// emitted here goes to sink.emit at once.  Returns bit 0 when it emits, bit 1
+// when the ray goes on to interaction q + 1 (s then holds its state there).
+template <typename G, bool GEN, typename Sink>
+__device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RayState<G>& s, Sink& sink) {
+  typedef v3<double> V;
+  const double* R = P.R;
   const G kk = (G)P.k;
-
-  for (int q = 1; q <= P.p_max + 1; ++q) {
-    // outward normal and incidence-plane basis (FP64)
-    V Ar = mk3(P.A[0] * r.x, P.A[1] * r.y, P.A[2] * r.z);
-    const double inA = rsq_d(dot(Ar, Ar));
-    V nh = scl(inA, Ar);
-    const double dn = dot(d, nh);  // n . k_hat (signed)
-    const double sgn = dn > 0 ? 1.0 : -1.0;
-    const double ci = sgn * dn;    // cos(theta_i)
-    V c = scl(sgn, cross(d, nh));  // d x nu
-    const double c2 = dot(c, c);
-    V ep = c2 < 1e-24 ? u1 : scl(rsq_d(c2), c);
-    // rotate the carried state into (e_perp, e_par): e_perp = cs u1 + sn u2
-    const G cs = (G)dot(ep, u1), sn = (G)dot(ep, u2);
-    cx<G> Jl[2][2];
-    for (int k = 0; k < 2; ++k) {
-      Jl[0][k].re = cs * J[0][k].re + sn * J[1][k].re;
-      Jl[0][k].im = cs * J[0][k].im + sn * J[1][k].im;
-      Jl[1][k].re = -sn * J[0][k].re + cs * J[1][k].re;
-      Jl[1][k].im = -sn * J[0][k].im + cs * J[1][k].im;
-    }
-    G t11 = cs * cs * q11 + 2 * cs * sn * q12 + sn * sn * q22;
-    G t12 = (cs * cs - sn * sn) * q12 + cs * sn * (q22 - q11);
-    G t22 = sn * sn * q11 - 2 * cs * sn * q12 + cs * cs * q22;
-
-    // surface curvature in (s1, s2) = (e_perp, n x e_perp), shape operator of r^T A r = 1
-    V s2 = cross(nh, ep);
-    const G C11 = (G)((P.A[0] * ep.x * ep.x + P.A[1] * ep.y * ep.y + P.A[2] * ep.z * ep.z) * inA);
-    const G C12 = (G)((P.A[0] * ep.x * s2.x + P.A[1] * ep.y * s2.y + P.A[2] * ep.z * s2.z) * inA);
-    const G C22 = (G)((P.A[0] * s2.x * s2.x + P.A[1] * s2.y * s2.y + P.A[2] * s2.z * s2.z) * inA);
-
-    // Snell (Eq. 4), FP64
-    const double mrel = n_oth / n_cur;
-    const double st2 = 1.0 - ci * ci;
-    const double ct2 = 1.0 - st2 / (mrel * mrel);
-    const bool tir = ct2 < 0.0;
-    V dr = axpy(-2.0 * dn, nh, d);
-    const double gr = -dn;  // n . k_hat of the reflected wave
-    double ct = 0.0, gt = 0.0;
-    V dt = d;
-    if (!tir) {
-      ct = sqrt_d(ct2);
-      const double sct = sgn * ct, im = rcp_d(mrel);
-      dt = mk3((d.x - dn * nh.x) * im + sct * nh.x, (d.y - dn * nh.y) * im + sct * nh.y,
-               (d.z - dn * nh.z) * im + sct * nh.z);
-      gt = dot(dt, nh);
-    }
-    // Fresnel (Eq. 8) in units of n_cur k, in G
-    cx<G> rp, rl, tp, tl;
-    {
-      const G cig = (G)ci, mg = (G)mrel, m2 = mg * mg;
-      if (!tir) {
-        const G b = (G)(mrel * ct);  // k_rn / (n_cur k)
-        const G inv1 = rcp_t(cig + b), inv2 = rcp_t(m2 * cig + b);
-        rp.re = (cig - b) * inv1;  rp.im = 0;
-        rl.re = (m2 * cig - b) * inv2;  rl.im = 0;
-        tp.re = 2 * cig * inv1;  tp.im = 0;
-        tl.re = 2 * mg * cig * inv2;  tl.im = 0;
-      } else {
-        // evanescent transmitted wave, k_rn = +i n_cur k sqrt(sin^2 - m_rel^2)
-        const G beta = (G)sqrt(st2 - mrel * mrel);
-        cx<G> a1, b1, a2, b2;
-        a1.re = cig; a1.im = -beta; b1.re = cig; b1.im = beta;
-        a2.re = m2 * cig; a2.im = -beta; b2.re = m2 * cig; b2.im = beta;
-        rp = cdiv(a1, b1);
-        rl = cdiv(a2, b2);
-        tp.re = tp.im = tl.re = tl.im = 0;
-      }
-    }
-
-    // wavefront equation (Eq. 3) with diagonal projections P = diag(1, n.k_hat):
-    //   k' P' Q' P' = k_i P_i Q~ P_i + C n.(k' - k_i)
-    const G ki = (G)n_cur * kk;
-    const G dng = (G)dn;
-    const G M11i = ki * t11, M12i = ki * dng * t12, M22i = ki * dng * dng * t22;
-
-    // ---- emission of an order, if this interaction emits one ----
-    int p_emit = -1;
-    bool emit_t = false;
-    if (q == 1) p_emit = 0;  // external reflection
-    else if (!tir) { p_emit = q - 1; emit_t = true; }
-    if (p_emit >= P.p_min && p_emit <= P.p_max) {
-      const double kod = emit_t ? n_oth * P.k : n_cur * P.k;
-      const double god = emit_t ? gt : gr;
-      const G ko = (G)kod;
-      const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
-      const V dout = emit_t ? dt : dr;
-      const G inko = rcp_t(ko), igo = (G)rcp_d(god);
-      const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
-      double Q11 = (double)(a11 * inko);
-      double Q12 = (double)(a12 * inko * igo);
-      double Q22 = (double)(a22 * inko * igo * igo);
-      double detQ = Q11 * Q22 - Q12 * Q12;
-      int nft = nf + neg_eigs(Q11, Q12, Q22);
-      double e_amplif = amplif;
-      {
-        // cancellation in det of the Eq. 3 sum M = k_i P Q~ P + w C: a flat exit
-        // wavefront (far-field caustic) makes det M small against its terms;
-        // first-order bound of the relative error of det M for entry-wise errors
-        double t11a = fabs((double)M11i) + fabs((double)(w * C11)), t12a = fabs((double)M12i) + fabs((double)(w * C12));
-        double t22a = fabs((double)M22i) + fabs((double)(w * C22));
-        double b11 = a11, b12 = a12, b22 = a22;
-        e_amplif = fmax(e_amplif, (t11a * fabs(b22) + fabs(b11) * t22a + 2.0 * t12a * fabs(b12)) /
-                                      fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
-      }
-      double amp = sqrt_d(D * rcp_d(fabs(detQ)));
-      v3<G> ul;
-      V epo = cross(dout, ep);  // e_par' of the outgoing wave
-      // lab vectors: direction rounded once to G; the phase uses exactly that vector
-      const V dl64 = mk3(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z, R[3] * dout.x + R[4] * dout.y + R[5] * dout.z,
-                         R[6] * dout.x + R[7] * dout.y + R[8] * dout.z);
-      v3<G> dl = mk3<G>((G)dl64.x, (G)dl64.y, (G)dl64.z);
-      V ul64 = dl64;
-      V rl_lab = mk3(R[0] * r.x + R[1] * r.y + R[2] * r.z, R[3] * r.x + R[4] * r.y + R[5] * r.z,
-                     R[6] * r.x + R[7] * r.y + R[8] * r.z);
-      double phase = opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
-      ul = dl;
-      if (GEN && P.robs > 0.0) {
-        // finite observation radius: continue the ray by d_M to M on the
-        // sphere; the last leg's divergence factor is 1 / det(I + d_M Q')
-        // d_M - R without the cancellation of the plain difference at large R
-        const double drr = dot(dout, r);
-        const double rp2 = dot(r, r) - drr * drr;
-        const double dMR = -drr - rp2 * rcp_d(sqrt_d(P.robs * P.robs - rp2) + P.robs);
-        const double dM = P.robs + dMR;
-        const double g11 = 1.0 + dM * Q11, g12 = dM * Q12, g22 = 1.0 + dM * Q22;
-        const double detG = g11 * g22 - g12 * g12;
-        nft = nf + neg_eigs(g11, g12, g22);
-        amp = P.robs * sqrt_d(D * rcp_d(fabs(detG)));
-        // Q' carries the error amplified so far; det(I + d_M Q') scales its
-        // entries' rounding by half its entry-wise condition.  Far from the
-        // particle that tends to det Q''s own condition, which e_amplif
-        // already holds, so only the excess over it multiplies e_amplif (it
-        // grows where a caustic meets the observation sphere)
-        const double cg = 0.5 * (fabs(dM * Q11) * fabs(g22) + fabs(g11) * fabs(dM * Q22) + 2.0 * dM * dM * Q12 * Q12) /
-                          fmax(fabs(detG), 1e-300);
-        const double cq = (fabs(Q11 * Q22) + Q12 * Q12) / fmax(fabs(detQ), 1e-300);
-        e_amplif *= fmax(1.0, cg / cq);
-        phase = opl + P.k * dMR - nft * 1.5707963267948966;
-        const V Mb = mk3(r.x + dM * dout.x, r.y + dM * dout.y, r.z + dM * dout.z);
-        const double ir = rcp_d(P.robs);
-        const V u = mk3((R[0] * Mb.x + R[1] * Mb.y + R[2] * Mb.z) * ir, (R[3] * Mb.x + R[4] * Mb.y + R[5] * Mb.z) * ir,
-                        (R[6] * Mb.x + R[7] * Mb.y + R[8] * Mb.z) * ir);
-        ul = mk3<G>((G)u.x, (G)u.y, (G)u.z);
-        ul64 = u;
-        // refer the phase to the rounded direction, as the far field does: the
-        // phase gained from R u to the sphere's point along (G)u (exact, also
-        // where d_M vanishes)
-        if (sizeof(G) < 8)
-          phase += near_carry(P.k * P.robs, P.k * rl_lab.x, P.k * rl_lab.y, P.k * rl_lab.z, u.x, u.y, u.z,
-                              (double)ul.x, (double)ul.y, (double)ul.z);
-      }
-      G sph, cph;
-      if (sizeof(G) == 8) sincos_t((G)phase, &sph, &cph);
-      else sincos_t((G)reduce_2pi(phase), &sph, &cph);
-      G ga = (G)amp;
-      cx<G> pa;
-      pa.re = ga * cph; pa.im = ga * sph;
-      v3<G> epl = mk3<G>((G)(R[0] * ep.x + R[1] * ep.y + R[2] * ep.z), (G)(R[3] * ep.x + R[4] * ep.y + R[5] * ep.z),
-                         (G)(R[6] * ep.x + R[7] * ep.y + R[8] * ep.z));
-      v3<G> eql = mk3<G>((G)(R[0] * epo.x + R[1] * epo.y + R[2] * epo.z),
-                         (G)(R[3] * epo.x + R[4] * epo.y + R[5] * epo.z),
-                         (G)(R[6] * epo.x + R[7] * epo.y + R[8] * epo.z));
-      cx<G> c0 = emit_t ? tp : rp, c1 = emit_t ? tl : rl;
-      Emission<G> e;
-      e.slot = p_emit - P.p_min;
-      e.nf = nft;
-      e.det_neg = detQ < 0.0;
-      e.dir = dl;
-      e.obs = ul;
-      e.obs64 = ul64;
-      e.rexit = rl_lab;
-      e.phase = phase;
-      e.amp = amp;
-      e.amplif = e_amplif;
-      e.drift = drift;
-      for (int k = 0; k < 2; ++k) {
-        cx<G> jp = cmul(pa, cmul(c0, Jl[0][k]));
-        cx<G> jq = cmul(pa, cmul(c1, Jl[1][k]));
-        e.f[k][0].re = jp.re * epl.x + jq.re * eql.x; e.f[k][0].im = jp.im * epl.x + jq.im * eql.x;
-        e.f[k][1].re = jp.re * epl.y + jq.re * eql.y; e.f[k][1].im = jp.im * epl.y + jq.im * eql.y;
-        e.f[k][2].re = jp.re * epl.z + jq.re * eql.z; e.f[k][2].im = jp.im * epl.z + jq.im * eql.z;
-      }
-      sink.emit(e);
-    }
-    if (q == P.p_max + 1) break;
-
-    // ---- continuing branch: transmitted at q = 1, reflected afterwards ----
-    const bool cont_t = (q == 1);
-    if (cont_t && tir) break;
-    const double kod = cont_t ? n_oth * P.k : n_cur * P.k;
-    const double god = cont_t ? gt : gr;
-    const G ko = (G)kod;
-    const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
-    const G inko = rcp_t(ko), igo = (G)rcp_d(god);
-    const G Q11 = (M11i + w * C11) * inko;
-    const G Q12 = (M12i + w * C12) * inko * igo;
-    const G Q22 = (M22i + w * C22) * inko * igo * igo;
-    cx<G> c0 = cont_t ? tp : rp, c1 = cont_t ? tl : rl;
-    for (int k = 0; k < 2; ++k) {
-      J[0][k] = cmul(c0, Jl[0][k]);
-      J[1][k] = cmul(c1, Jl[1][k]);
-    }
-    d = cont_t ? dt : dr;
-    u1 = ep;
-    u2 = cross(d, ep);
-    if (cont_t) { n_cur = n_oth; n_oth = 1.0; }
-
-    // free propagation along the chord (FP64): G = I + L Q, Q <- Q G^-1
-    const double L = -2.0 * (P.A[0] * d.x * r.x + P.A[1] * d.y * r.y + P.A[2] * d.z * r.z) /
-                     (P.A[0] * d.x * d.x + P.A[1] * d.y * d.y + P.A[2] * d.z * d.z);
-    double g11 = 1.0 + L * (double)Q11, g12 = L * (double)Q12, g22 = 1.0 + L * (double)Q22;
-    double detG = g11 * g22 - g12 * g12;
-    {
-      double mid = 0.5 * (g11 + g22), rad = sqrt(0.25 * (g11 - g22) * (g11 - g22) + g12 * g12);
-      drift *= fmax(1.0, fmax(fabs(mid + rad), fabs(mid - rad)));
-    }
-    // cancellation in det(I + L Q) (relative errors enter through L Q only)
-    amplif = fmax(amplif, (fabs(L * (double)Q11) * fabs(g22) + fabs(g11) * fabs(L * (double)Q22) + 2.0 * g12 * g12) /
-                              fmax(fabs(detG), 1e-300));
-    D *= rcp_d(fabs(detG));
-    nf += neg_eigs(g11, g12, g22);
-    double idg = rcp_d(detG);
-    // Q G^-1 with G^-1 = [[g22, -g12], [-g12, g11]] / det G  (symmetric result)
-    double n11 = ((double)Q11 * g22 - (double)Q12 * g12) * idg;
-    double n12 = ((double)Q12 * g11 - (double)Q11 * g12) * idg;
-    double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
-    q11 = (G)n11; q12 = (G)n12; q22 = (G)n22;
-    opl += n_cur * P.k * L;
-    if (GEN && n_cur != 1.0 && P.m_im > 0.0) {
-      // weak absorption along the internal segment
-      const G att = (G)exp(-P.k * P.m_im * L);
-      for (int k = 0; k < 2; ++k)
-        for (int a = 0; a < 2; ++a) { J[a][k].re *= att; J[a][k].im *= att; }
-    }
-    r = axpy(L, d, r);
+  int status = 0;
+  // outward normal and incidence-plane basis (FP64)
+  V Ar = mk3(P.A[0] * s.r.x, P.A[1] * s.r.y, P.A[2] * s.r.z);
+  const double inA = rsq_d(dot(Ar, Ar));
+  V nh = scl(inA, Ar);
+  const double dn = dot(s.d, nh);  // n . k_hat (signed)
+  const double sgn = dn > 0 ? 1.0 : -1.0;
+  const double ci = sgn * dn;    // cos(theta_i)
+  V c = scl(sgn, cross(s.d, nh));  // d x nu
+  const double c2 = dot(c, c);
+  V ep = c2 < 1e-24 ? s.u1 : scl(rsq_d(c2), c);
+  // rotate the carried state into (e_perp, e_par): e_perp = cs u1 + sn u2
+  const G cs = (G)dot(ep, s.u1), sn = (G)dot(ep, s.u2);
+  cx<G> Jl[2][2];
+  for (int k = 0; k < 2; ++k) {
+    Jl[0][k].re = cs * s.J[0][k].re + sn * s.J[1][k].re;
+    Jl[0][k].im = cs * s.J[0][k].im + sn * s.J[1][k].im;
+    Jl[1][k].re = -sn * s.J[0][k].re + cs * s.J[1][k].re;
+    Jl[1][k].im = -sn * s.J[0][k].im + cs * s.J[1][k].im;
   }
+  G t11 = cs * cs * s.q11 + 2 * cs * sn * s.q12 + sn * sn * s.q22;
+  G t12 = (cs * cs - sn * sn) * s.q12 + cs * sn * (s.q22 - s.q11);
+  G t22 = sn * sn * s.q11 - 2 * cs * sn * s.q12 + cs * cs * s.q22;
+
+  // surface curvature in (s1, s2) = (e_perp, n x e_perp), shape operator of r^T A r = 1
+  V s2 = cross(nh, ep);
+  const G C11 = (G)((P.A[0] * ep.x * ep.x + P.A[1] * ep.y * ep.y + P.A[2] * ep.z * ep.z) * inA);
+  const G C12 = (G)((P.A[0] * ep.x * s2.x + P.A[1] * ep.y * s2.y + P.A[2] * ep.z * s2.z) * inA);
+  const G C22 = (G)((P.A[0] * s2.x * s2.x + P.A[1] * s2.y * s2.y + P.A[2] * s2.z * s2.z) * inA);
+
+  // Snell (Eq. 4), FP64
+  const double n_cur = s.n_cur, n_oth = s.n_oth;
+  const double mrel = n_oth / n_cur;
+  const double st2 = 1.0 - ci * ci;
+  const double ct2 = 1.0 - st2 / (mrel * mrel);
+  const bool tir = ct2 < 0.0;
+  V dr = axpy(-2.0 * dn, nh, s.d);
+  const double gr = -dn;  // n . k_hat of the reflected wave
+  double ct = 0.0, gt = 0.0;
+  V dt = s.d;
+  if (!tir) {
+    ct = sqrt_d(ct2);
+    const double sct = sgn * ct, im = rcp_d(mrel);
+    dt = mk3((s.d.x - dn * nh.x) * im + sct * nh.x, (s.d.y - dn * nh.y) * im + sct * nh.y,
+             (s.d.z - dn * nh.z) * im + sct * nh.z);
+    gt = dot(dt, nh);
+  }
+  // Fresnel (Eq. 8) in units of n_cur k, in G
+  cx<G> rp, rl, tp, tl;
+  {
+    const G cig = (G)ci, mg = (G)mrel, m2 = mg * mg;
+    if (!tir) {
+      const G b = (G)(mrel * ct);  // k_rn / (n_cur k)
+      const G inv1 = rcp_t(cig + b), inv2 = rcp_t(m2 * cig + b);
+      rp.re = (cig - b) * inv1;  rp.im = 0;
+      rl.re = (m2 * cig - b) * inv2;  rl.im = 0;
+      tp.re = 2 * cig * inv1;  tp.im = 0;
+      tl.re = 2 * mg * cig * inv2;  tl.im = 0;
+    } else {
+      // evanescent transmitted wave, k_rn = +i n_cur k sqrt(sin^2 - m_rel^2)
+      const G beta = (G)sqrt(st2 - mrel * mrel);
+      cx<G> a1, b1, a2, b2;
+      a1.re = cig; a1.im = -beta; b1.re = cig; b1.im = beta;
+      a2.re = m2 * cig; a2.im = -beta; b2.re = m2 * cig; b2.im = beta;
+      rp = cdiv(a1, b1);
+      rl = cdiv(a2, b2);
+      tp.re = tp.im = tl.re = tl.im = 0;
+    }
+  }
+
+  // wavefront equation (Eq. 3) with diagonal projections P = diag(1, n.k_hat):
+  //   k' P' Q' P' = k_i P_i Q~ P_i + C n.(k' - k_i)
+  const G ki = (G)n_cur * kk;
+  const G dng = (G)dn;
+  const G M11i = ki * t11, M12i = ki * dng * t12, M22i = ki * dng * dng * t22;
+
+  // ---- emission of an order, if this interaction emits one ----
+  int p_emit = -1;
+  bool emit_t = false;
+  if (q == 1) p_emit = 0;  // external reflection
+  else if (!tir) { p_emit = q - 1; emit_t = true; }
+  if (p_emit >= P.p_min && p_emit <= P.p_max) {
+    status |= 1;
+    const double kod = emit_t ? n_oth * P.k : n_cur * P.k;
+    const double god = emit_t ? gt : gr;
+    const G ko = (G)kod;
+    const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
+    const V dout = emit_t ? dt : dr;
+    const G inko = rcp_t(ko), igo = (G)rcp_d(god);
+    const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
+    double Q11 = (double)(a11 * inko);
+    double Q12 = (double)(a12 * inko * igo);
+    double Q22 = (double)(a22 * inko * igo * igo);
+    double detQ = Q11 * Q22 - Q12 * Q12;
+    int nft = s.nf + neg_eigs(Q11, Q12, Q22);
+    double e_amplif = s.amplif;
+    {
+      // cancellation in det of the Eq. 3 sum M = k_i P Q~ P + w C: a flat exit
+      // wavefront (far-field caustic) makes det M small against its terms;
+      // first-order bound of the relative error of det M for entry-wise errors
+      double t11a = fabs((double)M11i) + fabs((double)(w * C11)), t12a = fabs((double)M12i) + fabs((double)(w * C12));
+      double t22a = fabs((double)M22i) + fabs((double)(w * C22));
+      double b11 = a11, b12 = a12, b22 = a22;
+      e_amplif = fmax(e_amplif, (t11a * fabs(b22) + fabs(b11) * t22a + 2.0 * t12a * fabs(b12)) /
+                                    fmax(fabs(b11 * b22 - b12 * b12), 1e-300));
+    }
+    double amp = sqrt_d(s.D * rcp_d(fabs(detQ)));
+    v3<G> ul;
+    V epo = cross(dout, ep);  // e_par' of the outgoing wave
+    // lab vectors: direction rounded once to G; the phase uses exactly that vector
+    const V dl64 = mk3(R[0] * dout.x + R[1] * dout.y + R[2] * dout.z, R[3] * dout.x + R[4] * dout.y + R[5] * dout.z,
+                       R[6] * dout.x + R[7] * dout.y + R[8] * dout.z);
+    v3<G> dl = mk3<G>((G)dl64.x, (G)dl64.y, (G)dl64.z);
+    V ul64 = dl64;
+    V rl_lab = mk3(R[0] * s.r.x + R[1] * s.r.y + R[2] * s.r.z, R[3] * s.r.x + R[4] * s.r.y + R[5] * s.r.z,
+                   R[6] * s.r.x + R[7] * s.r.y + R[8] * s.r.z);
+    double phase = s.opl - P.k * dot(cvt<double>(dl), rl_lab) - nft * 1.5707963267948966;
+    ul = dl;
+    if (GEN && P.robs > 0.0) {
+      // finite observation radius: continue the ray by d_M to M on the
+      // sphere; the last leg's divergence factor is 1 / det(I + d_M Q')
+      // d_M - R without the cancellation of the plain difference at large R
+      const double drr = dot(dout, s.r);
+      const double rp2 = dot(s.r, s.r) - drr * drr;
+      const double dMR = -drr - rp2 * rcp_d(sqrt_d(P.robs * P.robs - rp2) + P.robs);
+      const double dM = P.robs + dMR;
+      const double g11 = 1.0 + dM * Q11, g12 = dM * Q12, g22 = 1.0 + dM * Q22;
+      const double detG = g11 * g22 - g12 * g12;
+      nft = s.nf + neg_eigs(g11, g12, g22);
+      amp = P.robs * sqrt_d(s.D * rcp_d(fabs(detG)));
+      // Q' carries the error amplified so far; det(I + d_M Q') scales its
+      // entries' rounding by half its entry-wise condition.  Far from the
+      // particle that tends to det Q''s own condition, which e_amplif
+      // already holds, so only the excess over it multiplies e_amplif (it
+      // grows where a caustic meets the observation sphere)
+      const double cg = 0.5 * (fabs(dM * Q11) * fabs(g22) + fabs(g11) * fabs(dM * Q22) + 2.0 * dM * dM * Q12 * Q12) /
+                        fmax(fabs(detG), 1e-300);
+      const double cq = (fabs(Q11 * Q22) + Q12 * Q12) / fmax(fabs(detQ), 1e-300);
+      e_amplif *= fmax(1.0, cg / cq);
+      phase = s.opl + P.k * dMR - nft * 1.5707963267948966;
+      const V Mb = mk3(s.r.x + dM * dout.x, s.r.y + dM * dout.y, s.r.z + dM * dout.z);
+      const double ir = rcp_d(P.robs);
+      const V u = mk3((R[0] * Mb.x + R[1] * Mb.y + R[2] * Mb.z) * ir, (R[3] * Mb.x + R[4] * Mb.y + R[5] * Mb.z) * ir,
+                      (R[6] * Mb.x + R[7] * Mb.y + R[8] * Mb.z) * ir);
+      ul = mk3<G>((G)u.x, (G)u.y, (G)u.z);
+      ul64 = u;
+      // refer the phase to the rounded direction, as the far field does: the
+      // phase gained from R u to the sphere's point along (G)u (exact, also
+      // where d_M vanishes)
+      if (sizeof(G) < 8)
+        phase += near_carry(P.k * P.robs, P.k * rl_lab.x, P.k * rl_lab.y, P.k * rl_lab.z, u.x, u.y, u.z,
+                            (double)ul.x, (double)ul.y, (double)ul.z);
+    }
+    G sph, cph;
+    if (sizeof(G) == 8) sincos_t((G)phase, &sph, &cph);
+    else sincos_t((G)reduce_2pi(phase), &sph, &cph);
+    G ga = (G)amp;
+    cx<G> pa;
+    pa.re = ga * cph; pa.im = ga * sph;
+    v3<G> epl = mk3<G>((G)(R[0] * ep.x + R[1] * ep.y + R[2] * ep.z), (G)(R[3] * ep.x + R[4] * ep.y + R[5] * ep.z),
+                       (G)(R[6] * ep.x + R[7] * ep.y + R[8] * ep.z));
+    v3<G> eql = mk3<G>((G)(R[0] * epo.x + R[1] * epo.y + R[2] * epo.z),
+                       (G)(R[3] * epo.x + R[4] * epo.y + R[5] * epo.z),
+                       (G)(R[6] * epo.x + R[7] * epo.y + R[8] * epo.z));
+    cx<G> c0 = emit_t ? tp : rp, c1 = emit_t ? tl : rl;
+    Emission<G> e;
+    e.slot = p_emit - P.p_min;
+    e.nf = nft;
+    e.det_neg = detQ < 0.0;
+    e.dir = dl;
+    e.obs = ul;
+    e.obs64 = ul64;
+    e.rexit = rl_lab;
+    e.phase = phase;
+    e.amp = amp;
+    e.amplif = e_amplif;
+    e.drift = s.drift;
+    for (int k = 0; k < 2; ++k) {
+      cx<G> jp = cmul(pa, cmul(c0, Jl[0][k]));
+      cx<G> jq = cmul(pa, cmul(c1, Jl[1][k]));
+      e.f[k][0].re = jp.re * epl.x + jq.re * eql.x; e.f[k][0].im = jp.im * epl.x + jq.im * eql.x;
+      e.f[k][1].re = jp.re * epl.y + jq.re * eql.y; e.f[k][1].im = jp.im * epl.y + jq.im * eql.y;
+      e.f[k][2].re = jp.re * epl.z + jq.re * eql.z; e.f[k][2].im = jp.im * epl.z + jq.im * eql.z;
+    }
+    sink.emit(e);
+  }
+  if (q == P.p_max + 1) return status;
+
+  // ---- continuing branch: transmitted at q = 1, reflected afterwards ----
+  const bool cont_t = (q == 1);
+  if (cont_t && tir) return status;
+  const double kod = cont_t ? n_oth * P.k : n_cur * P.k;
+  const double god = cont_t ? gt : gr;
+  const G ko = (G)kod;
+  const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
+  const G inko = rcp_t(ko), igo = (G)rcp_d(god);
+  const G Q11 = (M11i + w * C11) * inko;
+  const G Q12 = (M12i + w * C12) * inko * igo;
+  const G Q22 = (M22i + w * C22) * inko * igo * igo;
+  cx<G> c0 = cont_t ? tp : rp, c1 = cont_t ? tl : rl;
+  for (int k = 0; k < 2; ++k) {
+    s.J[0][k] = cmul(c0, Jl[0][k]);
+    s.J[1][k] = cmul(c1, Jl[1][k]);
+  }
+  const V d = cont_t ? dt : dr;
+  s.d = d;
+  s.u1 = ep;
+  s.u2 = cross(d, ep);
+  if (cont_t) { s.n_cur = n_oth; s.n_oth = 1.0; }
+
+  // free propagation along the chord (FP64): G = I + L Q, Q <- Q G^-1
+  const V r = s.r;
+  const double L = -2.0 * (P.A[0] * d.x * r.x + P.A[1] * d.y * r.y + P.A[2] * d.z * r.z) /
+                   (P.A[0] * d.x * d.x + P.A[1] * d.y * d.y + P.A[2] * d.z * d.z);
+  double g11 = 1.0 + L * (double)Q11, g12 = L * (double)Q12, g22 = 1.0 + L * (double)Q22;
+  double detG = g11 * g22 - g12 * g12;
+  {
+    double mid = 0.5 * (g11 + g22), rad = sqrt(0.25 * (g11 - g22) * (g11 - g22) + g12 * g12);
+    s.drift *= fmax(1.0, fmax(fabs(mid + rad), fabs(mid - rad)));
+  }
+  // cancellation in det(I + L Q) (relative errors enter through L Q only)
+  s.amplif = fmax(s.amplif, (fabs(L * (double)Q11) * fabs(g22) + fabs(g11) * fabs(L * (double)Q22) + 2.0 * g12 * g12) /
+                                fmax(fabs(detG), 1e-300));
+  s.D *= rcp_d(fabs(detG));
+  s.nf += neg_eigs(g11, g12, g22);
+  double idg = rcp_d(detG);
+  // Q G^-1 with G^-1 = [[g22, -g12], [-g12, g11]] / det G  (symmetric result)
+  double n11 = ((double)Q11 * g22 - (double)Q12 * g12) * idg;
+  double n12 = ((double)Q12 * g11 - (double)Q11 * g12) * idg;
+  double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
+  s.q11 = (G)n11; s.q12 = (G)n12; s.q22 = (G)n22;
+  s.opl += s.n_cur * P.k * L;
+  if (GEN && s.n_cur != 1.0 && P.m_im > 0.0) {
+    // weak absorption along the internal segment
+    const G att = (G)exp(-P.k * P.m_im * L);
+    for (int k = 0; k < 2; ++k)
+      for (int a = 0; a < 2; ++a) { s.J[a][k].re *= att; s.J[a][k].im *= att; }
+  }
+  s.r = axpy(L, d, r);
+  return status | 2;
+}
+
+template <typename G, bool GEN = true, typename Sink>
+__device__ void trace_ray(const ParticleConst& P, int ix, int iy, Sink& sink) {
+  RayState<G> s;
+  if (!ray_init(P, ix, iy, s)) return;
+  for (int q = 1; q <= P.p_max + 1; ++q)
+    if (!(ray_interact<G, GEN>(P, q, s, sink) & 2)) break;
 }
 
 }  // namespace rtw

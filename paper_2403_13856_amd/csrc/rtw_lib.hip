@@ -1,11 +1,16 @@
 // rtw_lib.hip -- librtw.so: the C ABI of include/rtw.h over the gfx950 kernels.
 //
 // rtw_farfield runs, on the caller's stream:
-//   k_setup       node tables (sin/cos of the node angles) and pool reset
-//   k_trace<G>    one thread per incident ray: Eqs. 3-10, emission records (SoA)
-//   k_raster<G>   one thread per (order, grid quad): triangle -> node hits
-//   k_node_sum<G> one thread per node: ordered sum of its hits -> far field
+//   k_setup         node tables (sin/cos of the node angles) and pool reset
+//   k_trace_tiles   persistent, one thread per incident ray: Eqs. 3-10, emission records
+//   k_retrace64     (mixed) FP64 re-trace of the rays ill-conditioned in FP32
+//   k_raster<G>     one thread per (order, grid quad): triangle -> node hits
+//   k_scan          node counts -> node ranges
+//   k_store_hits<G> one thread per hit: interpolated contribution, in node order
+//   k_node_sum<G>   one thread per node: ordered sum of its hits -> far field
 // G = double (RTW_FP64) or float (RTW_MIXED, with FP64 path/phase/Jacobian).
+// rtw_batch with rtw_batch_opts.fused replaces trace to hit store by k_fused
+// (rtw_fused.hpp), then k_scan, k_scatter and k_node_sum.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +25,7 @@
 #include "../../include/rtw.h"
 #include "rtw_device.hpp"
 #include "rtw_raster.hpp"
+#include "rtw_fused.hpp"
 
 using namespace rtw;
 
@@ -203,6 +209,7 @@ enum : int {
   C_FP64_TOTAL,    // rays re-traced in FP64 over the call
   C_HITS,          // node hits over the call (64-bit, two slots: must be 8-byte aligned)
   C_HITS_HI,
+  C_FUSED_HITS,    // hits of the current chunk on the fused path (its pool counters count slots)
   C_COUNT
 };
 static_assert(C_HITS % 2 == 0, "the 64-bit hit total needs an 8-byte aligned slot");
@@ -289,6 +296,125 @@ __global__ void __launch_bounds__(256) k_retrace64(const BatchDev B, const Recor
   }
 }
 
+// FP64 re-trace of one ray inside k_fused, into its scratch records.
+template <bool GEN>
+__device__ __forceinline__ void fused_retrace(const ParticleConst& P, int ix, int iy, LRec* rb, int n_ord,
+                                              double kappa) {
+  for (int o = 0; o < n_ord; ++o) rb[o].flags = 0;
+  ScratchSink sk{rb, P.k, kappa, P.n_pol};
+  trace_ray<double, GEN>(P, ix, iy, sk);
+}
+
+// The mixed-path far field of plain particles (or, GEN, of those observed at
+// a finite radius or absorbing) in one persistent kernel: blocks take tiles
+// of 64 x 4 steps rays from the chunk's queue; per step, each interaction
+// that emits an order is followed by the rasterisation of that order's quads
+// of the step (fused_raster), rays ill-conditioned in FP32 being re-traced in
+// FP64 by the block.  carry: dynamic LDS, n_ord x 64 records (the last ray
+// row of the previous step, per order slot).
+template <bool GEN>
+__global__ void __launch_bounds__(256, FUSED_BPC)
+    k_fused(const BatchDev B, const NodeGrid ng, const FusedPool fp, unsigned* queue, const int steps,
+            const double margin) {
+  __shared__ FusedShared sh;
+  extern __shared__ LRec carry[];
+  const int tid = threadIdx.x, lane = tid & 63, row = tid >> 6;
+  const long n_items = B.tile_off[B.n] - B.tile_base;
+  const AxisFast axt = axis_fast(ng.seg_t, ng.n_theta), axp = axis_fast(ng.seg_p, ng.n_phi);
+  LRec* scratch = fp.scratch + (long)blockIdx.x * 256 * B.n_ord;
+  const int QH = FUSED_ROWS * steps - 1;  // quad rows per tile
+  // the wave's run of hit-pool slots (empty: the first hit takes a run)
+  SlotRun run;
+  run.part = (int)(((long)blockIdx.x * FUSED_ROWS + row) % NPART);
+  run.next = run.end = 0;
+  if (tid == 0) sh.n_hit = 0;
+  for (;;) {
+    if (tid == 0) sh.item = (long)atomicAdd(queue, 1u);
+    __syncthreads();
+    const long item = sh.item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int p = __builtin_amdgcn_readfirstlane(find_part(B.tile_off, B.n, B.tile_base, item));
+    const ParticleConst P = load_uniform(B.P + p);
+    if (GEN != needs_general_trace(P)) continue;
+    const int N = P.N;
+    const int tiles_x = (N - 2) / 63 + 1;
+    const long local = item - (B.tile_off[p] - B.tile_base);
+    const int sy = (int)(local / tiles_x), sx = (int)(local - (long)sy * tiles_x);
+    FusedStep st;
+    st.N = N;
+    st.part = p;
+    st.col0 = 63 * sx;
+    st.nq = (long)(N - 1) * (N - 1);
+    st.node0 = p * ng.n_theta * ng.n_phi;
+    const int row0 = QH * sy;
+    const double kappa = P.k * P.robs;
+    for (int k = 0; k < steps; ++k) {
+      const int r0 = row0 + FUSED_ROWS * k;
+      if (r0 >= N) break;  // block-uniform: the tile's remaining rows lie beyond the grid
+      st.row_top = r0 - 1;
+      st.first = k == 0;
+      const int ix = st.col0 + lane, iy = r0 + row;
+      RayState<float> s;
+      bool alive = ix < N && iy < N && ray_init(P, ix, iy, s);
+      if (tid == 0) sh.n_list = 0;
+      // a step none of whose rays meets the particle: the next step's first
+      // quad row has no valid upper corners
+      // (one vote buffer per step parity: a wave may reach the next step's vote
+      // before another has read this one when the step has no interactions)
+      int* vote = sh.wave_any[k & 1];
+      const unsigned long long wv = __ballot(alive);
+      if (lane == 0) vote[row] = wv != 0ull;
+      __syncthreads();
+      const bool any = vote[0] | vote[1] | vote[2] | vote[3];
+      if (!any) {
+        for (int o = row; o < B.n_ord; o += FUSED_ROWS) carry[o * FUSED_COLS + lane].flags = 0;
+      }
+      bool redo = false;
+      int my_e = 0, done = 0;
+      for (int q = 1; any && q <= P.p_max + 1; ++q) {
+        const int slot = q - 1 - P.p_min;  // order slot emitted at this interaction, if any
+        LdsSink sink{&sh.T[row][lane], P.k, kappa, P.amplif_limit, P.n_pol, false, false};
+        if (alive) alive = (ray_interact<float, GEN>(P, q, s, sink) & 2) != 0;
+        if (slot < 0) continue;  // block-uniform
+        if (sink.need64) {
+          redo = true;
+          alive = false;
+          my_e = atomicAdd(&sh.n_list, 1);
+          sh.list[my_e] = tid;
+        } else if (!sink.wrote && !redo) {
+          sh.T[row][lane].flags = 0;
+        }
+        __syncthreads();
+        // rays listed at this interaction: traced again in FP64, one per
+        // thread.  Every thread parks its own FP32 ray state in global memory
+        // meanwhile, so that the FP64 trace has the registers to itself.
+        const int n_list = sh.n_list;
+        if (n_list > done) {
+          RayState<float>* park = fp.park + (long)blockIdx.x * 256 + tid;
+          *park = s;
+          const int e = done + tid;
+          if (e < n_list) {
+            const int who = sh.list[e];
+            fused_retrace<GEN>(P, st.col0 + (who & 63), r0 + (who >> 6), scratch + (long)e * B.n_ord, B.n_ord, kappa);
+          }
+          if (tid == 0) atomicAdd(fp.n_fp64, (unsigned)(n_list - done));
+          done = n_list;
+          s = *park;
+          __syncthreads();
+        }
+        if (redo) sh.T[row][lane] = scratch[(long)my_e * B.n_ord + slot];
+        __syncthreads();
+        st.slot = slot;
+        fused_raster(sh, carry + slot * FUSED_COLS, ng, axt, axp, fp, st, margin, run);
+        __syncthreads();
+        if (row == FUSED_ROWS - 1) carry[slot * FUSED_COLS + lane] = sh.T[FUSED_ROWS - 1][lane];
+      }
+    }
+  }
+  close_run(fp, run);
+}
+
 // Sink of rtw_trace: FP64 diagnostic records.
 template <typename G>
 struct DiagSink {
@@ -361,7 +487,7 @@ __global__ void __launch_bounds__(256) k_trace_diag(const ParticleConst P, const
 __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg, double* th,
                         double* ph, double* sth, double* cth, double* sph, double* cph, float* tf, unsigned* counter,
                         WsHeader* hdr, WsHeader hv, ParticleConst* meta_P, long* meta_off, int* meta_out,
-                        ParticleConst P1, int tile, int one) {
+                        ParticleConst P1, long items1, int one) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const double D2R = 3.14159265358979323846 / 180.0;
   if (i < n_theta) {
@@ -388,7 +514,7 @@ __global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const d
       meta_P[0] = P1;
       meta_off[0] = 0; meta_off[1] = NN;                    // rays
       meta_off[2] = 0; meta_off[3] = nq;                    // quads
-      meta_off[4] = 0; meta_off[5] = (NN + tile - 1) / tile;  // trace items
+      meta_off[4] = 0; meta_off[5] = items1;                // trace work items
       meta_out[0] = 0;
     }
   }
@@ -434,7 +560,9 @@ __global__ void k_chunk_reset(int* count, long n_nodes_chunk, unsigned* counter)
 }
 
 // End of a chunk: fullest partition (overflow check), hit and FP64 totals.
-__global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter) {
+// On the fused path the partition fills count slots handed out in runs; the
+// chunk's hits are counted apart (and that count is cleared for the next).
+__global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter, int fused) {
   __shared__ unsigned mx[1024];
   __shared__ unsigned long long sm[1024];
   unsigned m = 0;
@@ -455,7 +583,8 @@ __global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter) {
   }
   if (threadIdx.x == 0) {
     atomicMax(&counter[C_NEED], mx[0]);
-    atomicAdd((unsigned long long*)&counter[C_HITS], sm[0]);
+    atomicAdd((unsigned long long*)&counter[C_HITS], fused ? (unsigned long long)counter[C_FUSED_HITS] : sm[0]);
+    counter[C_FUSED_HITS] = 0u;
     atomicAdd(&counter[C_FP64_TOTAL], counter[C_REDO]);
   }
 }
@@ -542,7 +671,7 @@ int check_keys(const rtw_trace_opts* o) {
 // the largest chunk; metadata for every particle of the call.
 struct Layout {
   size_t hdr, counter, th, ph, sth, cth, sph, cph, tf, seg, mP, moff, mout, flags, rr, dir, ang, ph64, head, cursor,
-      bsum, redo, rows, link, contrib, desc, hphi, hnf, total;
+      bsum, redo, rows, fscr, fpark, link, contrib, desc, hphi, hnf, total;
   size_t fixed;          // everything except the hit pool
   size_t bytes_per_hit;  // link + contrib
 };
@@ -555,6 +684,8 @@ struct Shape {
   int max_chunk_parts;  // particles of the largest chunk
   long rows_cap;        // (triangle, row) items of the row list
   int corr;             // RTW_CAUSTIC | RTW_DIFFRACTION
+  int fused;            // the mixed far field by k_fused (no per-ray records in the workspace)
+  long fused_grid;      // blocks of k_fused (its FP64 re-trace scratch is per block)
 };
 
 Layout layout(const Shape& S, long cap_total) {
@@ -562,7 +693,7 @@ Layout layout(const Shape& S, long cap_total) {
   const size_t gs = S.precision == RTW_FP64 ? 8 : 4;
   const size_t rr = S.precision == RTW_FP64 ? sizeof(RayRec<double>) : sizeof(RayRec<float>);
   const long n_nodes = (long)S.n_theta * S.n_phi;
-  const size_t nrec = (size_t)S.n_ord * S.max_chunk_rays;
+  const size_t nrec = S.fused ? 0 : (size_t)S.n_ord * S.max_chunk_rays;  // per-ray record arrays
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
   L.hdr = take(sizeof(WsHeader));
@@ -584,10 +715,14 @@ Layout layout(const Shape& S, long cap_total) {
   L.head = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.cursor = take(4 * (size_t)S.max_chunk_parts * n_nodes);
   L.bsum = take(4 * ((size_t)S.max_chunk_parts * n_nodes / SCAN_BLOCK + 1));
-  L.redo = take(S.precision == RTW_FP64 ? 4 : 4 * (size_t)S.max_chunk_rays);
-  L.rows = take(sizeof(int2) * (size_t)S.rows_cap);
+  L.redo = take(S.precision == RTW_FP64 || S.fused ? 4 : 4 * (size_t)S.max_chunk_rays);
+  L.rows = take(S.fused ? 0 : sizeof(int2) * (size_t)S.rows_cap);
+  L.fscr = take(S.fused ? sizeof(LRec) * 256 * (size_t)S.n_ord * S.fused_grid : 0);
+  L.fpark = take(S.fused ? sizeof(RayState<float>) * 256 * (size_t)S.fused_grid : 0);
   L.fixed = off;
-  const size_t ds = S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>);
+  // a hit: its descriptor (fused: its hit record), then its key and contribution in node order
+  const size_t ds = S.fused ? 16 * (1 + (size_t)S.n_pol)
+                            : (S.precision == RTW_FP64 ? sizeof(HitDesc<double>) : sizeof(HitDesc<float>));
   L.bytes_per_hit = sizeof(int) + gs * 4 * S.n_pol + ds + (caustic ? sizeof(double) + sizeof(int) : 0);
   L.link = take(sizeof(int) * (size_t)cap_total);
   L.contrib = take(gs * 4 * S.n_pol * (size_t)cap_total);
@@ -627,12 +762,34 @@ struct Plan {
 
 constexpr long DEFAULT_RAYS_PER_CHUNK = 1L << 26;
 constexpr double DEFAULT_HITS_PER_NODE = 6.0;
+constexpr int DEFAULT_TILE_STAGED = 1024;  // rays per trace work item
+constexpr int DEFAULT_TILE_FUSED = 2048;   // 64 x 32 rays: 8 steps of 64 x 4
+
+int compute_units();
+
+// Whether a call runs the fused kernel: asked for by the caller, the mixed
+// path, at most FUSED_MAX_ORD orders (the LDS carry), no caustic correction
+// (it needs the rays' FP64 phases at every hit).
+bool use_fused(const rtw_trace_opts* o, bool want) {
+  return want && o->precision == RTW_MIXED && o->p_max - o->p_min + 1 <= FUSED_MAX_ORD &&
+         !(o->corrections & RTW_CAUSTIC);
+}
+
+// Work items (tiles) of one particle: the staged trace's runs of `tile` rays,
+// or the fused kernel's 64 x (tile / 64)-ray tiles, neighbours sharing a ray
+// column or row (63 x (tile / 64 - 1) quads each).
+long tiles_of(int N, int tile, bool fused) {
+  if (!fused) return ((long)N * N + tile - 1) / tile;
+  const int qh = tile / FUSED_COLS - 1;
+  return (long)((N - 2) / (FUSED_COLS - 1) + 1) * ((N - 2) / qh + 1);
+}
 
 // Largest particles first (LPT); chunks are filled greedily up to the ray
 // budget (a larger particle is a chunk of its own).  Every chunk keeps its
 // 32-bit triangle keys and record indices in range.
 int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_incident* inc,
-              const rtw_trace_opts* opts, const rtw_grid* grid, long rays_per_chunk, int tile, Plan& pl) {
+              const rtw_trace_opts* opts, const rtw_grid* grid, long rays_per_chunk, int tile, bool want_fused,
+              Plan& pl) {
   if (n < 1 || !parts || !grid_n) return fail(RTW_ERR_INVALID_ARG, "need n >= 1 particles and grid sides");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -652,6 +809,8 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   if (rays_per_chunk <= 0) rays_per_chunk = DEFAULT_RAYS_PER_CHUNK;
   rays_per_chunk = std::min(rays_per_chunk, key_limit);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return grid_n[a] > grid_n[b]; });
+  const bool fused = use_fused(opts, want_fused);
+  if (tile <= 0) tile = fused ? DEFAULT_TILE_FUSED : DEFAULT_TILE_STAGED;
   pl.tile = tile;
   pl.P.resize(n);
   pl.out_index.resize(n);
@@ -667,7 +826,7 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
     const long NN = (long)grid_n[i] * grid_n[i];
     pl.ray_off[j + 1] = pl.ray_off[j] + NN;
     pl.quad_off[j + 1] = pl.quad_off[j] + (long)(grid_n[i] - 1) * (grid_n[i] - 1);
-    pl.tile_off[j + 1] = pl.tile_off[j] + (NN + tile - 1) / tile;
+    pl.tile_off[j + 1] = pl.tile_off[j] + tiles_of(grid_n[i], tile, fused);
   }
   pl.S.precision = opts->precision;
   pl.S.n_pol = inc->n_pol;
@@ -679,6 +838,8 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   pl.S.max_chunk_parts = 0;
   pl.S.rows_cap = ROWS_CAP;
   pl.S.corr = opts->corrections;
+  pl.S.fused = fused ? 1 : 0;
+  pl.S.fused_grid = 0;
   // node indices of a chunk (chunk particle, theta, phi) are 32-bit: a chunk
   // holds at most (2^31 - 1) / n_nodes particles
   const long n_nodes = (long)grid->n_theta * grid->n_phi;
@@ -690,6 +851,9 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
     pl.chunks.push_back({c0, c1});
     pl.S.max_chunk_rays = std::max(pl.S.max_chunk_rays, pl.ray_off[c1] - pl.ray_off[c0]);
     pl.S.max_chunk_parts = std::max(pl.S.max_chunk_parts, c1 - c0);
+    if (fused)
+      pl.S.fused_grid = std::max(pl.S.fused_grid, std::min<long>(pl.tile_off[c1] - pl.tile_off[c0],
+                                                                 (long)compute_units() * FUSED_BPC));
     c0 = c1;
   }
   return RTW_OK;
@@ -700,7 +864,7 @@ struct Tuning {
 };
 
 Tuning tuning_of(const rtw_tune* t) {
-  Tuning u{1024, 8, CAND_INLINE};
+  Tuning u{0, 8, CAND_INLINE};  // tile 0: the pipeline's default
   if (t) {
     if (t->tile_rays > 0) u.tile = t->tile_rays;
     if (t->blocks_per_cu > 0) u.blocks_per_cu = t->blocks_per_cu;
@@ -724,6 +888,66 @@ int compute_units() {
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
   }
   return cu;
+}
+
+// The kernels of chunk [c0, c1) on the fused path: k_fused (trace,
+// rasterisation and hit contributions), the scan of the node counts, the
+// scatter into node order, the ordered per-node sum, the diffraction term,
+// the pool check.
+int launch_fused(const Plan& pl, const Tuning& tu, int c0, int c1, const BatchDev& B, const NodeGrid& ng,
+                 const HitPool<float>& pool, char* ws, const Layout& L, unsigned* counter, long items, long n_cnodes,
+                 int n_nodes, void* out, int32_t* ncontrib, void* incoh, hipStream_t st) {
+  const Shape& S = pl.S;
+  FusedPool fp;
+  fp.count = pool.count;
+  fp.counter = counter;
+  fp.hits = (V4<float>*)(ws + L.desc);
+  fp.cap_part = pool.cap_part;
+  fp.n_pol = S.n_pol;
+  fp.scratch = (LRec*)(ws + L.fscr);
+  fp.park = (RayState<float>*)(ws + L.fpark);
+  fp.n_fp64 = counter + C_REDO;
+  fp.n_hits = counter + C_FUSED_HITS;
+  const long grid_f = std::min<long>({items, (long)compute_units() * std::min(tu.blocks_per_cu, FUSED_BPC),
+                                      S.fused_grid});
+  const size_t lds = sizeof(LRec) * FUSED_COLS * (size_t)S.n_ord;  // the carry
+  const int steps = pl.tile / (FUSED_COLS * FUSED_ROWS);
+  // the carry with the static LDS exceeds 64 KB: allow the kernels that much
+  // dynamic LDS (once per process; the launch reports any failure)
+  static std::once_flag lds_once;
+  std::call_once(lds_once, [] {
+    const int most = (int)(sizeof(LRec) * FUSED_COLS * FUSED_MAX_ORD);
+    (void)hipFuncSetAttribute((const void*)k_fused<false>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    (void)hipFuncSetAttribute((const void*)k_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+  });
+  { ProfScope ps("k_fused_mixed", st);
+  bool any_gen = false, any_plain = false;
+  for (int c = c0; c < c1; ++c) (needs_general_trace(pl.P[c]) ? any_gen : any_plain) = true;
+  if (any_plain)
+    hipLaunchKernelGGL(k_fused<false>, dim3((unsigned)grid_f), dim3(256), lds, st, B, ng, fp, counter + C_QUEUE,
+                       steps, BOX_MARGIN);
+  if (any_gen)
+    hipLaunchKernelGGL(k_fused<true>, dim3((unsigned)grid_f), dim3(256), lds, st, B, ng, fp, counter + C_QUEUE_GEN,
+                       steps, BOX_MARGIN); }
+  { ProfScope ps("k_scan", st);
+  const long nsb = (n_cnodes + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  int* bsum = (int*)(ws + L.bsum);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_cnodes, pool.cursor, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_cnodes, bsum); }
+  { ProfScope ps("k_scatter", st);
+  const long slots = (long)NPART * pool.cap_part;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, fp, pool); }
+  { ProfScope ps("k_node_sum_mixed", st);
+  hipLaunchKernelGGL((k_node_sum<float, false>), dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool,
+                     n_nodes, S.n_pol, (float*)out, ncontrib, (float*)incoh, 1); }
+  if (S.corr & RTW_DIFFRACTION) {
+    ProfScope ps("k_diffraction", st);
+    hipLaunchKernelGGL(k_diffraction<float>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng,
+                       n_nodes, S.n_pol, (float*)out);
+  }
+  hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter, 1);
+  return RTW_OK;
 }
 
 // Queue every kernel of a call on the stream.  With one_meta the single
@@ -799,7 +1023,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   hipLaunchKernelGGL(k_setup, dim3((unsigned)((setup_n + 255) / 256)), dim3(256), 0, st, grid->n_theta,
                      grid->theta_deg, grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth,
                      (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, tf, counter, (WsHeader*)(ws + L.hdr), hv, mP,
-                     moff, mout, pl.P[0], pl.tile, one_meta ? 1 : 0);
+                     moff, mout, pl.P[0], pl.tile_off[1], one_meta ? 1 : 0);
   hipLaunchKernelGGL(k_axis_segments, dim3(2), dim3(256), 0, st, ng.th, ng.n_theta, ng.ph, ng.n_phi,
                      (AxisSeg*)(ws + L.seg), (AxisSeg*)(ws + L.seg) + 1); }
 
@@ -825,6 +1049,14 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     const long n_cnodes = (long)nc * n_nodes;
     hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_cnodes, C_COUNT) + 255) / 256)), dim3(256),
                        0, st, pool.count, n_cnodes, counter);
+    if constexpr (sizeof(G) == 4) {
+      if (S.fused) {
+        int rc = launch_fused(pl, tu, c0, c1, B, ng, pool, ws, L, counter, items, n_cnodes, n_nodes, out, ncontrib,
+                              incoh, st);
+        if (rc) return rc;
+        continue;
+      }
+    }
     { ProfScope ps(fp64 ? "k_trace_fp64" : "k_trace_mixed", st);
     const long grid_t = std::min<long>(items, (long)cu * tu.blocks_per_cu);
     bool any_gen = false, any_plain = false;
@@ -857,16 +1089,16 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     { ProfScope ps(fp64 ? "k_node_sum_fp64" : "k_node_sum_mixed", st);
     if (pool.phi)
       hipLaunchKernelGGL((k_node_sum<G, true>), dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool,
-                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh);
+                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh, 0);
     else
       hipLaunchKernelGGL((k_node_sum<G, false>), dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, pool,
-                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh); }
+                         n_nodes, S.n_pol, (G*)out, ncontrib, (G*)incoh, 0); }
     if (S.corr & RTW_DIFFRACTION) {
       ProfScope ps("k_diffraction", st);
       hipLaunchKernelGGL(k_diffraction<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng, n_nodes,
                          S.n_pol, (G*)out);
     }
-    hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter);
+    hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter, 0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -972,7 +1204,7 @@ int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* in
   rc = check_keys(opts);
   if (rc) return rc;
   Plan pl;
-  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tuning_of(nullptr).tile, pl);
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tuning_of(nullptr).tile, false, pl);
   if (rc) return rc;
   *bytes = plan_bytes(pl, hits_per_node);
   return RTW_OK;
@@ -990,7 +1222,7 @@ int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_tr
   if (((uintptr_t)workspace & 255) != 0) return fail(RTW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   const Tuning tu = tuning_of(nullptr);
   Plan pl;
-  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, pl);
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, false, pl);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   if (opts->precision == RTW_FP64)
@@ -1010,7 +1242,7 @@ int rtw_farfield_static(const rtw_particle* part, const rtw_incident* inc, const
   if (!out_field) return fail(RTW_ERR_INVALID_ARG, "NULL output");
   const Tuning tu = tuning_of(nullptr);
   Plan pl;
-  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, pl);
+  rc = make_plan(1, part, &opts->grid_n, inc, opts, grid, 0, tu.tile, false, pl);
   if (rc) return rc;
   pl.S.rows_cap = STATIC_ROWS_CAP;
   const size_t need = plan_bytes(pl, 0.0);
@@ -1063,7 +1295,7 @@ int rtw_batch_workspace_size(int n, const rtw_particle* parts, const int* grid_n
   if (!bytes || !opts || !inc) return fail(RTW_ERR_INVALID_ARG, "NULL argument");
   Plan pl;
   int rc = make_plan(n, parts, grid_n, inc, opts, grid, bopts ? (long)bopts->rays_per_chunk : 0,
-                     tuning_of(nullptr).tile, pl);
+                     tuning_of(nullptr).tile, bopts && bopts->fused, pl);
   if (rc) return rc;
   *bytes = plan_bytes(pl, bopts ? bopts->hits_per_node : 0.0);
   return RTW_OK;
@@ -1080,7 +1312,8 @@ int rtw_batch(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
   int rc = check_tuning(tu);
   if (rc) return rc;
   Plan pl;
-  rc = make_plan(n, parts, grid_n, inc, opts, grid, bopts ? (long)bopts->rays_per_chunk : 0, tu.tile, pl);
+  rc = make_plan(n, parts, grid_n, inc, opts, grid, bopts ? (long)bopts->rays_per_chunk : 0, tu.tile,
+                 bopts && bopts->fused, pl);
   if (rc) return rc;
   Layout base = layout(pl.S, 0);
   if (workspace_bytes < base.fixed + base.bytes_per_hit * NPART + 512)

@@ -212,6 +212,60 @@ __device__ __forceinline__ void set_tail(RecTail<float>& t, const v3<double>& d,
   t.pad = 0;
 }
 
+// The compact record of one emission, as the rasteriser and the hit store
+// read it (fields as RayRec and Records), built from an emission traced in E.
+template <typename G>
+struct RecVals {
+  int flags;        // bit0 valid, bits 1..7 nf, bit 8 det_neg
+  G kr[3], dir[3], f[8];
+  RecTail<G> tail;
+  float th, ph;     // (theta, phi) of the stored direction (rad), phi in [0, 2 pi)
+  double ph64;      // the ray's unreduced FP64 phase at the stored direction
+};
+
+template <typename G, typename E>
+__device__ __forceinline__ void record_values(const Emission<E>& e, double k, double kappa, int n_pol,
+                                              RecVals<G>& r) {
+  r.flags = 1 | (e.nf << 1) | (e.det_neg << 8);
+  Dir4<G> dv;
+  dv.x = (G)e.obs.x; dv.y = (G)e.obs.y; dv.z = (G)e.obs.z; dv.pad = (G)0;
+  r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
+  // The field's phase contains -k dir.r_exit and the rasteriser carries it
+  // with k r_exit.(dir - n) using the stored direction, so the two must use
+  // the same direction.  An FP64 emission stored in FP32 records is turned
+  // to the rounded direction: phase += k r_exit.(dir - (G)dir), in FP64
+  // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
+  double cre = 1.0, cim = 0.0;
+  r.ph64 = e.phase;
+  if (sizeof(E) > sizeof(G)) {
+    const double dphi = near_carry(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
+                                   (double)e.obs.y, (double)e.obs.z, (double)dv.x, (double)dv.y, (double)dv.z);
+    sincos(dphi, &cim, &cre);
+    r.ph64 = e.phase + dphi;
+  }
+  v3<double> et, ep;
+  dir_basis((double)dv.x, (double)dv.y, (double)dv.z, et, ep);
+  for (int p = 0; p < 2; ++p) {
+    const double ar = (double)e.f[p][0].re * et.x + (double)e.f[p][1].re * et.y + (double)e.f[p][2].re * et.z;
+    const double ai = (double)e.f[p][0].im * et.x + (double)e.f[p][1].im * et.y + (double)e.f[p][2].im * et.z;
+    const double br = (double)e.f[p][0].re * ep.x + (double)e.f[p][1].re * ep.y;
+    const double bi = (double)e.f[p][0].im * ep.x + (double)e.f[p][1].im * ep.y;
+    const bool live = p < n_pol;
+    r.f[p * 4 + 0] = live ? (G)(ar * cre - ai * cim) : (G)0;
+    r.f[p * 4 + 1] = live ? (G)(ar * cim + ai * cre) : (G)0;
+    r.f[p * 4 + 2] = live ? (G)(br * cre - bi * cim) : (G)0;
+    r.f[p * 4 + 3] = live ? (G)(br * cim + bi * cre) : (G)0;
+  }
+  r.dir[0] = dv.x; r.dir[1] = dv.y; r.dir[2] = dv.z;
+  set_tail(r.tail, e.obs64, dv);
+  const float dx = (float)e.obs.x, dy = (float)e.obs.y, dz = (float)e.obs.z;
+  float phi = atan2f(dy, dx);
+  if (phi < 0.0f) phi += 6.28318531f;
+  if (phi >= 6.28318531f) phi = 0.0f;
+  r.th = atan2f(sqrtf(dx * dx + dy * dy), dz);
+  r.ph = phi;
+}
+
 // Sink writing the compact emission records used by the rasteriser.  In the
 // mixed path an emission whose divergence factor is ill-conditioned for FP32
 // (amplif > amplif_limit) marks the ray for an FP64 re-trace.
@@ -229,47 +283,19 @@ struct RecordSink {
   __device__ void emit(const Emission<E>& e) {
     if (sizeof(E) == 4 && e.amplif > amplif_limit) need64 = true;
     const long at = base + e.slot * NN + id;
-    rec.flags[at] = 1 | (e.nf << 1) | (e.det_neg << 8);
+    RecVals<G> v;
+    record_values(e, k, kappa, rec.n_pol, v);
+    rec.flags[at] = v.flags;
+    if (rec.ph64) rec.ph64[at] = v.ph64;
     RayRec<G> r;
     Dir4<G> dv;
-    dv.x = (G)e.obs.x; dv.y = (G)e.obs.y; dv.z = (G)e.obs.z; dv.pad = (G)0;
-    r.kr[0] = (G)(k * e.rexit.x); r.kr[1] = (G)(k * e.rexit.y); r.kr[2] = (G)(k * e.rexit.z);
-    // The field's phase contains -k dir.r_exit and the rasteriser carries it
-    // with k r_exit.(dir - n) using the stored direction, so the two must use
-    // the same direction.  An FP64 emission stored in FP32 records is turned
-    // to the rounded direction: phase += k r_exit.(dir - (G)dir), in FP64
-    // (k |r_exit| reaches 10^4 rad, the correction ~10^-4 rad).
-    double cre = 1.0, cim = 0.0;
-    if (sizeof(E) > sizeof(G)) {
-      const double dphi = near_carry(kappa, k * e.rexit.x, k * e.rexit.y, k * e.rexit.z, (double)e.obs.x,
-                                     (double)e.obs.y, (double)e.obs.z, (double)dv.x, (double)dv.y, (double)dv.z);
-      sincos(dphi, &cim, &cre);
-      if (rec.ph64) rec.ph64[at] = e.phase + dphi;
-    } else if (rec.ph64) {
-      rec.ph64[at] = e.phase;
-    }
-    v3<double> et, ep;
-    dir_basis((double)dv.x, (double)dv.y, (double)dv.z, et, ep);
-    for (int p = 0; p < 2; ++p) {
-      const double ar = (double)e.f[p][0].re * et.x + (double)e.f[p][1].re * et.y + (double)e.f[p][2].re * et.z;
-      const double ai = (double)e.f[p][0].im * et.x + (double)e.f[p][1].im * et.y + (double)e.f[p][2].im * et.z;
-      const double br = (double)e.f[p][0].re * ep.x + (double)e.f[p][1].re * ep.y;
-      const double bi = (double)e.f[p][0].im * ep.x + (double)e.f[p][1].im * ep.y;
-      const bool live = p < rec.n_pol;
-      r.f[p * 4 + 0] = live ? (G)(ar * cre - ai * cim) : (G)0;
-      r.f[p * 4 + 1] = live ? (G)(ar * cim + ai * cre) : (G)0;
-      r.f[p * 4 + 2] = live ? (G)(br * cre - bi * cim) : (G)0;
-      r.f[p * 4 + 3] = live ? (G)(br * cim + bi * cre) : (G)0;
-    }
-    r.dir[0] = dv.x; r.dir[1] = dv.y; r.dir[2] = dv.z;
-    set_tail(r.tail, e.obs64, dv);
+    dv.x = v.dir[0]; dv.y = v.dir[1]; dv.z = v.dir[2]; dv.pad = (G)0;
+    for (int i = 0; i < 3; ++i) { r.kr[i] = v.kr[i]; r.dir[i] = v.dir[i]; }
+    for (int i = 0; i < 8; ++i) r.f[i] = v.f[i];
+    r.tail = v.tail;
     rec.rr[at] = r;
     rec.dir[at] = dv;
-    const float dx = (float)e.obs.x, dy = (float)e.obs.y, dz = (float)e.obs.z;
-    float phi = atan2f(dy, dx);
-    if (phi < 0.0f) phi += 6.28318531f;
-    if (phi >= 6.28318531f) phi = 0.0f;
-    rec.ang[at] = make_float2(atan2f(sqrtf(dx * dx + dy * dy), dz), phi);
+    rec.ang[at] = make_float2(v.th, v.ph);
   }
 };
 
@@ -758,6 +784,74 @@ __device__ __forceinline__ v3<double> full_dir(const RayRec<float>& r) {
              (double)r.dir[2] + (double)r.tail.dlo[2] * s);
 }
 
+// Contribution of a triangle (vertex records v[0..2], in triangle order) to
+// node (it, ip): sum_v lambda_v F_v exp(i k r_v.(d_v - n)) on the node's
+// (e_theta, e_phi), accumulated into acc[pol][theta|phi][re|im].  lam: the
+// weights of the membership test; an FP32 record set recomputes them in FP64
+// from the directions plus their residuals.  With_phase: phi_t receives the
+// triangle's phase carried to the node, from the vertices' FP64 phases ph64.
+template <typename G, typename R>
+__device__ __forceinline__ void hit_contrib(const R& v0, const R& v1, const R& v2, const NodeGrid& ng, int it,
+                                            int ip, int n_pol, const G lam_in[3], G acc[2][2][2], bool with_phase,
+                                            double ph0, double ph1, double ph2, double& phi_t) {
+
+  const double st = ng.sth[it], ct = ng.cth[it], sp = ng.sph[ip], cp = ng.cph[ip];
+  const v3<double> eth = mk3<double>(ct * cp, ct * sp, -st);
+  const v3<double> eph = mk3<double>(-sp, cp, 0.0);
+  for (int p = 0; p < 2; ++p)
+    for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
+  const v3<double> n = node_dir(ng, it, ip);
+  G lam[3] = {lam_in[0], lam_in[1], lam_in[2]};
+  double lam64[3] = {(double)lam_in[0], (double)lam_in[1], (double)lam_in[2]};
+  if (sizeof(G) == 4) {
+    // weights of the central projection from the FP64 vertex directions
+    // (stored direction plus its rounding residual): (d_a x d_b).n over the
+    // cyclic edges, normalised
+    v3<double> dd[3];
+    dd[0] = full_dir(v0);
+    dd[1] = full_dir(v1);
+    dd[2] = full_dir(v2);
+    const double w0 = dot(cross(dd[1], dd[2]), n), w1 = dot(cross(dd[2], dd[0]), n), w2 = dot(cross(dd[0], dd[1]), n);
+    const double sw = w0 + w1 + w2;
+    if (sw != 0.0) {
+      const double is = 1.0 / sw;
+      lam64[0] = w0 * is; lam64[1] = w1 * is; lam64[2] = w2 * is;
+      lam[0] = (G)lam64[0]; lam[1] = (G)lam64[1]; lam[2] = (G)lam64[2];
+    }
+  }
+  double ph = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R& vr = k == 0 ? v0 : (k == 1 ? v1 : v2);
+    const double lk = k == 0 ? lam64[0] : (k == 1 ? lam64[1] : lam64[2]);
+    const G lkg = k == 0 ? lam[0] : (k == 1 ? lam[1] : lam[2]);
+    const G dkx = vr.dir[0], dky = vr.dir[1], dkz = vr.dir[2];
+    // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
+    // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
+    const double psi = near_carry(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dkx,
+                                  (double)dky, (double)dkz, n.x, n.y, n.z);
+    if (with_phase) ph += lk * ((k == 0 ? ph0 : (k == 1 ? ph1 : ph2)) + psi);
+    G s_, c_;
+    if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
+    else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
+    const G lr = lkg * c_, li = lkg * s_;
+    // the vertex field is stored on its direction's (e_theta, e_phi); turn it
+    // onto the node's
+    v3<double> et, ep;
+    dir_basis((double)dkx, (double)dky, (double)dkz, et, ep);
+    const G ctt = (G)dot(et, eth), cpt = (G)dot(ep, eth), ctp = (G)dot(et, eph), cpp = (G)dot(ep, eph);
+    const G* fp = vr.f;
+    for (int p = 0; p < n_pol; ++p) {
+      const G ar = fp[p * 4 + 0], ai = fp[p * 4 + 1], br = fp[p * 4 + 2], bi = fp[p * 4 + 3];
+      const G tr = ar * ctt + br * cpt, ti = ai * ctt + bi * cpt;
+      const G pr = ar * ctp + br * cpp, pi_ = ai * ctp + bi * cpp;
+      acc[p][0][0] += lr * tr - li * ti;  acc[p][0][1] += lr * ti + li * tr;
+      acc[p][1][0] += lr * pr - li * pi_; acc[p][1][1] += lr * pi_ + li * pr;
+    }
+  }
+  phi_t = ph;
+}
+
 // Contribution of the hit in pool slot idx (its descriptor), stored at its
 // place in its node's range (node-major order): the range start from the
 // scan plus the rank the rasteriser took with the node's count, so this
@@ -776,62 +870,17 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
   const long v00 = (long)quad + quad / (unsigned)(N - 1);
   const long rb = (long)B.n_ord * (B.ray_off[part] - B.ray_base) + (long)slot * N * N;
   const long vid[3] = {v00, t == 0 ? v00 + 1 : v00 + N + 1, t == 0 ? v00 + N + 1 : v00 + N};
-  const double st = ng.sth[it], ct = ng.cth[it], sp = ng.sph[ip], cp = ng.cph[ip];
-  const v3<double> eth = mk3<double>(ct * cp, ct * sp, -st);
-  const v3<double> eph = mk3<double>(-sp, cp, 0.0);
+  const bool with_phase = pool.phi != nullptr;
   G acc[2][2][2];
-  for (int p = 0; p < 2; ++p)
-    for (int a = 0; a < 2; ++a) acc[p][a][0] = acc[p][a][1] = 0;
-  const v3<double> n = node_dir(ng, it, ip);
-  G lam[3] = {d.lam[0], d.lam[1], d.lam[2]};
-  double lam64[3] = {(double)d.lam[0], (double)d.lam[1], (double)d.lam[2]};
-  if (sizeof(G) == 4) {
-    // weights of the central projection from the FP64 vertex directions
-    // (stored direction plus its rounding residual): (d_a x d_b).n over the
-    // cyclic edges, normalised
-    v3<double> dd[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dd[k] = full_dir(rec.rr[rb + vid[k]]);
-    const double w0 = dot(cross(dd[1], dd[2]), n), w1 = dot(cross(dd[2], dd[0]), n), w2 = dot(cross(dd[0], dd[1]), n);
-    const double sw = w0 + w1 + w2;
-    if (sw != 0.0) {
-      const double is = 1.0 / sw;
-      lam64[0] = w0 * is; lam64[1] = w1 * is; lam64[2] = w2 * is;
-      lam[0] = (G)lam64[0]; lam[1] = (G)lam64[1]; lam[2] = (G)lam64[2];
-    }
-  }
   double phi_t = 0.0;  // the triangle's phase carried to the node (caustic correction)
-  for (int k = 0; k < 3; ++k) {
-    const RayRec<G>& vr = rec.rr[rb + vid[k]];
-    const Dir4<G> dk{vr.dir[0], vr.dir[1], vr.dir[2], (G)0};
-    // carried phase k r.(d - n) in FP64: for large particles k |r| reaches
-    // 10^4 and the product tens of radians, beyond FP32's absolute accuracy
-    const double psi = near_carry(ng.kappa, (double)vr.kr[0], (double)vr.kr[1], (double)vr.kr[2], (double)dk.x,
-                                  (double)dk.y, (double)dk.z, n.x, n.y, n.z);
-    if (pool.phi) phi_t += lam64[k] * (rec.ph64[rb + vid[k]] + psi);
-    G s_, c_;
-    if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
-    else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
-    const G lr = lam[k] * c_, li = lam[k] * s_;
-    // the vertex field is stored on its direction's (e_theta, e_phi); turn it
-    // onto the node's
-    v3<double> et, ep;
-    dir_basis((double)dk.x, (double)dk.y, (double)dk.z, et, ep);
-    const G ctt = (G)dot(et, eth), cpt = (G)dot(ep, eth), ctp = (G)dot(et, eph), cpp = (G)dot(ep, eph);
-    const G* fp = vr.f;
-    for (int p = 0; p < rec.n_pol; ++p) {
-      const G ar = fp[p * 4 + 0], ai = fp[p * 4 + 1], br = fp[p * 4 + 2], bi = fp[p * 4 + 3];
-      const G tr = ar * ctt + br * cpt, ti = ai * ctt + bi * cpt;
-      const G pr = ar * ctp + br * cpp, pi_ = ai * ctp + bi * cpp;
-      acc[p][0][0] += lr * tr - li * ti;  acc[p][0][1] += lr * ti + li * tr;
-      acc[p][1][0] += lr * pr - li * pi_; acc[p][1][1] += lr * pi_ + li * pr;
-    }
-  }
+  hit_contrib<G>(rec.rr[rb + vid[0]], rec.rr[rb + vid[1]], rec.rr[rb + vid[2]], ng, it, ip, rec.n_pol, d.lam, acc,
+                 with_phase, with_phase ? rec.ph64[rb + vid[0]] : 0.0, with_phase ? rec.ph64[rb + vid[1]] : 0.0,
+                 with_phase ? rec.ph64[rb + vid[2]] : 0.0, phi_t);
   V4<G>* out = reinterpret_cast<V4<G>*>(pool.contrib + at * (rec.n_pol * 4));
   for (int p = 0; p < rec.n_pol; ++p) {
-    V4<G> v;
-    v.x = acc[p][0][0]; v.y = acc[p][0][1]; v.z = acc[p][1][0]; v.w = acc[p][1][1];
-    out[p] = v;
+    V4<G> v4;
+    v4.x = acc[p][0][0]; v4.y = acc[p][0][1]; v4.z = acc[p][1][0]; v4.w = acc[p][1][1];
+    out[p] = v4;
   }
   pool.key[at] = d.key;
   if (pool.phi) {
@@ -1394,14 +1443,15 @@ __device__ inline void add_fold_pair(const HitPool<G>& pool, long a, long b, int
 // uniform Airy form; the plain instantiation keeps its arrays in registers.
 template <typename G, bool CAUSTIC>
 __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPool<G> pool, int n_nodes, int n_pol,
-                                                  G* out, int32_t* ncontrib, G* incoh) {
+                                                  G* out, int32_t* ncontrib, G* incoh, int cursor_at_end) {
   const long gn = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gn >= (long)B.n * n_nodes) return;
   const int pl = (int)(gn / n_nodes);
   const int node = (int)(gn - (long)pl * n_nodes);
   const long ob = (long)B.out_index[pl];
   const int cnt = pool.count[gn];
-  const long s0 = (long)pool.cursor[gn];
+  // the range start (the fused path's scatter leaves the cursor at its end)
+  const long s0 = (long)pool.cursor[gn] - (cursor_at_end ? cnt : 0);
   int keys[NODE_SORT_MAX], idxs[NODE_SORT_MAX];
   const int w = n_pol * 4;
   G acc[8], inc[2] = {0, 0};

@@ -56,7 +56,7 @@ class Tune(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("rays_per_chunk", ctypes.c_longlong), ("hits_per_node", ctypes.c_double)]
+    _fields_ = [("rays_per_chunk", ctypes.c_longlong), ("hits_per_node", ctypes.c_double), ("fused", ctypes.c_int)]
 
 
 EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_static", "rtw_farfield_status",
@@ -297,6 +297,7 @@ class Batch:
     allocate: bool = True  # False: describe the particles only (no workspace or output)
     incoherent: bool = False  # also return per-node incoherent intensities (self.incoh)
     m_im: Optional[Sequence[float]] = None  # imaginary parts of the indices (None: all 0)
+    fused: bool = False  # the fused kernel where it applies (mixed, <= 6 orders, no caustic correction)
 
     def __post_init__(self):
         import torch
@@ -305,7 +306,7 @@ class Batch:
         mi = [0.0] * n if self.m_im is None else [float(x) for x in self.m_im]
         self.parts = (Particle * n)(*[make_particle(a, e, m, mi[i]) for i, (a, e, m) in enumerate(self.particles)])
         self.gn = (ctypes.c_int * n)(*[int(g) for g in self.grid_n])
-        self.bopts = BatchOpts(int(self.rays_per_chunk), float(self.hits_per_node))
+        self.bopts = BatchOpts(int(self.rays_per_chunk), float(self.hits_per_node), 1 if self.fused else 0)
         self.theta = torch.as_tensor(self.theta_deg, dtype=torch.float64, device=self.device).contiguous()
         self.phi = torch.as_tensor(self.phi_deg, dtype=torch.float64, device=self.device).contiguous()
         self.grid = Grid(self.theta.numel(), self.theta.data_ptr(), self.phi.numel(), self.phi.data_ptr())
