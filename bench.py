@@ -58,7 +58,7 @@ PEAK_HBM_GBS = 8000.0
 CORRECTIONS = {"none": 0, "caustic": 1, "diffraction": 2, "both": 3}  # rtw_trace_opts.corrections bits
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_raster_mixed_c2_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_13856_amd", "csrc", f)
-                  for f in ("rtw_lib.hip", "rtw_device.hpp", "rtw_raster.hpp")]
+                  for f in ("rtw_lib.hip", "rtw_device.hpp", "rtw_raster.hpp", "rtw_fused.hpp")]
 
 
 def source_hash():
@@ -364,6 +364,28 @@ def bench_large(args, rtw, inputs):
     log(f"[large] mixed: {ms:.3f} ms/step, hits {hits}, FP64 re-traced rays {fp64_rays}")
     for k, (t, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
         log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's trace of every 16th ray row (all orders p <= 5), row by
+        # row until ~20 s; the assembly, which needs whole quads of rows, is
+        # not part of this sample
+        import oracle
+        op = oracle.particle(w.semi_axes, w.euler_deg, w.m)
+        st = oracle.setup(w.wavelength, w.n_pol, w.p_min, w.p_max, N)
+        xs = u  # the cell-centred abscissae of the grid above (same half-width)
+        t0 = time.perf_counter()
+        rows_done = act_done = 0
+        for r0 in range(0, N, 16):
+            xy = np.stack([xs, np.full(N, u[r0])], 1)
+            oracle.trace_rays(op, st, xy)
+            act_done += int(((xs / a) ** 2 + (u[r0] / b) ** 2 < 1.0).sum())  # the row's rays that meet it
+            rows_done += 1
+            if time.perf_counter() - t0 > 20.0:
+                break
+        dt = time.perf_counter() - t0
+        cpu = dict(value=round(act_done / dt, 1), unit="active rays/s", cores=oracle.get_threads(), kind="oracle",
+                   sample=f"trace of {rows_done} of the {N // 16} rows 0, 16, 32, ... ({rows_done * N} grid rays, "
+                          f"{act_done} active), {dt:.1f} s; the assembly is not included")
     result = {
         "metric": "rays/s (p<=5) mixed, large ellipsoid", "value": round(n_active / (ms * 1e-3), 1),
         "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -373,7 +395,7 @@ def bench_large(args, rtw, inputs):
                                f"x-polarised, mixed",
                    "active_rays": n_active, "nodes": w.n_nodes, "hits": hits, "fp64_retraced_rays": fp64_rays,
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof.items()}},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
 
@@ -589,6 +611,21 @@ def bench_surrogate(args, rtw, inputs):
     # the network's own share: at the 1% bar it may answer nothing, and the
     # value is then the rate of RTW answering through the query path
     answered_by = "network and RTW fallback" if frac_acc > 0 else "RTW fallback only (the network met the 1% bar nowhere)"
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the method without the network on the host: the oracle's far field of
+        # the query particles on the cells' band of nodes, particle after
+        # particle until ~20 s, at the dense set's 128 queries per particle
+        import oracle
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 20.0 and done < n_qp:
+            oracle.farfield(oracle.particle(*parts[done]), oracle.setup(inputs.WAVELENGTH, 2, 0, 3, sides[done]), th, ph)
+            done += 1
+        dt = time.perf_counter() - t0
+        cpu = dict(value=round(done * k_q / dt, 1), unit="queries/s", cores=oracle.get_threads(), kind="oracle",
+                   sample=f"oracle far fields of the first {done} query particles on the cells' band "
+                          f"({th.size}x{ph.size} nodes), {dt:.1f} s, at {k_q} queries per particle")
     out = {
         "metric": "surrogate queries/s at 1% err",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -605,7 +642,7 @@ def bench_surrogate(args, rtw, inputs):
                    "calibration_accepted_fraction": acc_cal, "calibration_accepted_at_other_bars": others,
                    "calibration_median_err": float(err.median().item()), "by_bar": at_bars,
                    "lr_peak": LR_PEAK, "train_particles": 4096 * len(TRAIN_SEEDS)},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -724,7 +761,8 @@ def main():
     # the method's HBM budget per step: inputs (~100 B), the output field and
     # two passes of 36 B over every contribution
     budget = 100 + w.n_nodes * w.n_pol * 2 * 2 * 4 + 2 * 36 * hits
-    step_bytes = sum(ctr["per_kernel_bytes"].values()) if ctr else None
+    # (k_trace_diag is the rtw_trace call that counts the active rays, not a step kernel)
+    step_bytes = sum(v for k, v in ctr["per_kernel_bytes"].items() if "k_trace_diag" not in k) if ctr else None
     roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_VALU_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_VALU_FP32_TFLOPS, 5),
                     traffic=round(traffic) if traffic is not None else None, kernel=dom,
