@@ -179,6 +179,36 @@ def time_path(rtw, w, grid_n, precision, steps, warmup, zs=0.0, robs=0.0, corr=0
     return ms, prof, hits, fp64_rays
 
 
+def time_fused(rtw, w, grid_n, steps, warmup):
+    """The same mixed far field through the opt-in fused kernel (rtw_batch of
+    one particle with rtw_batch_opts.fused): ms per step, per-kernel times,
+    workspace bytes."""
+    import torch
+    b = rtw.Batch([(w.semi_axes, w.euler_deg, w.m)], [grid_n], rtw.make_incident(w.wavelength, w.n_pol),
+                  rtw.make_opts(w.p_min, w.p_max, grid_n, rtw.MIXED), w.theta_deg, w.phi_deg, fused=True)
+    b()
+    for _ in range(warmup):
+        b.launch(with_counts=False)
+    torch.cuda.synchronize()
+    rtw.profile_read()
+    rtw.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.launch(with_counts=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rtw.profile_enable(False)
+    prof = rtw.profile_read()
+    rc, _ = b.status()
+    if rc != rtw.RTW_OK:
+        raise RuntimeError("hit pool overflowed during the timed steps (fused)")
+    ws = b.ws_bytes
+    del b
+    torch.cuda.empty_cache()
+    return (t1 - t0) * 1e3 / steps, prof, ws
+
+
 def bench_batch(args, rtw, inputs):
     """The batched workload: 4096 seeded ellipsoids (radius 20-500 um, ray-grid
     side 256-2048), p = 0..3, 361 x 180 nodes each, both polarisations, mixed,
@@ -655,6 +685,8 @@ def main():
     ap.add_argument("--grid-n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fused", action="store_true",
+                    help="ellipsoid workload: also time the opt-in fused kernel (rtw_batch_opts.fused) beside it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
     ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate", "paper_spheroid", "large"],
@@ -731,6 +763,13 @@ def main():
             log(f"    {k:20s} {t / n:9.4f} ms/launch  x{n}")
         fp64 = dict(ms_per_step=round(ms64, 4), rays_per_s=n_active / (ms64 * 1e-3),
                     kernels_ms={k: round(t / n, 5) for k, (t, n) in prof64.items()})
+
+    fused = None
+    if args.fused and zs == 0 and robs == 0 and corr == 0 and m_im == 0:
+        msf, proff, wsf = time_fused(rtw, w, args.grid_n, args.steps, args.warmup)
+        log(f"[bench] fused: {msf:.3f} ms/step, workspace {wsf / 2**20:.0f} MiB")
+        fused = dict(ms_per_step=round(msf, 4), rays_per_s=round(n_active / (msf * 1e-3), 1), workspace_bytes=wsf,
+                     kernels_ms={k: round(t / n, 5) for k, (t, n) in proff.items()})
 
     value = n_active / (ms_mixed * 1e-3)
     # roofline of the dominant kernel (plain VALU arithmetic: "alu"), in the
@@ -839,6 +878,7 @@ def main():
                    "kernels_ms": {k: round(t / n, 5) for k, (t, n) in prof_mixed.items()}},
         "fp64_path": fp64,
         "speedup_mixed_over_fp64": round(fp64["ms_per_step"] / ms_mixed, 3) if fp64 else None,
+        "fused_path": fused,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
