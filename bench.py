@@ -86,18 +86,22 @@ def measured_counters():
     if kv.get("source_hash") != source_hash():
         return None
     try:
-        per_kernel = {}
+        per_kernel, per_kernel_valu = {}, {}
         with open(COUNTERS_FILE) as fh:
             for line in fh:
                 parts = line.split()
                 if len(parts) >= 3 and parts[0].startswith(("k_", "rtw::k_")):
                     try:
                         per_kernel[parts[0]] = (float(parts[1]) + float(parts[2])) * 1e6
+                        if len(parts) >= 12:  # counted FP32 + FP64 TFLOP/s, fraction of 78.6, VALU issue fraction
+                            per_kernel_valu[parts[0]] = dict(tflops=float(parts[8]), frac_unpacked=float(parts[9]),
+                                                             issue_frac=float(parts[11]))
                     except ValueError:
                         pass
         return dict(traffic=float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]),
                     valu_busy_pct=float(kv["valu_busy_pct"]), valu_utilization_pct=float(kv["valu_utilization_pct"]),
                     valu_insts=float(kv["valu_insts_per_launch"]), per_kernel_bytes=per_kernel,
+                    per_kernel_valu=per_kernel_valu,
                     kernel=kv.get("kernel"))
     except (KeyError, ValueError):
         return None
@@ -105,8 +109,9 @@ def measured_counters():
 
 def measured_batch_trace_issue():
     """VALU issue fraction of the batched trace kernel (wave instructions over
-    the issue peak) from the committed rocprofv3 summary of this workload, or
-    None if the kernel sources changed since it was taken."""
+    the issue peak) and its counted FP32 + FP64 FLOP rate from the committed
+    rocprofv3 summary of this workload, or None if the kernel sources changed
+    since it was taken."""
     path = os.path.join(ROOT, "profiles", "k_trace_batch4096_valu.txt")
     if not os.path.exists(path):
         return None
@@ -119,7 +124,10 @@ def measured_batch_trace_issue():
     if kv.get("source_hash") != source_hash():
         return None
     try:
-        return float(kv["trace_valu_issue_frac"])
+        out = dict(issue_frac=float(kv["trace_valu_issue_frac"]))
+        if "trace_counted_tflops" in kv:
+            out.update(tflops=float(kv["trace_counted_tflops"]), frac_unpacked=float(kv["trace_counted_frac_unpacked"]))
+        return out
     except (KeyError, ValueError):
         return None
 
@@ -219,7 +227,8 @@ def bench_batch(args, rtw, inputs):
     parts = [(p.semi_axes, p.euler_deg, p.m) for p in bp]
     sides = [p.grid_n for p in bp]
     grid_rays = sum(n * n for n in sides)
-    b = rtw.Batch(parts, sides, rtw.make_incident(inputs.WAVELENGTH, 2), rtw.make_opts(0, 3, 2, rtw.MIXED), th, ph)
+    b = rtw.Batch(parts, sides, rtw.make_incident(inputs.WAVELENGTH, 2), rtw.make_opts(0, 3, 2, rtw.MIXED), th, ph,
+                  rays_per_chunk=args.rays_per_chunk)
     log(f"[bench] batch: {len(parts)} ellipsoids, {grid_rays / 1e9:.3f} G grid rays, {th.size}x{ph.size} nodes each, "
         f"workspace {b.ws_bytes / 2**30:.1f} GiB, output {b.out.numel() * b.out.element_size() / 2**30:.2f} GiB")
     t0 = time.perf_counter()
@@ -284,13 +293,14 @@ def bench_batch(args, rtw, inputs):
         "config": {"workload": f"{len(parts)} seeded ellipsoids (SplitMix64 seed 0), radius 20-500 um, axis ratios "
                                f"0.8-1.2, m 1.30-1.50, p=0..3, ray-grid side 256-2048, 361x180 nodes, 2 polarisations",
                    "grid_rays": grid_rays, "active_rays_est": round(n_active), "hits": hits,
+                   "rays_per_chunk": args.rays_per_chunk or None, "workspace_bytes": b.ws_bytes,
                    "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(len(parts) * th.size * ph.size * 2 / (ms * 1e-3), 1),
                    "tune": {"tile_rays": tune.tile_rays, "blocks_per_cu": tune.blocks_per_cu,
                             "cand_inline": tune.cand_inline},
                    "kernels_ms_per_step": {k: round(t / args.steps, 4) for k, (t, n) in prof.items()},
                    "dominant_kernel": dom,
-                   "trace_valu_issue_frac": measured_batch_trace_issue()},
+                   "trace_valu": measured_batch_trace_issue()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -689,6 +699,11 @@ def main():
                     help="ellipsoid workload: also time the opt-in fused kernel (rtw_batch_opts.fused) beside it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
+    ap.add_argument("--rays-per-chunk", type=int, default=1 << 28,
+                    help="batch: incident rays per chunk of rtw_batch (default 2^28: 23 chunks and a 117 GiB "
+                         "workspace for the 4096 particles; 0: the library's default, 2^26)")
+    ap.add_argument("--flop-calibration", action="store_true",
+                    help="run FP32 and FP64 elementwise kernels of known FLOP count first (scales the VALU FLOP counters)")
     ap.add_argument("--workload", choices=["ellipsoid", "batch", "surrogate", "paper_spheroid", "large"],
                     default="ellipsoid",
                     help="ellipsoid: the 2048^2-ray ellipsoid (default); batch: 4096 seeded ellipsoids via rtw_batch; "
@@ -731,6 +746,20 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        torch.cuda.empty_cache()
+    if args.flop_calibration:
+        # torch's add (a + alpha b: one FMA, 2 FLOP an element) and addcmul
+        # (a + v b c: a multiply and an FMA, 3 FLOP an element) over 2^26
+        # elements, FP32 then FP64, to scale the VALU FLOP counters of a
+        # profiled run
+        n = 1 << 26
+        for dt in (torch.float32, torch.float64):
+            a = torch.ones(n, dtype=dt, device="cuda")
+            b, c = torch.ones_like(a), torch.ones_like(a)
+            torch.add(a, b)
+            torch.addcmul(a, b, c)
+            torch.cuda.synchronize()
+            del a, b, c
         torch.cuda.empty_cache()
     if args.workload == "batch":
         return bench_batch(args, rtw, inputs)
@@ -817,7 +846,12 @@ def main():
                     traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic is not None else None,
                     valu_busy_pct=dom_ctr["valu_busy_pct"] if dom_ctr else None,
                     valu_utilization_pct=dom_ctr["valu_utilization_pct"] if dom_ctr else None,
-                    valu_issue_frac=round(dom_ctr["valu_insts"] / avg_s / VALU_ISSUE_PEAK, 4) if dom_ctr else None)
+                    valu_issue_frac=round(dom_ctr["valu_insts"] / avg_s / VALU_ISSUE_PEAK, 4) if dom_ctr else None,
+                    # every FP operation the step kernels issue (calibrated VALU FLOP counters) over their time, as a
+                    # fraction of the 78.6 TFLOP/s unpacked FP32/FP64 FMA rate, and their VALU issue fractions
+                    counted_valu={k.replace("rtw::", ""): v for k, v in ctr["per_kernel_valu"].items()
+                                  if any(x in k for x in ("k_trace_tiles", "k_retrace64", "k_raster<", "k_store_hits",
+                                                          "k_node_sum"))} if ctr else None)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
@@ -27,12 +29,16 @@ def test_counter_summary_matches_or_is_dropped(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
     c = bench.measured_counters()
     assert c == dict(traffic=123.0, valu_busy_pct=55.5, valu_utilization_pct=40.25, valu_insts=7.0,
-                     per_kernel_bytes={}, kernel="k")
-    # per-kernel rows of the table (MB fetched, MB written) are summed per kernel
+                     per_kernel_bytes={}, per_kernel_valu={}, kernel="k")
+    # per-kernel rows of the table (MB fetched, MB written) are summed per kernel; full rows also give
+    # the counted TFLOP/s, its fraction of the unpacked FMA rate and the VALU issue fraction
     f.write_text(f"kernel: k\nsource_hash: {bench.source_hash()}\n" + COUNTER_LINES +
-                 "k_trace_tiles<float>  1.5  2.5  80.0\nrtw::k_raster<float>  10.0  0.5  50.0\n")
+                 "k_trace_tiles<float>  1.5  2.5  80.0\nrtw::k_raster<float>  10.0  0.5  50.0\n"
+                 "k_retrace64  2.2  175.2  49.4  92.8  28.89  0.107  1.651  17.66  0.225  0.100  0.473\n")
     c = bench.measured_counters()
-    assert c["per_kernel_bytes"] == {"k_trace_tiles<float>": 4.0e6, "rtw::k_raster<float>": 10.5e6}
+    assert c["per_kernel_bytes"] == pytest.approx({"k_trace_tiles<float>": 4.0e6, "rtw::k_raster<float>": 10.5e6,
+                                                   "k_retrace64": 177.4e6})
+    assert c["per_kernel_valu"] == {"k_retrace64": dict(tflops=17.66, frac_unpacked=0.225, issue_frac=0.473)}
     f.write_text("source_hash: 0000\n" + COUNTER_LINES)
     assert bench.measured_counters() is None  # kernel changed since the counters were taken
 
