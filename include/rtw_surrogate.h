@@ -99,8 +99,15 @@ int rtw_surrogate_save(rtw_surrogate* h, const char* path);
 int rtw_surrogate_load(rtw_surrogate* h, const char* path);
 
 /* Predictions for n feature rows (DEVICE feats [n][9] FP32) into DEVICE pred
- * [n][4] FP32: ln I_x, ln I_y, ln sigma_x, ln sigma_y.  n <= max_rows. */
+ * [n][4] FP32: ln I_x, ln I_y, ln sigma_x, ln sigma_y.  n <= max_rows.  One
+ * kernel takes every layer of each tile of 128 rows, the activations held on
+ * chip (160 KB of LDS per compute unit; 130 KB used).
+ * rtw_surrogate_forward_layered computes the same predictions through the
+ * per-layer products that training runs (pre-activations written to the
+ * handle's buffers, as the gradient pass needs them); both sum every product
+ * in the same order with the same rounding. */
 int rtw_surrogate_forward(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream);
+int rtw_surrogate_forward_layered(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream);
 
 /* Loss and gradients of the mean beta-NLL over n rows (DEVICE feats
  * [n][9], DEVICE targets [n][2] = ln I_x, ln I_y); *loss (DEVICE float)

@@ -9,7 +9,9 @@
 // master weights W[in][out], Adam moments, and two BF16 copies W[in][out]
 // (for dX = dZ W^T) and W^T[out][in] (for Y = X W).  The 23 embedded inputs
 // are padded to 128 and the 4 outputs to 128 columns (zero weights), so every
-// product is a multiple of the 128 x 128 block tile.
+// product is a multiple of the 128 x 128 block tile.  Training runs the
+// layers as separate products (k_gemm); inference runs them all in one
+// kernel per tile of 128 queries with the activations in LDS (k_mlp_infer).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -90,10 +93,23 @@ struct GemmArgs {
                        //                 slice, i.e. the bias gradient when B = dZ)
 };
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678f)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678f)) + z * 0.39894228f * __expf(-0.5f * z * z);
+// GELU(z) = z Phi(z), Phi(z) = erfc(-z / sqrt 2) / 2, with erfc(u) for u >= 0
+// from Abramowitz & Stegun 7.1.26 (erf to 1.5e-7 absolute):
+//   erfc(u) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-u^2), t = 1 / (1 + p u),
+// and erfc(-u) = 2 - erfc(u).  With the hardware reciprocal and exponential
+// (about one ulp each) Phi stays within a few 1e-7, far below the BF16
+// rounding the activations take, in about a third of the instructions of the
+// library erff.  Training and inference share it.
+__device__ __forceinline__ float phi_cdf(float z) {
+  const float u = fabsf(z) * 0.70710678f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float e = poly * __expf(-u * u);  // erfc(u)
+  return z >= 0.f ? fmaf(-0.5f, e, 1.0f) : 0.5f * e;
 }
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
+__device__ __forceinline__ float gelu_grad(float z) { return phi_cdf(z) + z * 0.39894228f * __expf(-0.5f * z * z); }
 
 // Global -> register staging of one K step of the A and B tiles (16 BF16 of
 // each per thread), and register -> LDS placement in the [row][k] layout.
@@ -216,6 +232,107 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
           g.Fout[(long)blockIdx.z * g.M * g.ldo + o] = v;  // split-K partial
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: every layer of a tile of MQ queries in one block, the activations
+// held in LDS from the embedded inputs to the last hidden layer (they never
+// reach HBM), the weights streamed from L2.  The products are the transposes
+// of the GEMMs' (D[feature][query] = W^T(feature, k) X(query, k), weights as
+// the instruction's A operand, activations as its B operand), so a lane's four
+// accumulators are four consecutive features of one query: one 8-byte LDS
+// store each after bias and GELU.  Every output element sums the same 32-wide
+// products over the same k steps in the same order as k_gemm, with the same
+// bias, GELU and BF16 rounding.  Wave w computes features [64 w, 64 w + 64) of
+// every hidden layer for all MQ queries; the output layer's first 16 features
+// (the four outputs and zero padding) go one query tile per wave.
+// ---------------------------------------------------------------------------
+constexpr int MQ = 128;                   // queries per block
+constexpr int MLP_LDX = HID + 8;          // LDS row of one query's activations: 1040 bytes
+constexpr int MLP_THREADS = 512;          // 8 waves
+constexpr size_t MLP_LDS = (size_t)MQ * MLP_LDX * sizeof(bf16);
+static_assert(MLP_THREADS / 64 * 64 == HID, "eight waves of 64 features cover a hidden layer");
+static_assert(MLP_THREADS / 64 * 16 == MQ, "one query tile per wave in the output layer");
+
+struct MlpWeights {
+  const bf16* Wt[N_LAYERS];     // W^T[out][in] of each layer
+  const float* bias[N_LAYERS];  // [out]
+};
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(MLP_THREADS) k_mlp_infer(const bf16* X0, const MlpWeights P, float* out) {
+  extern __shared__ __align__(16) unsigned char mlp_smem[];
+  bf16(*X)[MLP_LDX] = reinterpret_cast<bf16(*)[MLP_LDX]>(mlp_smem);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const long q0 = (long)blockIdx.x * MQ;
+  // the tile's embedded inputs, IN_PAD BF16 a query
+  for (int i = t; i < MQ * IN_PAD / 8; i += MLP_THREADS) {
+    const int r = i / (IN_PAD / 8), c = (i % (IN_PAD / 8)) * 8;
+    *reinterpret_cast<bf16x8*>(&X[r][c]) = *reinterpret_cast<const bf16x8*>(X0 + (q0 + r) * IN_PAD + c);
+  }
+  __syncthreads();
+  const int rr = lane & 15, kq = 8 * (lane >> 4);
+  const int f0 = 64 * wave;
+  for (int l = 0; l < N_HIDDEN; ++l) {
+    const int K = layer_in(l);
+    const bf16* W = P.Wt[l];
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(W + (long)(f0 + 16 * i + rr) * K + kq);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      // the next k step's weight fragments are in flight during this one's products
+      bf16x8 an[4];
+      const int kn = k0 + 32 < K ? k0 + 32 : k0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) an[i] = *reinterpret_cast<const bf16x8*>(W + (long)(f0 + 16 * i + rr) * K + kn + kq);
+      bf16x8 b[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&X[16 * j + rr][k0 + kq]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = an[i];
+    }
+    __syncthreads();  // every wave has read this layer's inputs
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = f0 + 16 * i + 4 * (lane >> 4);
+      const float4 bb = *reinterpret_cast<const float4*>(P.bias[l] + f);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        bf16x4 v;
+        v[0] = (bf16)gelu(acc[i][j][0] + bb.x);
+        v[1] = (bf16)gelu(acc[i][j][1] + bb.y);
+        v[2] = (bf16)gelu(acc[i][j][2] + bb.z);
+        v[3] = (bf16)gelu(acc[i][j][3] + bb.w);
+        *reinterpret_cast<bf16x4*>(&X[16 * j + rr][f]) = v;
+      }
+    }
+    __syncthreads();
+  }
+  // output layer, features 0..15 of query tile `wave`
+  {
+    const bf16* W = P.Wt[N_LAYERS - 1];
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < HID; k0 += 32) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(W + (long)rr * HID + k0 + kq);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&X[16 * wave + rr][k0 + kq]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int f = 4 * (lane >> 4);
+    const float4 bb = *reinterpret_cast<const float4*>(P.bias[N_LAYERS - 1] + f);
+    float4 o;
+    o.x = acc[0] + bb.x; o.y = acc[1] + bb.y; o.z = acc[2] + bb.z; o.w = acc[3] + bb.w;
+    *reinterpret_cast<float4*>(out + (q0 + 16 * wave + rr) * OUT_PAD + f) = o;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -527,6 +644,23 @@ int forward(rtw_surrogate* h, int n_pad, hipStream_t st) {
   return RTW_OK;
 }
 
+// Forward pass for inference (no pre-activations kept): k_mlp_infer over the
+// n_pad / MQ query tiles; the output pre-activations land in h->out (columns
+// 0..15 written).
+int infer(rtw_surrogate* h, int n_pad, hipStream_t st) {
+  static std::once_flag once;
+  static hipError_t attr = hipSuccess;
+  std::call_once(once, [] {
+    attr = hipFuncSetAttribute((const void*)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_LDS);
+  });
+  if (attr != hipSuccess) return mfail(RTW_ERR_DEVICE, "inference kernel needs %zu bytes of LDS", MLP_LDS);
+  if (n_pad % MQ) return mfail(RTW_ERR_INVALID_ARG, "inference rows %d not a multiple of %d", n_pad, MQ);
+  MlpWeights P;
+  for (int l = 0; l < N_LAYERS; ++l) { P.Wt[l] = h->Wtb[l]; P.bias[l] = h->bias[l]; }
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)(n_pad / MQ)), dim3(MLP_THREADS), MLP_LDS, st, h->X0, P, h->out);
+  return RTW_OK;
+}
+
 int upload_inputs(rtw_surrogate* h, int n, int n_pad, const float* feats, hipStream_t st) {
   hipLaunchKernelGGL(k_inputs, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, st, n, n_pad, feats, h->norm,
                      h->norm + IN_RAW, h->X0);
@@ -744,17 +878,25 @@ int rtw_surrogate_set_params(rtw_surrogate* h, const float* host, size_t n) {
   return RTW_OK;
 }
 
-int rtw_surrogate_forward(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream) {
+static int predict(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream, bool layered) {
   if (!h || !feats || !pred) return mfail(RTW_ERR_INVALID_ARG, "NULL argument");
   if (n < 1 || n > h->max_rows) return mfail(RTW_ERR_INVALID_ARG, "n must be in [1, %d]", h->max_rows);
   hipStream_t st = (hipStream_t)hip_stream;
   const int n_pad = pad_rows(n);
   int rc = upload_inputs(h, n, n_pad, feats, st);
-  if (!rc) rc = forward(h, n_pad, st);
+  if (!rc) rc = layered ? forward(h, n_pad, st) : infer(h, n_pad, st);
   if (rc) return rc;
   hipLaunchKernelGGL(k_predict, dim3((n + 255) / 256), dim3(256), 0, st, n, h->out, h->norm + 18, h->norm + 20, pred);
   if (hipGetLastError() != hipSuccess) return mfail(RTW_ERR_DEVICE, "launch failed");
   return RTW_OK;
+}
+
+int rtw_surrogate_forward(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream) {
+  return predict(h, n, feats, pred, hip_stream, false);
+}
+
+int rtw_surrogate_forward_layered(rtw_surrogate* h, int n, const float* feats, float* pred, void* hip_stream) {
+  return predict(h, n, feats, pred, hip_stream, true);
 }
 
 int rtw_surrogate_grad(rtw_surrogate* h, int n, const float* feats, const float* targets, float* loss,

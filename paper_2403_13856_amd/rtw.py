@@ -378,7 +378,8 @@ class Batch:
 # ---------------------------------------------------------------------------
 SURROGATE_EXPORTED = ["rtw_surrogate_last_error", "rtw_surrogate_param_count", "rtw_surrogate_create",
                       "rtw_surrogate_destroy", "rtw_surrogate_set_normalization", "rtw_surrogate_get_params",
-                      "rtw_surrogate_set_params", "rtw_surrogate_forward", "rtw_surrogate_grad",
+                      "rtw_surrogate_set_params", "rtw_surrogate_forward", "rtw_surrogate_forward_layered",
+                      "rtw_surrogate_grad",
                       "rtw_surrogate_get_grads", "rtw_surrogate_train_step", "rtw_surrogate_features",
                       "rtw_cell_log_intensity", "rtw_surrogate_query_scratch_size", "rtw_surrogate_query"]
 EXPORTED = EXPORTED + SURROGATE_EXPORTED
@@ -419,6 +420,7 @@ def sload():
     L.rtw_surrogate_save.argtypes = [vp, ctypes.c_char_p]
     L.rtw_surrogate_load.argtypes = [vp, ctypes.c_char_p]
     L.rtw_surrogate_forward.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.rtw_surrogate_forward_layered.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.rtw_surrogate_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.rtw_surrogate_train_step.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_float, vp, vp]
     L.rtw_surrogate_features.argtypes = [ctypes.c_int, P(Particle), P(Incident), ctypes.c_int, P(ctypes.c_double),
@@ -523,14 +525,16 @@ class Surrogate:
         _scheck(sload().rtw_surrogate_get_grads(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size))
         return out
 
-    def forward(self, feats, stream=None):
-        """feats: device float32 [n, 9] -> device [n, 4] (ln I_x, ln I_y, ln sigma_x, ln sigma_y)."""
+    def forward(self, feats, stream=None, layered=False):
+        """feats: device float32 [n, 9] -> device [n, 4] (ln I_x, ln I_y, ln sigma_x, ln sigma_y).
+        layered: through the per-layer products of training (rtw_surrogate_forward_layered)."""
         import torch
         n = feats.shape[0]
         out = torch.empty((n, 4), dtype=torch.float32, device=feats.device)
+        fn = sload().rtw_surrogate_forward_layered if layered else sload().rtw_surrogate_forward
         for a in range(0, n, self.max_rows):
             b = min(n, a + self.max_rows)
-            _scheck(sload().rtw_surrogate_forward(self.h, b - a, _ptr(feats[a:b]), _ptr(out[a:b]), _stream_ptr(stream)))
+            _scheck(fn(self.h, b - a, _ptr(feats[a:b]), _ptr(out[a:b]), _stream_ptr(stream)))
         return out
 
     def grad(self, feats, targets, stream=None):

@@ -73,12 +73,29 @@ def test_forward_matches_reference(R):
     rng = np.random.default_rng(1)
     s = _net(R, 11, scale=0.02)
     f = _feats(rng, 300)  # not a multiple of the 128-row tile
-    say("[surrogate forward] 300 rows vs FP64 reference on BF16 operands")
-    got = s.forward(torch.from_numpy(f).cuda()).cpu().numpy()
+    say("[surrogate forward] 300 rows vs FP64 reference on BF16 operands (on-chip and layered forward)")
     ref = M.predict(s.get_params(), f, NORM, bf16_ops=True)
-    err = np.abs(got - ref) / (1.0 + np.abs(ref))
-    say(f"   max scaled error {err.max():.3e}")
-    assert err.max() < 5e-3
+    for layered in (False, True):
+        got = s.forward(torch.from_numpy(f).cuda(), layered=layered).cpu().numpy()
+        err = np.abs(got - ref) / (1.0 + np.abs(ref))
+        say(f"   layered={layered}: max scaled error {err.max():.3e}")
+        assert err.max() < 5e-3
+
+
+@pytest.mark.parametrize("n", [1, 128, 300, 4096, 9000])
+def test_onchip_forward_equals_layered_forward(R, n):
+    """The inference kernel (every layer of a 128-row tile in one block,
+    activations in LDS, products transposed) against the per-layer products
+    of training: the same sums in the same order, so bitwise equal, for a
+    partial tile, one tile, several, the handle's row capacity and more rows
+    than that (chunked by the binding)."""
+    rng = np.random.default_rng(7 + n)
+    s = _net(R, 13, scale=0.02)
+    f = torch.from_numpy(_feats(rng, n)).cuda()
+    say(f"[surrogate on-chip forward] {n} rows")
+    a = s.forward(f)
+    b = s.forward(f, layered=True)
+    assert torch.equal(a, b), f"max difference {(a - b).abs().max().item():.3e}"
 
 
 def test_gradients_match_reference(R):
