@@ -70,6 +70,7 @@ constexpr int layer_out(int l) { return l == N_LAYERS - 1 ? OUT_PAD : HID; }
 // l % 16).
 // ---------------------------------------------------------------------------
 constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;  // padded LDS row: 80 bytes
+constexpr long GEMM_CUS = 256;  // compute units of the chip: the tile choice aims at >= 2 blocks each
 
 enum Epi : int { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_STORE_F32 = 3 };
 
@@ -111,95 +112,116 @@ __device__ __forceinline__ float phi_cdf(float z) {
 __device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 __device__ __forceinline__ float gelu_grad(float z) { return phi_cdf(z) + z * 0.39894228f * __expf(-0.5f * z * z); }
 
-// Global -> register staging of one K step of the A and B tiles (16 BF16 of
-// each per thread), and register -> LDS placement in the [row][k] layout.
+// Global -> register staging of one K step of the A and B tiles (TM / 8 BF16
+// of each per thread: NV = TM / 64 vectors of 8), and register -> LDS
+// placement in the [row][k] layout.  Untransposed: 4 / NV threads a row, each
+// NV vectors along k; transposed (k rows of TM): 8 threads a k row, each NV
+// vectors along the row index.
+template <int TM>
 struct Stage {
-  bf16x8 a0, a1, b0, b1;
+  static constexpr int NV = TM / 64;
+  bf16x8 a[NV], b[NV];
 };
 
-__device__ __forceinline__ void stage_load(const GemmArgs& g, long m0, long n0, int k0, int t, Stage& r) {
+template <int TM>
+__device__ __forceinline__ void stage_load(const GemmArgs& g, long m0, long n0, int k0, int t, Stage<TM>& r) {
+  constexpr int NV = TM / 64, TPR = 4 / NV;
   if (!g.transA) {
-    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (m0 + (t >> 1)) * g.lda + k0 + (t & 1) * 16);
-    r.a0 = src[0]; r.a1 = src[1];
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (m0 + t / TPR) * g.lda + k0 + (t % TPR) * NV * 8);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.a[v] = src[v];
   } else {
-    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (long)(k0 + (t >> 3)) * g.lda + m0 + (t & 7) * 16);
-    r.a0 = src[0]; r.a1 = src[1];
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.A + (long)(k0 + (t >> 3)) * g.lda + m0 + (t & 7) * NV * 8);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.a[v] = src[v];
   }
   if (g.transB) {
-    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (n0 + (t >> 1)) * g.ldb + k0 + (t & 1) * 16);
-    r.b0 = src[0]; r.b1 = src[1];
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (n0 + t / TPR) * g.ldb + k0 + (t % TPR) * NV * 8);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.b[v] = src[v];
   } else {
-    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (long)(k0 + (t >> 3)) * g.ldb + n0 + (t & 7) * 16);
-    r.b0 = src[0]; r.b1 = src[1];
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(g.B + (long)(k0 + (t >> 3)) * g.ldb + n0 + (t & 7) * NV * 8);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.b[v] = src[v];
   }
 }
 
-__device__ __forceinline__ void stage_store(const GemmArgs& g, int t, const Stage& r, bf16 (*As)[LDK],
+template <int TM>
+__device__ __forceinline__ void stage_store(const GemmArgs& g, int t, const Stage<TM>& r, bf16 (*As)[LDK],
                                             bf16 (*Bs)[LDK]) {
+  constexpr int NV = TM / 64, TPR = 4 / NV;
   if (!g.transA) {
-    const int row = t >> 1, kh = (t & 1) * 16;
-    *reinterpret_cast<bf16x8*>(&As[row][kh]) = r.a0;
-    *reinterpret_cast<bf16x8*>(&As[row][kh + 8]) = r.a1;
-  } else {
-    const int kk = t >> 3, mc = (t & 7) * 16;
+    const int row = t / TPR, kh = (t % TPR) * NV * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) { As[mc + j][kk] = r.a0[j]; As[mc + 8 + j][kk] = r.a1[j]; }
+    for (int v = 0; v < NV; ++v) *reinterpret_cast<bf16x8*>(&As[row][kh + 8 * v]) = r.a[v];
+  } else {
+    const int kk = t >> 3, mc = (t & 7) * NV * 8;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[mc + 8 * v + j][kk] = r.a[v][j];
   }
   if (g.transB) {
-    const int row = t >> 1, kh = (t & 1) * 16;
-    *reinterpret_cast<bf16x8*>(&Bs[row][kh]) = r.b0;
-    *reinterpret_cast<bf16x8*>(&Bs[row][kh + 8]) = r.b1;
-  } else {
-    const int kk = t >> 3, nc = (t & 7) * 16;
+    const int row = t / TPR, kh = (t % TPR) * NV * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) { Bs[nc + j][kk] = r.b0[j]; Bs[nc + 8 + j][kk] = r.b1[j]; }
+    for (int v = 0; v < NV; ++v) *reinterpret_cast<bf16x8*>(&Bs[row][kh + 8 * v]) = r.b[v];
+  } else {
+    const int kk = t >> 3, nc = (t & 7) * NV * 8;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[nc + 8 * v + j][kk] = r.b[v][j];
   }
 }
 
 // Software-pipelined main loop: the next K step's tiles are loaded into
 // registers while the matrix cores work on the current one from LDS, then
-// placed into the other LDS buffer; one barrier per K step.
-template <int EPI>
+// placed into the other LDS buffer; one barrier per K step.  TM x TM block
+// tiles (128, or 64 where 128 would leave the compute units short of blocks),
+// 4 waves in 2 x 2, each (TM / 2)^2 = (TM / 32)^2 MFMA tiles.
+template <int EPI, int TM>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
-  __shared__ bf16 As[2][BM][LDK];
-  __shared__ bf16 Bs[2][BN][LDK];
+  static_assert(TM == 128 || (TM == 64 && EPI != EPI_STORE_F32), "64-wide tiles for the forward and backward products");
+  constexpr int NT = TM / 32;  // MFMA tiles per wave and dimension
+  __shared__ bf16 As[2][TM][LDK];
+  __shared__ bf16 Bs[2][TM][LDK];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long m0 = (long)blockIdx.y * BM, n0 = (long)blockIdx.x * BN;
-  f32x4 acc[4][4];
+  const long m0 = (long)blockIdx.y * TM, n0 = (long)blockIdx.x * TM;
+  f32x4 acc[NT][NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   float csum = 0.f;  // column sum of B over this block's K slice (weight-gradient products)
   const bool do_csum = EPI == EPI_STORE_F32 && g.colsum && blockIdx.y == 0;
   const int k_begin = blockIdx.z * g.K_slice, k_end = min(g.K, k_begin + g.K_slice);
-  Stage r;
-  stage_load(g, m0, n0, k_begin, t, r);
-  stage_store(g, t, r, As[0], Bs[0]);
+  Stage<TM> r;
+  stage_load<TM>(g, m0, n0, k_begin, t, r);
+  stage_store<TM>(g, t, r, As[0], Bs[0]);
   __syncthreads();
   int cur = 0;
   for (int k0 = k_begin; k0 < k_end; k0 += BK) {
     const bool more = k0 + BK < k_end;
-    if (more) stage_load(g, m0, n0, k0 + BK, t, r);
+    if (more) stage_load<TM>(g, m0, n0, k0 + BK, t, r);
     if (do_csum) {
       // column sums of this K step of B, in a fixed order (two halves of k per column)
       const int n = t & 127, kh = (t >> 7) * 16;
 #pragma unroll
       for (int j = 0; j < 16; ++j) csum += (float)Bs[cur][n][kh + j];
     }
-    bf16x8 af[4], bfr[4];
+    bf16x8 af[NT], bfr[NT];
     const int kq = 8 * (lane >> 4), rr = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm * 64 + i * 16 + rr][kq]);
+    for (int i = 0; i < NT; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm * (TM / 2) + i * 16 + rr][kq]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn * 64 + j * 16 + rr][kq]);
+    for (int j = 0; j < NT; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn * (TM / 2) + j * 16 + rr][kq]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    if (more) stage_store(g, t, r, As[cur ^ 1], Bs[cur ^ 1]);
+      for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (more) stage_store<TM>(g, t, r, As[cur ^ 1], Bs[cur ^ 1]);
     __syncthreads();
     cur ^= 1;
   }
@@ -211,13 +233,13 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   }
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int rr2 = 0; rr2 < 4; ++rr2) {
-        const long row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + rr2;
-        const long col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const long row = m0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + rr2;
+        const long col = n0 + wn * (TM / 2) + j * 16 + (lane & 15);
         const long o = row * g.ldo + col;
         const float v = acc[i][j][rr2];
         if (EPI == EPI_FWD_GELU) {
@@ -604,12 +626,18 @@ int gemm(int epi, GemmArgs g, hipStream_t st, int splits = 1, int* used_splits =
   splits = (g.K + g.K_slice - 1) / g.K_slice;
   if (splits > 1 && epi != EPI_STORE_F32) return mfail(RTW_ERR_INVALID_ARG, "split K only for weight gradients");
   if (used_splits) *used_splits = splits;
-  dim3 grid(g.N / BN, g.M / BM, splits);
-  switch (epi) {
-    case EPI_FWD_GELU: hipLaunchKernelGGL(k_gemm<EPI_FWD_GELU>, grid, dim3(256), 0, st, g); break;
-    case EPI_FWD_LINEAR: hipLaunchKernelGGL(k_gemm<EPI_FWD_LINEAR>, grid, dim3(256), 0, st, g); break;
-    case EPI_BWD_GELU: hipLaunchKernelGGL(k_gemm<EPI_BWD_GELU>, grid, dim3(256), 0, st, g); break;
-    default: hipLaunchKernelGGL(k_gemm<EPI_STORE_F32>, grid, dim3(256), 0, st, g); break;
+  // 64-wide tiles where 128-wide ones would give fewer than two blocks a compute unit
+  const bool small = epi != EPI_STORE_F32 && (long)(g.N / BN) * (g.M / BM) < 2L * GEMM_CUS;
+  const int tm = small ? 64 : 128;
+  dim3 grid(g.N / tm, g.M / tm, splits);
+  switch (epi * 2 + (small ? 1 : 0)) {
+    case 2 * EPI_FWD_GELU: hipLaunchKernelGGL((k_gemm<EPI_FWD_GELU, 128>), grid, dim3(256), 0, st, g); break;
+    case 2 * EPI_FWD_GELU + 1: hipLaunchKernelGGL((k_gemm<EPI_FWD_GELU, 64>), grid, dim3(256), 0, st, g); break;
+    case 2 * EPI_FWD_LINEAR: hipLaunchKernelGGL((k_gemm<EPI_FWD_LINEAR, 128>), grid, dim3(256), 0, st, g); break;
+    case 2 * EPI_FWD_LINEAR + 1: hipLaunchKernelGGL((k_gemm<EPI_FWD_LINEAR, 64>), grid, dim3(256), 0, st, g); break;
+    case 2 * EPI_BWD_GELU: hipLaunchKernelGGL((k_gemm<EPI_BWD_GELU, 128>), grid, dim3(256), 0, st, g); break;
+    case 2 * EPI_BWD_GELU + 1: hipLaunchKernelGGL((k_gemm<EPI_BWD_GELU, 64>), grid, dim3(256), 0, st, g); break;
+    default: hipLaunchKernelGGL((k_gemm<EPI_STORE_F32, 128>), grid, dim3(256), 0, st, g); break;
   }
   return RTW_OK;
 }
