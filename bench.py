@@ -228,7 +228,7 @@ def bench_batch(args, rtw, inputs):
     sides = [p.grid_n for p in bp]
     grid_rays = sum(n * n for n in sides)
     b = rtw.Batch(parts, sides, rtw.make_incident(inputs.WAVELENGTH, 2), rtw.make_opts(0, 3, 2, rtw.MIXED), th, ph,
-                  rays_per_chunk=args.rays_per_chunk)
+                  rays_per_chunk=args.rays_per_chunk, fused=args.fused)
     log(f"[bench] batch: {len(parts)} ellipsoids, {grid_rays / 1e9:.3f} G grid rays, {th.size}x{ph.size} nodes each, "
         f"workspace {b.ws_bytes / 2**30:.1f} GiB, output {b.out.numel() * b.out.element_size() / 2**30:.2f} GiB")
     t0 = time.perf_counter()
@@ -294,6 +294,7 @@ def bench_batch(args, rtw, inputs):
                                f"0.8-1.2, m 1.30-1.50, p=0..3, ray-grid side 256-2048, 361x180 nodes, 2 polarisations",
                    "grid_rays": grid_rays, "active_rays_est": round(n_active), "hits": hits,
                    "rays_per_chunk": args.rays_per_chunk or None, "workspace_bytes": b.ws_bytes,
+                   "fused": bool(args.fused),
                    "fp64_retraced_rays": fp64_rays,
                    "far_field_points_per_s": round(len(parts) * th.size * ph.size * 2 / (ms * 1e-3), 1),
                    "tune": {"tile_rays": tune.tile_rays, "blocks_per_cu": tune.blocks_per_cu,
@@ -696,7 +697,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fused", action="store_true",
-                    help="ellipsoid workload: also time the opt-in fused kernel (rtw_batch_opts.fused) beside it")
+                    help="ellipsoid workload: also time the opt-in fused kernel (rtw_batch_opts.fused) beside it; "
+                         "batch workload: run the batch through it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
     ap.add_argument("--rays-per-chunk", type=int, default=1 << 28,
