@@ -913,13 +913,23 @@ int launch_fused(const Plan& pl, const Tuning& tu, int c0, int c1, const BatchDe
   const size_t lds = sizeof(LRec) * FUSED_COLS * (size_t)S.n_ord;  // the carry
   const int steps = pl.tile / (FUSED_COLS * FUSED_ROWS);
   // the carry with the static LDS exceeds 64 KB: allow the kernels that much
-  // dynamic LDS (once per process; the launch reports any failure)
-  static std::once_flag lds_once;
-  std::call_once(lds_once, [] {
-    const int most = (int)(sizeof(LRec) * FUSED_COLS * FUSED_MAX_ORD);
-    (void)hipFuncSetAttribute((const void*)k_fused<false>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
-    (void)hipFuncSetAttribute((const void*)k_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
-  });
+  // dynamic LDS, once per device with that device current
+  {
+    static std::mutex lds_mu;
+    static bool lds_set[64] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+      return fail(RTW_ERR_DEVICE, "fused far field: no current device");
+    std::lock_guard<std::mutex> lk(lds_mu);
+    if (!lds_set[dev]) {
+      const int most = (int)(sizeof(LRec) * FUSED_COLS * FUSED_MAX_ORD);
+      hipError_t e = hipFuncSetAttribute((const void*)k_fused<false>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+      if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "fused far field: LDS attribute: %s", hipGetErrorString(e));
+      lds_set[dev] = true;
+    }
+  }
   { ProfScope ps("k_fused_mixed", st);
   bool any_gen = false, any_plain = false;
   for (int c = c0; c < c1; ++c) (needs_general_trace(pl.P[c]) ? any_gen : any_plain) = true;

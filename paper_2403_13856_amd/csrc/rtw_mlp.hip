@@ -676,12 +676,20 @@ int forward(rtw_surrogate* h, int n_pad, hipStream_t st) {
 // n_pad / MQ query tiles; the output pre-activations land in h->out (columns
 // 0..15 written).
 int infer(rtw_surrogate* h, int n_pad, hipStream_t st) {
-  static std::once_flag once;
-  static hipError_t attr = hipSuccess;
-  std::call_once(once, [] {
-    attr = hipFuncSetAttribute((const void*)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_LDS);
-  });
-  if (attr != hipSuccess) return mfail(RTW_ERR_DEVICE, "inference kernel needs %zu bytes of LDS", MLP_LDS);
+  // the kernel's dynamic LDS beyond 64 KB, allowed once per device with that device current
+  {
+    static std::mutex mu;
+    static bool set[64] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return mfail(RTW_ERR_DEVICE, "no current device");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!set[dev]) {
+      if (hipFuncSetAttribute((const void*)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MLP_LDS) !=
+          hipSuccess)
+        return mfail(RTW_ERR_DEVICE, "inference kernel needs %zu bytes of LDS", MLP_LDS);
+      set[dev] = true;
+    }
+  }
   if (n_pad % MQ) return mfail(RTW_ERR_INVALID_ARG, "inference rows %d not a multiple of %d", n_pad, MQ);
   MlpWeights P;
   for (int l = 0; l < N_LAYERS; ++l) { P.Wt[l] = h->Wtb[l]; P.bias[l] = h->bias[l]; }
