@@ -259,10 +259,10 @@ __device__ __forceinline__ void record_values(const Emission<E>& e, double k, do
   r.dir[0] = dv.x; r.dir[1] = dv.y; r.dir[2] = dv.z;
   set_tail(r.tail, e.obs64, dv);
   const float dx = (float)e.obs.x, dy = (float)e.obs.y, dz = (float)e.obs.z;
-  float phi = atan2f(dy, dx);
+  float phi = atan2_f32(dy, dx);
   if (phi < 0.0f) phi += 6.28318531f;
   if (phi >= 6.28318531f) phi = 0.0f;
-  r.th = atan2f(sqrtf(dx * dx + dy * dy), dz);
+  r.th = atan2_f32(sqrtf(dx * dx + dy * dy), dz);
   r.ph = phi;
 }
 
@@ -833,7 +833,7 @@ __device__ __forceinline__ void hit_contrib(const R& v0, const R& v1, const R& v
     if (with_phase) ph += lk * ((k == 0 ? ph0 : (k == 1 ? ph1 : ph2)) + psi);
     G s_, c_;
     if (sizeof(G) == 8) sincos_t((G)psi, &s_, &c_);
-    else sincos_t((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
+    else sincos_red((G)(psi - 6.283185307179586 * rint(psi * 0.15915494309189535)), &s_, &c_);
     const G lr = lkg * c_, li = lkg * s_;
     // the vertex field is stored on its direction's (e_theta, e_phi); turn it
     // onto the node's
