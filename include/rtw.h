@@ -316,6 +316,12 @@ int rtw_farfield_stats(const void* workspace, void* hip_stream, uint64_t* hits, 
 int rtw_profile_enable(int on);
 int rtw_profile_read(int max_kernels, char* names, double* total_ms, int* launches, int* n_kernels);
 
+/* Restricts the events of rtw_profile_enable to the kernels reported under
+ * this name by rtw_profile_read, so that a benchmark timing one kernel inside
+ * a timed loop adds two events a launch of it instead of two for every
+ * kernel; NULL or "" records every kernel again.  The name is copied. */
+int rtw_profile_only(const char* name);
+
 const char* rtw_last_error(void);
 
 /* Library version string. */

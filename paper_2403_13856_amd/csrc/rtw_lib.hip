@@ -49,6 +49,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 bool g_prof_on = false;
+std::string g_prof_only;  // record only the kernels of this name (empty: every kernel)
 thread_local bool g_prof_off = false;  // set while a call must not create events
 
 struct ProfScope {
@@ -57,6 +58,10 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
     if (!g_prof_on || g_prof_off) return;
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      if (!g_prof_only.empty() && g_prof_only != name) return;
+    }
     hipEventCreate(&a);
     hipEventCreate(&b);
     hipEventRecord(a, st);
@@ -1150,6 +1155,12 @@ const char* rtw_last_error(void) { return g_err.c_str(); }
 int rtw_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  return RTW_OK;
+}
+
+int rtw_profile_only(const char* name) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_only = name ? name : "";
   return RTW_OK;
 }
 

@@ -61,7 +61,7 @@ class BatchOpts(ctypes.Structure):
 
 EXPORTED = ["rtw_trace", "rtw_farfield_workspace_size", "rtw_farfield", "rtw_farfield_static", "rtw_farfield_status",
             "rtw_farfield_stats", "rtw_batch_workspace_size", "rtw_batch", "rtw_batch_autotune",
-            "rtw_profile_enable", "rtw_profile_read", "rtw_last_error", "rtw_version"]
+            "rtw_profile_enable", "rtw_profile_read", "rtw_profile_only", "rtw_last_error", "rtw_version"]
 
 _lib = None
 
@@ -104,6 +104,7 @@ def load():
                                      ctypes.c_void_p, P(Tune)]
     L.rtw_farfield_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_uint64), P(ctypes.c_uint64)]
     L.rtw_profile_enable.argtypes = [ctypes.c_int]
+    L.rtw_profile_only.argtypes = [ctypes.c_char_p]
     L.rtw_profile_read.argtypes = [ctypes.c_int, ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int),
                                    P(ctypes.c_int)]
     L.rtw_last_error.restype = ctypes.c_char_p
@@ -120,6 +121,11 @@ def _check(rc):
 def profile_enable(on: bool = True):
     """Bracket every library kernel with HIP events on its stream (for benchmarks)."""
     _check(load().rtw_profile_enable(1 if on else 0))
+
+
+def profile_only(name=None):
+    """Record events only for the kernel reported under this name (None: every kernel)."""
+    _check(load().rtw_profile_only(name.encode() if name else None))
 
 
 def profile_read(max_kernels: int = 32):
