@@ -206,3 +206,15 @@ def test_batch_chunks_keep_node_indices_32bit():
     _, small1 = _batch_ws(parts[:1], [16], inc, opts, 64, 64)
     _, small3 = _batch_ws(parts, [16, 16, 16], inc, opts, 64, 64)
     assert small3 - small1 >= 2 * 2 * 4 * 64 * 64
+
+
+def test_profile_filter_without_device():
+    """rtw_profile_only takes a name or NULL and records nothing by itself:
+    with no kernel launched, a read reports no kernels either way."""
+    L = rtw.load()
+    n = ctypes.c_int(-1)
+    for name in (b"k_raster_mixed", b"", None):
+        assert L.rtw_profile_only(name) == rtw.RTW_OK
+        assert L.rtw_profile_read(0, None, None, None, ctypes.byref(n)) == rtw.RTW_OK
+        assert n.value == 0
+    assert L.rtw_profile_only(None) == rtw.RTW_OK
