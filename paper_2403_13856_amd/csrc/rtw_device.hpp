@@ -10,12 +10,16 @@
 //
 // Precision policy (template parameter G = type of the wave quantities):
 //   G = double : every step in FP64.
-//   G = float  : Fresnel coefficients, Jones matrix, wavefront-curvature
-//                recursion and the emitted fields in FP32; the polyline
-//                (positions, directions, normals, Snell), chord lengths, optical
-//                path, phase reduction, divergence product and the propagation
-//                Jacobian I + L Q (which vanishes at caustics) stay in FP64.
-//                Records and the far-field assembly are FP32.
+//   G = float  : Fresnel coefficients, Jones matrix and the emitted fields in
+//                FP32; the polyline (positions, directions, normals, Snell),
+//                chord lengths, optical path, phase reduction, the
+//                wavefront-curvature recursion, the divergence product and the
+//                propagation Jacobian I + L Q (which vanishes at caustics) stay
+//                in FP64.  Records and the far-field assembly are FP32.  An
+//                FP64 FMA issues at the rate of an unpacked FP32 one on this
+//                chip, so the curvature costs registers, not time, in FP64,
+//                while in FP32 its rounding, amplified where det(I + L Q)
+//                cancels, sent 15% of the rays to an FP64 re-trace.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -335,7 +339,7 @@ __host__ __device__ inline bool needs_general_trace(const ParticleConst& P) { re
 template <typename G>
 struct RayState {
   v3<double> r, d, u1, u2;  // position on the surface, direction, polarisation basis (u2 = d x u1)
-  G q11, q12, q22;          // WFC in (u1, u2)
+  double q11, q12, q22;     // WFC in (u1, u2)
   cx<G> J[2][2];            // J[component along u_a][incident pol]
   double D;                 // divergence product of the internal segments
   double opl;               // optical path (phase), referenced to the particle centre
@@ -399,7 +403,7 @@ __device__ __forceinline__ bool ray_init(const ParticleConst& P, int ix, int iy,
     // zs / rho, phase k (rho - zs) (both referenced to the particle centre)
     const double rho = t0 + t;
     const double irho = rcp_d(rho);
-    s.q11 = s.q22 = (G)irho;
+    s.q11 = s.q22 = irho;
     s.J[0][0].re = s.J[1][1].re = (G)(P.zs * irho);
     s.opl = P.k * (rho - P.zs);
   }
@@ -421,7 +425,6 @@ template <typename G, bool GEN, typename Sink>
 __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RayState<G>& s, Sink& sink) {
   typedef v3<double> V;
   const double* R = P.R;
-  const G kk = (G)P.k;
   int status = 0;
   // outward normal and incidence-plane basis (FP64)
   V Ar = mk3(P.A[0] * s.r.x, P.A[1] * s.r.y, P.A[2] * s.r.z);
@@ -442,15 +445,16 @@ __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RaySt
     Jl[1][k].re = -sn * s.J[0][k].re + cs * s.J[1][k].re;
     Jl[1][k].im = -sn * s.J[0][k].im + cs * s.J[1][k].im;
   }
-  G t11 = cs * cs * s.q11 + 2 * cs * sn * s.q12 + sn * sn * s.q22;
-  G t12 = (cs * cs - sn * sn) * s.q12 + cs * sn * (s.q22 - s.q11);
-  G t22 = sn * sn * s.q11 - 2 * cs * sn * s.q12 + cs * cs * s.q22;
+  const double csd = dot(ep, s.u1), snd = dot(ep, s.u2);
+  const double t11 = csd * csd * s.q11 + 2 * csd * snd * s.q12 + snd * snd * s.q22;
+  const double t12 = (csd * csd - snd * snd) * s.q12 + csd * snd * (s.q22 - s.q11);
+  const double t22 = snd * snd * s.q11 - 2 * csd * snd * s.q12 + csd * csd * s.q22;
 
   // surface curvature in (s1, s2) = (e_perp, n x e_perp), shape operator of r^T A r = 1
   V s2 = cross(nh, ep);
-  const G C11 = (G)((P.A[0] * ep.x * ep.x + P.A[1] * ep.y * ep.y + P.A[2] * ep.z * ep.z) * inA);
-  const G C12 = (G)((P.A[0] * ep.x * s2.x + P.A[1] * ep.y * s2.y + P.A[2] * ep.z * s2.z) * inA);
-  const G C22 = (G)((P.A[0] * s2.x * s2.x + P.A[1] * s2.y * s2.y + P.A[2] * s2.z * s2.z) * inA);
+  const double C11 = (P.A[0] * ep.x * ep.x + P.A[1] * ep.y * ep.y + P.A[2] * ep.z * ep.z) * inA;
+  const double C12 = (P.A[0] * ep.x * s2.x + P.A[1] * ep.y * s2.y + P.A[2] * ep.z * s2.z) * inA;
+  const double C22 = (P.A[0] * s2.x * s2.x + P.A[1] * s2.y * s2.y + P.A[2] * s2.z * s2.z) * inA;
 
   // Snell (Eq. 4), FP64
   const double n_cur = s.n_cur, n_oth = s.n_oth;
@@ -494,9 +498,8 @@ __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RaySt
 
   // wavefront equation (Eq. 3) with diagonal projections P = diag(1, n.k_hat):
   //   k' P' Q' P' = k_i P_i Q~ P_i + C n.(k' - k_i)
-  const G ki = (G)n_cur * kk;
-  const G dng = (G)dn;
-  const G M11i = ki * t11, M12i = ki * dng * t12, M22i = ki * dng * dng * t22;
+  const double ki = n_cur * P.k;
+  const double M11i = ki * t11, M12i = ki * dn * t12, M22i = ki * dn * dn * t22;
 
   // ---- emission of an order, if this interaction emits one ----
   int p_emit = -1;
@@ -507,14 +510,13 @@ __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RaySt
     status |= 1;
     const double kod = emit_t ? n_oth * P.k : n_cur * P.k;
     const double god = emit_t ? gt : gr;
-    const G ko = (G)kod;
-    const G w = (G)(emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
+    const double w = emit_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn));
     const V dout = emit_t ? dt : dr;
-    const G inko = rcp_t(ko), igo = (G)rcp_d(god);
-    const G a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
-    double Q11 = (double)(a11 * inko);
-    double Q12 = (double)(a12 * inko * igo);
-    double Q22 = (double)(a22 * inko * igo * igo);
+    const double inko = rcp_d(kod), igo = rcp_d(god);
+    const double a11 = M11i + w * C11, a12 = M12i + w * C12, a22 = M22i + w * C22;
+    double Q11 = a11 * inko;
+    double Q12 = a12 * inko * igo;
+    double Q22 = a22 * inko * igo * igo;
     double detQ = Q11 * Q22 - Q12 * Q12;
     int nft = s.nf + neg_eigs(Q11, Q12, Q22);
     double e_amplif = s.amplif;
@@ -615,12 +617,11 @@ __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RaySt
   if (cont_t && tir) return status;
   const double kod = cont_t ? n_oth * P.k : n_cur * P.k;
   const double god = cont_t ? gt : gr;
-  const G ko = (G)kod;
-  const G w = (G)(cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn)));
-  const G inko = rcp_t(ko), igo = (G)rcp_d(god);
-  const G Q11 = (M11i + w * C11) * inko;
-  const G Q12 = (M12i + w * C12) * inko * igo;
-  const G Q22 = (M22i + w * C22) * inko * igo * igo;
+  const double w = cont_t ? (kod * gt - n_cur * P.k * dn) : (n_cur * P.k * (gr - dn));
+  const double inko = rcp_d(kod), igo = rcp_d(god);
+  const double Q11 = (M11i + w * C11) * inko;
+  const double Q12 = (M12i + w * C12) * inko * igo;
+  const double Q22 = (M22i + w * C22) * inko * igo * igo;
   cx<G> c0 = cont_t ? tp : rp, c1 = cont_t ? tl : rl;
   for (int k = 0; k < 2; ++k) {
     s.J[0][k] = cmul(c0, Jl[0][k]);
@@ -652,7 +653,7 @@ __device__ __forceinline__ int ray_interact(const ParticleConst& P, int q, RaySt
   double n11 = ((double)Q11 * g22 - (double)Q12 * g12) * idg;
   double n12 = ((double)Q12 * g11 - (double)Q11 * g12) * idg;
   double n22 = ((double)Q22 * g11 - (double)Q12 * g12) * idg;
-  s.q11 = (G)n11; s.q12 = (G)n12; s.q22 = (G)n22;
+  s.q11 = n11; s.q12 = n12; s.q22 = n22;
   s.opl += s.n_cur * P.k * L;
   if (GEN && s.n_cur != 1.0 && P.m_im > 0.0) {
     // weak absorption along the internal segment

@@ -189,13 +189,14 @@ ParticleConst make_const(const rtw_particle* p, const rtw_incident* inc, const r
   P.p_min = o->p_min;
   P.p_max = o->p_max;
   P.n_pol = inc->n_pol;
-  // FP64 re-trace above this amplification.  Against the FP64 oracle an FP32
-  // divergence factor carries up to ~8 x amplif x 2^-24 relative error (the
-  // rounding of the whole FP32 WFC chain, not one operation: 4.1e-5 at amplif
-  // 87 on the 60/50/40 um ellipsoid observed at 90 um), and a node's intensity
-  // error relative to its incoherent sum is up to 2 n_b times that for n_b
-  // contributions in phase; at 32 that stays below 1e-4 for n_b <= 4
-  P.amplif_limit = 32.0;
+  // FP64 re-trace above this amplification.  The wavefront curvature and the
+  // divergence product are FP64 in both paths, so the amplified rounding is
+  // FP64's: ~8 x amplif x 2^-53 relative in the divergence factor, and a
+  // node's intensity error relative to its incoherent sum up to 2 n_b times
+  // that for n_b contributions in phase; at 1e9 that stays below 1e-5.  (With
+  // the curvature in FP32 the same bound, 8 x amplif x 2^-24, needed a limit
+  // of 32, and 15% of the rays were re-traced.)
+  P.amplif_limit = 1e9;
   return P;
 }
 
@@ -856,9 +857,14 @@ int make_plan(int n, const rtw_particle* parts, const int* grid_n, const rtw_inc
     pl.chunks.push_back({c0, c1});
     pl.S.max_chunk_rays = std::max(pl.S.max_chunk_rays, pl.ray_off[c1] - pl.ray_off[c0]);
     pl.S.max_chunk_parts = std::max(pl.S.max_chunk_parts, c1 - c0);
-    if (fused)
-      pl.S.fused_grid = std::max(pl.S.fused_grid, std::min<long>(pl.tile_off[c1] - pl.tile_off[c0],
-                                                                 (long)compute_units() * FUSED_BPC));
+    if (fused) {
+      // k_fused's per-block scratch is sized for the most blocks any tuning
+      // can ask for (tiles of 256 rays, the smallest tile_rays accepted), so
+      // that the workspace size does not depend on the tuning of the call
+      long items = 0;
+      for (int c = c0; c < c1; ++c) items += tiles_of(pl.P[c].N, 256, true);
+      pl.S.fused_grid = std::max(pl.S.fused_grid, std::min<long>(items, (long)compute_units() * FUSED_BPC));
+    }
     c0 = c1;
   }
   return RTW_OK;

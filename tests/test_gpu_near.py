@@ -96,13 +96,14 @@ def test_near_trace_mixed_matches_oracle(oracle, R, ci):
     same = got["flags"] == ref["flags"]
     assert same.mean() > 0.999, same.mean()
     v = ((ref["flags"] & 1) == 1) & same
-    # rays whose divergence factor amplifies FP32 errors beyond the mixed
-    # path's limit (a caustic close to the observation sphere) are the ones
-    # the far-field path re-traces in FP64; the FP32 figures hold for the rest
+    # rays whose divergence factor amplifies rounding beyond the mixed path's
+    # limit (an FP64 curvature whose det(I + L Q) cancels to ~1e-9, a caustic
+    # on the observation sphere) are the ones the far-field path re-traces in
+    # FP64; the mixed figures hold for the rest
     amplif = got["cond"][:, 0]
-    fp32 = v & (amplif <= 32.0)
+    fp32 = v & (amplif <= 1e9)
     say(f"   {v.sum() - fp32.sum()} of {v.sum()} emissions above the FP64 re-trace limit")
-    assert fp32.sum() >= 0.8 * v.sum()  # measured 0.86 on the coarse 40^2 grid with a point source
+    assert fp32.sum() >= 0.99 * v.sum()
     v = fp32
     ddir = np.abs(got["dir"] - ref["dir"]).max(axis=1)[v]
     assert np.quantile(ddir, 0.999) < 2e-5 and ddir.max() < 1e-3
