@@ -528,9 +528,11 @@ def bench_surrogate(args, rtw, inputs):
     ks = torch.arange(1, e_sorted.numel() + 1, device=e_sorted.device)
 
     def calibrate(err_bar):
-        """Largest prefix (by sigma) in which 99% of the queries are within err_bar."""
+        """Largest prefix (by sigma) in which 99% of the queries are within
+        err_bar, among prefixes of at least 1000 queries (a 99th percentile of
+        fewer says nothing: one lucky query would set tau)."""
         bad = torch.cumsum((e_sorted > err_bar).int(), 0)
-        okk = bad.float() <= 0.01 * ks.float()
+        okk = (bad.float() <= 0.01 * ks.float()) & (ks >= 1000)
         k_best = int(torch.nonzero(okk).max().item()) + 1 if okk.any() else 0
         return (float(sig[order[k_best - 1]].item()) if k_best > 0 else 1e-30), k_best / err.numel()
 
