@@ -64,3 +64,48 @@ def test_committed_batch_trace_summary_is_parseable():
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     assert 0 < float(kv["trace_valu_issue_frac"]) <= 1.0 and len(kv["source_hash"]) == 16
+
+
+class _FakeProfiler:
+    """Records the bench's profiling calls and the launches between them."""
+
+    def __init__(self):
+        self.log, self.on, self.only, self.launches = [], False, None, []
+
+    def profile_enable(self, on):
+        self.on = on
+        self.log.append(("enable", on))
+
+    def profile_only(self, name):
+        self.only = name
+        self.log.append(("only", name))
+
+    def profile_read(self):
+        self.log.append(("read",))
+        rec = [x for x in self.launches if x[0]]
+        self.launches = []
+        out = {}
+        for _, only in rec:
+            for k, ms in (("k_a", 1.0), ("k_b", 3.0)):
+                if only in (None, k):
+                    t, n = out.get(k, (0.0, 0))
+                    out[k] = (t + ms, n + 1)
+        return out
+
+    def launch(self):
+        self.launches.append((self.on, self.only))
+
+
+def test_timed_steps_brackets_only_the_dominant_kernel(monkeypatch):
+    """Warm-up unprofiled, a profiled pass that names the dominant kernel,
+    then exactly `steps` timed launches with events around that kernel only
+    and the filter cleared afterwards."""
+    import torch
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    f = _FakeProfiler()
+    ms, prof, (dom, t, n) = bench.timed_steps(f, f.launch, steps=7, warmup=3, prof_steps=2)
+    assert prof == {"k_a": (2.0, 2), "k_b": (6.0, 2)}
+    assert (dom, t, n) == ("k_b", 21.0, 7)
+    assert ms >= 0.0
+    assert f.only is None and f.on is False
+    assert ("only", "k_b") in f.log and f.log[-2:] == [("only", None), ("read",)]
