@@ -245,7 +245,7 @@ int rtw_farfield_static(const rtw_particle* part, const rtw_incident* inc, const
  * workspace); its results are bitwise independent of the tuning and agree
  * with the staged pipeline's within the mixed path's rounding. */
 typedef struct {
-  int tile_rays;     /* incident rays per trace work item, multiple of 256 (0 = 1024) */
+  int tile_rays;     /* incident rays per trace work item, multiple of 256 (0 = 2048) */
   int blocks_per_cu; /* persistent trace blocks per compute unit (0 = 8) */
   int cand_inline;   /* triangles whose bounding box holds more nodes are rasterised
                         row by row (0 = 4096, the largest allowed) */
