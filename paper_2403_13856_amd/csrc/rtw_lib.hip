@@ -1,11 +1,12 @@
 // rtw_lib.hip -- librtw.so: the C ABI of include/rtw.h over the gfx950 kernels.
 //
 // rtw_farfield runs, on the caller's stream:
-//   k_setup         node tables (sin/cos of the node angles) and pool reset
+//   k_setup         node tables (sin/cos of the node angles), uniform runs of
+//                   the angle lists, counter and first-chunk node-count reset
 //   k_trace_tiles   persistent, one thread per incident ray: Eqs. 3-10, emission records
 //   k_retrace64     (mixed) FP64 re-trace of the rays ill-conditioned in FP32
 //   k_raster<G>     one thread per (order, grid quad): triangle -> node hits
-//   k_scan          node counts -> node ranges
+//   k_scan          node counts -> node ranges; the chunk's hit totals
 //   k_store_hits<G> one thread per hit: interpolated contribution, in node order
 //   k_node_sum<G>   one thread per node: ordered sum of its hits -> far field
 // G = double (RTW_FP64) or float (RTW_MIXED, with FP64 path/phase/Jacobian).
@@ -487,15 +488,83 @@ __global__ void __launch_bounds__(256) k_trace_diag(const ParticleConst P, const
   }
 }
 
-// Node tables from the degree lists, workspace header and counters (once per
-// call).  With P1 != nullptr the call has one particle, whose metadata is
-// written here from the kernel arguments (no host upload).
-__global__ void k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg, double* th,
-                        double* ph, double* sth, double* cth, double* sph, double* cph, float* tf, unsigned* counter,
-                        WsHeader* hdr, WsHeader hv, ParticleConst* meta_P, long* meta_off, int* meta_out,
-                        ParticleConst P1, long items1, int one) {
+constexpr double D2R = 3.14159265358979323846 / 180.0;
+
+// Split a node-angle list (degrees, turned to radians as the node tables
+// are) into uniformly spaced runs, one block of 256 threads.  A "break" is an
+// index where the spacing changes; more than MAXSEG - 1 breaks leaves the
+// list to binary search, and so does a run whose nodes deviate from its
+// arithmetic model by more than 1e-10 of its step (the lookups allow 1e-9).
+__device__ void axis_segments(const double* deg, int n, AxisSeg* out) {
+  __shared__ int nbreak, bad;
+  __shared__ int brk[MAXSEG];
+  __shared__ AxisSeg sg;
+  auto v = [&](int i) { return deg[i] * D2R; };
+  if (threadIdx.x == 0) { nbreak = 0; bad = 0; }
+  __syncthreads();
+  for (int i = 1 + (int)threadIdx.x; i < n - 1; i += blockDim.x) {
+    const double d0 = v(i) - v(i - 1), d1 = v(i + 1) - v(i);
+    if (fabs(d1 - d0) > 1e-7 * fmax(fabs(d0), fabs(d1))) {
+      const int k = atomicAdd(&nbreak, 1);
+      if (k < MAXSEG) brk[k] = i;
+    }
+  }
+  __syncthreads();
+  const int nb = nbreak;
+  if (n < 2 || nb > MAXSEG - 1) {
+    if (threadIdx.x == 0) out->nseg = 0;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    for (int a = 1; a < nb; ++a) {  // sort the few break indices
+      int x = brk[a], b = a;
+      while (b > 0 && brk[b - 1] > x) { brk[b] = brk[b - 1]; --b; }
+      brk[b] = x;
+    }
+    int lo = 0;
+    for (int k = 0; k <= nb; ++k) {
+      const int hi = k < nb ? brk[k] : n - 1;
+      sg.start[k] = lo;
+      sg.end[k] = hi;
+      sg.v0[k] = v(lo);
+      sg.vend[k] = v(hi);
+      sg.step[k] = (v(hi) - v(lo)) / (double)(hi - lo);
+      sg.inv_step[k] = 1.0 / sg.step[k];
+      lo = hi;
+    }
+    sg.nseg = nb + 1;
+  }
+  __syncthreads();
+  for (int k = 0; k < sg.nseg; ++k)
+    for (int i = sg.start[k] + (int)threadIdx.x; i <= sg.end[k]; i += blockDim.x) {
+      const double model = sg.v0[k] + (double)(i - sg.start[k]) * sg.step[k];
+      if (!(fabs(v(i) - model) <= 1e-10 * sg.step[k])) bad = 1;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bad) sg.nseg = 0;
+    *out = sg;
+  }
+}
+
+// Once per call: node tables from the degree lists, workspace header,
+// counters and the first chunk's node counts (blocks 0 .. n_main - 1), and
+// the uniform runs of the two angle lists (blocks n_main and n_main + 1).
+// With one != 0 the call has one particle, whose metadata is written here
+// from the kernel arguments (no host upload).
+__global__ void __launch_bounds__(256) k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg,
+                                               double* th, double* ph, double* sth, double* cth, double* sph,
+                                               double* cph, float* tf, unsigned* counter, WsHeader* hdr, WsHeader hv,
+                                               ParticleConst* meta_P, long* meta_off, int* meta_out, ParticleConst P1,
+                                               long items1, int one, int* count0, long n_count0, int n_main,
+                                               AxisSeg* seg_t, AxisSeg* seg_p) {
+  if ((int)blockIdx.x >= n_main) {  // block-uniform
+    if ((int)blockIdx.x == n_main) axis_segments(theta_deg, n_theta, seg_t);
+    else axis_segments(phi_deg, n_phi, seg_p);
+    return;
+  }
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const double D2R = 3.14159265358979323846 / 180.0;
+  if (i < n_count0) count0[i] = 0;
   if (i < n_theta) {
     double t = theta_deg[i] * D2R;
     th[i] = t;
@@ -565,34 +634,79 @@ __global__ void k_chunk_reset(int* count, long n_nodes_chunk, unsigned* counter)
   if (i <= C_QUEUE_GEN) counter[i] = 0u;
 }
 
-// End of a chunk: fullest partition (overflow check), hit and FP64 totals.
-// On the fused path the partition fills count slots handed out in runs; the
-// chunk's hits are counted apart (and that count is cleared for the next).
-__global__ void __launch_bounds__(1024) k_pool_check(unsigned* counter, int fused) {
-  __shared__ unsigned mx[1024];
-  __shared__ unsigned long long sm[1024];
+// End of a chunk's counting, one block of 256 threads: fullest partition
+// (overflow check), hit and FP64 totals.  On the fused path the partition
+// fills count slots handed out in runs; the chunk's hits are counted apart
+// (and that count is cleared for the next chunk).
+__device__ void pool_check(unsigned* counter, int fused) {
+  __shared__ unsigned mx[256];
+  __shared__ unsigned long long sm[256];
+  const int t = (int)threadIdx.x;
   unsigned m = 0;
   unsigned long long sum = 0;
-  for (int i = threadIdx.x; i < NPART; i += blockDim.x) {
+  for (int i = t; i < NPART; i += 256) {
     m = max(m, counter[i]);
     sum += counter[i];
   }
-  mx[threadIdx.x] = m;
-  sm[threadIdx.x] = sum;
+  mx[t] = m;
+  sm[t] = sum;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + w]);
-      sm[threadIdx.x] += sm[threadIdx.x + w];
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      mx[t] = max(mx[t], mx[t + w]);
+      sm[t] += sm[t + w];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     atomicMax(&counter[C_NEED], mx[0]);
     atomicAdd((unsigned long long*)&counter[C_HITS], fused ? (unsigned long long)counter[C_FUSED_HITS] : sm[0]);
     counter[C_FUSED_HITS] = 0u;
     atomicAdd(&counter[C_FP64_TOTAL], counter[C_REDO]);
   }
+}
+
+// Node ranges of a chunk, second pass (after k_scan_local): each node's
+// exclusive prefix within its scan block plus the sum of the block sums
+// before that block, either scanned by k_scan_sums (direct == 0) or added up
+// here from the raw block sums (direct != 0: few scan blocks).  The grid's
+// last block closes the chunk's counters instead; the hit counts are final
+// once the rasterisers (or the fused kernel) have run, and what follows in
+// the chunk reads only the partition fills.
+__global__ void __launch_bounds__(256) k_scan_add(int* out, long n, const int* bsum, int direct, unsigned* counter,
+                                                  int fused) {
+  if (blockIdx.x == gridDim.x - 1) {  // block-uniform
+    pool_check(counter, fused);
+    return;
+  }
+  __shared__ int lds[4];
+  int add;
+  if (direct) {
+    int s = 0;
+    for (int j = (int)threadIdx.x; j < (int)blockIdx.x; j += 256) s += bsum[j];
+    block_excl_scan(s, &add, lds);
+  } else {
+    add = bsum[blockIdx.x];
+  }
+  const long base = (long)blockIdx.x * SCAN_BLOCK;
+  for (int j = threadIdx.x; j < SCAN_BLOCK; j += 256)
+    if (base + j < n) out[base + j] += add;
+}
+
+// Scan blocks up to which k_scan_add adds up the block sums itself (its work
+// grows with their square; beyond, k_scan_sums scans them first).
+constexpr long SCAN_DIRECT = 4096;
+
+// Node ranges of a chunk (exclusive scan of its node counts into the range
+// cursors) and the close of its counters: two or three launches.
+void launch_ranges(const int* count, int* cursor, long n_cnodes, int* bsum, unsigned* counter, int fused,
+                   hipStream_t st) {
+  const long nsb = (n_cnodes + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const int direct = nsb <= SCAN_DIRECT ? 1 : 0;
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, count, n_cnodes, cursor, bsum);
+  if (!direct) hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)(nsb + 1)), dim3(256), 0, st, cursor, n_cnodes, (const int*)bsum,
+                     direct, counter, fused);
 }
 
 constexpr int ROWS_CAP = 1 << 24;  // (triangle, row) items of large triangles
@@ -603,66 +717,6 @@ constexpr int STATIC_ROWS_CAP = 1 << 16;
 // Status word of rtw_farfield_static: whether the hit pool held every hit.
 __global__ void k_static_status(const unsigned* counter, int cap_part, int32_t* status) {
   if (threadIdx.x == 0 && blockIdx.x == 0) status[0] = (long)counter[C_NEED] > cap_part ? RTW_ERR_WORKSPACE : RTW_OK;
-}
-
-// Split each node-angle list into uniformly spaced runs (block 0: theta,
-// block 1: phi).  A "break" is an index where the spacing changes; more than
-// MAXSEG - 1 breaks leaves the list to binary search, and so does a run whose
-// nodes deviate from its arithmetic model by more than 1e-10 of its step
-// (the lookups allow 1e-9).
-__global__ void __launch_bounds__(256) k_axis_segments(const double* th, int n_t, const double* ph, int n_p,
-                                                       AxisSeg* seg_t, AxisSeg* seg_p) {
-  const double* v = blockIdx.x == 0 ? th : ph;
-  const int n = blockIdx.x == 0 ? n_t : n_p;
-  AxisSeg* out = blockIdx.x == 0 ? seg_t : seg_p;
-  __shared__ int nbreak, bad;
-  __shared__ int brk[MAXSEG];
-  __shared__ AxisSeg sg;
-  if (threadIdx.x == 0) { nbreak = 0; bad = 0; }
-  __syncthreads();
-  for (int i = 1 + (int)threadIdx.x; i < n - 1; i += blockDim.x) {
-    const double d0 = v[i] - v[i - 1], d1 = v[i + 1] - v[i];
-    if (fabs(d1 - d0) > 1e-7 * fmax(fabs(d0), fabs(d1))) {
-      const int k = atomicAdd(&nbreak, 1);
-      if (k < MAXSEG) brk[k] = i;
-    }
-  }
-  __syncthreads();
-  const int nb = nbreak;
-  if (n < 2 || nb > MAXSEG - 1) {
-    if (threadIdx.x == 0) out->nseg = 0;
-    return;
-  }
-  if (threadIdx.x == 0) {
-    for (int a = 1; a < nb; ++a) {  // sort the few break indices
-      int x = brk[a], b = a;
-      while (b > 0 && brk[b - 1] > x) { brk[b] = brk[b - 1]; --b; }
-      brk[b] = x;
-    }
-    int lo = 0;
-    for (int k = 0; k <= nb; ++k) {
-      const int hi = k < nb ? brk[k] : n - 1;
-      sg.start[k] = lo;
-      sg.end[k] = hi;
-      sg.v0[k] = v[lo];
-      sg.vend[k] = v[hi];
-      sg.step[k] = (v[hi] - v[lo]) / (double)(hi - lo);
-      sg.inv_step[k] = 1.0 / sg.step[k];
-      lo = hi;
-    }
-    sg.nseg = nb + 1;
-  }
-  __syncthreads();
-  for (int k = 0; k < sg.nseg; ++k)
-    for (int i = sg.start[k] + (int)threadIdx.x; i <= sg.end[k]; i += blockDim.x) {
-      const double model = sg.v0[k] + (double)(i - sg.start[k]) * sg.step[k];
-      if (!(fabs(v[i] - model) <= 1e-10 * sg.step[k])) bad = 1;
-    }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (bad) sg.nseg = 0;
-    *out = sg;
-  }
 }
 
 // Triangle keys (order slot, quad, half) are 32-bit: 2 n_ord (N-1)^2 < 2^31.
@@ -951,11 +1005,7 @@ int launch_fused(const Plan& pl, const Tuning& tu, int c0, int c1, const BatchDe
     hipLaunchKernelGGL(k_fused<true>, dim3((unsigned)grid_f), dim3(256), lds, st, B, ng, fp, counter + C_QUEUE_GEN,
                        steps, BOX_MARGIN); }
   { ProfScope ps("k_scan", st);
-  const long nsb = (n_cnodes + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  int* bsum = (int*)(ws + L.bsum);
-  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_cnodes, pool.cursor, bsum);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_cnodes, bsum); }
+  launch_ranges(pool.count, pool.cursor, n_cnodes, (int*)(ws + L.bsum), counter, 1, st); }
   { ProfScope ps("k_scatter", st);
   const long slots = (long)NPART * pool.cap_part;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, fp, pool); }
@@ -967,7 +1017,6 @@ int launch_fused(const Plan& pl, const Tuning& tu, int c0, int c1, const BatchDe
     hipLaunchKernelGGL(k_diffraction<float>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng,
                        n_nodes, S.n_pol, (float*)out);
   }
-  hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter, 1);
   return RTW_OK;
 }
 
@@ -1039,14 +1088,16 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   long* m_tile = moff + 2 * (n + 1);
   if (one_meta) { m_ray = moff; m_quad = moff + 2; m_tile = moff + 4; }
 
-  long setup_n = std::max<long>({(long)grid->n_theta, (long)grid->n_phi, (long)C_COUNT});
+  // the first chunk's node counts are cleared by k_setup, later chunks' by k_chunk_reset
+  const long n_count0 = (long)(pl.chunks.front().second - pl.chunks.front().first) * n_nodes;
+  const long setup_n = std::max<long>({(long)grid->n_theta, (long)grid->n_phi, (long)C_COUNT, n_count0});
+  const int n_main = (int)((setup_n + 255) / 256);
   { ProfScope ps("k_setup", st);
-  hipLaunchKernelGGL(k_setup, dim3((unsigned)((setup_n + 255) / 256)), dim3(256), 0, st, grid->n_theta,
-                     grid->theta_deg, grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth,
-                     (double*)ng.cth, (double*)ng.sph, (double*)ng.cph, tf, counter, (WsHeader*)(ws + L.hdr), hv, mP,
-                     moff, mout, pl.P[0], pl.tile_off[1], one_meta ? 1 : 0);
-  hipLaunchKernelGGL(k_axis_segments, dim3(2), dim3(256), 0, st, ng.th, ng.n_theta, ng.ph, ng.n_phi,
-                     (AxisSeg*)(ws + L.seg), (AxisSeg*)(ws + L.seg) + 1); }
+  hipLaunchKernelGGL(k_setup, dim3((unsigned)(n_main + 2)), dim3(256), 0, st, grid->n_theta, grid->theta_deg,
+                     grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth, (double*)ng.cth,
+                     (double*)ng.sph, (double*)ng.cph, tf, counter, (WsHeader*)(ws + L.hdr), hv, mP, moff, mout,
+                     pl.P[0], pl.tile_off[1], one_meta ? 1 : 0, pool.count, n_count0, n_main, (AxisSeg*)(ws + L.seg),
+                     (AxisSeg*)(ws + L.seg) + 1); }
 
   const bool fp64 = S.precision == RTW_FP64;
   const int cu = compute_units();
@@ -1068,8 +1119,9 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     const long quads = pl.quad_off[c1] - pl.quad_off[c0];
     const long items = pl.tile_off[c1] - pl.tile_off[c0];
     const long n_cnodes = (long)nc * n_nodes;
-    hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_cnodes, C_COUNT) + 255) / 256)), dim3(256),
-                       0, st, pool.count, n_cnodes, counter);
+    if (c0 != pl.chunks.front().first)
+      hipLaunchKernelGGL(k_chunk_reset, dim3((unsigned)((std::max<long>(n_cnodes, C_COUNT) + 255) / 256)),
+                         dim3(256), 0, st, pool.count, n_cnodes, counter);
     if constexpr (sizeof(G) == 4) {
       if (S.fused) {
         int rc = launch_fused(pl, tu, c0, c1, B, ng, pool, ws, L, counter, items, n_cnodes, n_nodes, out, ncontrib,
@@ -1099,11 +1151,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
     { ProfScope ps(fp64 ? "k_raster_rows_fp64" : "k_raster_rows_mixed", st);
     hipLaunchKernelGGL(k_raster_rows<G>, dim3(1024), dim3(256), 0, st, B, rec, ng, pool, BOX_MARGIN); }
     { ProfScope ps("k_scan", st);
-    const long nsb = (n_cnodes + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    int* bsum = (int*)(ws + L.bsum);
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, st, pool.count, n_cnodes, pool.cursor, bsum);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, (int)nsb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, pool.cursor, n_cnodes, bsum); }
+    launch_ranges(pool.count, pool.cursor, n_cnodes, (int*)(ws + L.bsum), counter, 0, st); }
     { ProfScope ps(fp64 ? "k_store_hits_fp64" : "k_store_hits_mixed", st);
     const long slots = (long)NPART * cap_part;
     hipLaunchKernelGGL(k_store_hits<G>, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, B, rec, ng, pool); }
@@ -1119,7 +1167,6 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
       hipLaunchKernelGGL(k_diffraction<G>, dim3((unsigned)((n_cnodes + 255) / 256)), dim3(256), 0, st, B, ng, n_nodes,
                          S.n_pol, (G*)out);
     }
-    hipLaunchKernelGGL(k_pool_check, dim3(1), dim3(1024), 0, st, counter, 0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RTW_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));

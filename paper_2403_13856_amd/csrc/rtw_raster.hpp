@@ -1384,12 +1384,6 @@ __global__ void __launch_bounds__(1024) k_scan_sums(int* bsum, int nb) {
     if (b0 + j < nb) { const int x = bsum[b0 + j]; bsum[b0 + j] = run; run += x; }
 }
 
-__global__ void __launch_bounds__(256) k_scan_add(int* out, long n, const int* bsum) {
-  const long base = (long)blockIdx.x * SCAN_BLOCK;
-  const int add = bsum[blockIdx.x];
-  for (int j = threadIdx.x; j < SCAN_BLOCK; j += blockDim.x)
-    if (base + j < n) out[base + j] += add;
-}
 
 // Sum of the fold pair at pool positions a, b (the same order slot): the
 // uniform Airy form of the two branches (focal-line counts n and n + 1) with
