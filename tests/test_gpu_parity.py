@@ -257,6 +257,31 @@ def test_uniform_axis_boxes_match_segment_tables(R):
             assert np.array_equal(F[:, :, it][:, :, :, ip], F_u)
 
 
+def test_node_ranges_of_a_large_grid_match_its_halves(R):
+    # The node ranges come from a scan of the node counts whose block sums are
+    # added up by the final pass itself up to 4096 scan blocks of 2048 nodes,
+    # and scanned by a kernel of their own beyond.  A 3601 x 3600 node grid
+    # (13 M nodes) takes the second way, each of its two theta halves the
+    # first; every node's sum depends only on its own hits, so the halves
+    # must reproduce the whole grid bitwise.
+    w = I.ellipsoid_mixed()
+    th = I.uniform_angles(0.0, 180.0, 0.05)
+    ph = I.uniform_angles(0.0, 359.9, 0.1)
+    assert th.size * ph.size > 4096 * 2048 and (th.size // 2) * ph.size <= 4096 * 2048
+    half = th.size // 2
+    gp = R.make_particle(w.semi_axes, w.euler_deg, w.m)
+    gi = R.make_incident(w.wavelength, 2)
+    go = R.make_opts(0, 3, 256, R.MIXED)
+    say(f"[node ranges] ellipsoid N=256 mixed on {th.size}x{ph.size} nodes and on its two theta halves")
+    F, nc, _ = _farfield_gpu(R, gp, gi, go, th, ph)
+    Fa, nca, _ = _farfield_gpu(R, gp, gi, go, th[:half], ph)
+    Fb, ncb, _ = _farfield_gpu(R, gp, gi, go, th[half:], ph)
+    say(f"   {int(nc.sum())} contributions on the whole grid")
+    assert nc.sum() > 0 and nca.sum() > 0 and ncb.sum() > 0
+    assert np.array_equal(nc[:half], nca) and np.array_equal(nc[half:], ncb)
+    assert np.array_equal(F[:, :, :half], Fa) and np.array_equal(F[:, :, half:], Fb)
+
+
 def test_three_run_axis_boxes_match_segment_tables(R):
     # An axis of three uniform runs (a refined band, as on the large
     # workload's theta grid) and the same axis with one off-grid node more
