@@ -186,6 +186,32 @@ def test_farfield_deterministic(R):
     assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
 
 
+def test_farfield_graph_replay_equals_eager(R):
+    # rtw_farfield queues kernels only (no allocation, copy, fill or sync), so
+    # a caller can capture it into a HIP graph; every replay, with eager work
+    # on the same workspace between replays, must give the eager result.
+    w = I.ellipsoid_mixed()
+    say("[graph] ellipsoid N=256 mixed: captured far field replayed three times")
+    for prec in (R.MIXED, R.FP64):
+        ff = R.FarField(R.make_particle(w.semi_axes, w.euler_deg, w.m), R.make_incident(w.wavelength, 2),
+                        R.make_opts(0, 3, 256, prec), w.theta_deg, w.phi_deg)
+        ref = torch.view_as_real(ff()).clone()
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            ff.launch(stream=s, with_counts=False)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            ff.out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(ff.field()), ref)
+            ff.launch(with_counts=False)  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(ff.field()), ref)
+
+
 def test_farfield_edge_cases(oracle, R):
     # a single quad (N = 2), one node row, a lone order, both precisions
     say("[edge] N=2, tiny grids, lone orders")
