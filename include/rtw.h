@@ -203,7 +203,10 @@ int rtw_farfield_workspace_size(const rtw_particle* part, const rtw_incident* in
  * (grid_n - 1)^2 >= 2^31 (triangle keys are 32-bit).
  * The per-node sum is taken in a fixed order (deterministic).  If the hit pool
  * in the workspace overflows, the result is incomplete and
- * rtw_farfield_status() reports RTW_ERR_WORKSPACE with the size needed. */
+ * rtw_farfield_status() reports RTW_ERR_WORKSPACE with the size needed.
+ * The call only queues kernels on hip_stream (no allocation, copy, fill or
+ * synchronisation while profiling is off), so it may be captured into a HIP
+ * graph; calls that share a workspace must not overlap. */
 int rtw_farfield(const rtw_particle* part, const rtw_incident* inc, const rtw_trace_opts* opts,
                  const rtw_grid* grid, void* out_field, int32_t* ncontrib, void* workspace,
                  size_t workspace_bytes, void* hip_stream);
