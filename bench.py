@@ -727,7 +727,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run would shard the ray grid "
-              f"by rows and reduce the node field once, which this build does not implement.", file=sys.stderr)
+              f"by rows and reduce the node field once; the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch

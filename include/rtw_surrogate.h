@@ -31,8 +31,8 @@
  *
  * Queries whose predicted sigma exceeds a threshold tau (either polarisation)
  * are answered by the RTW path instead (rtw_batch on the query's particle,
- * then the same cell average): the trace is both the fallback and the judge
- * of the surrogate's error.
+ * then the same cell average): the trace is both the fallback and the
+ * reference the surrogate's error is measured against.
  *
  * Device pointers are caller-owned except the handle's own parameters and
  * activation buffers, which rtw_surrogate_create allocates and
