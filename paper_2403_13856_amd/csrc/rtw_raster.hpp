@@ -19,7 +19,8 @@
 //
 // Hits are appended to a pool as descriptors with one atomic per wave per pass
 // (wave ballot) on one of NPART counters; each hit takes its rank among its
-// node's hits from the node's count atomic.  A scan of the counts gives each
+// node's hits from the node's count atomic (issued first, so that the two
+// round trips overlap).  A scan of the counts gives each
 // node's range, the hit store places every hit's contribution at its range
 // start plus its rank, and the per-node kernel sorts the node's hits by
 // triangle key and sums them in that order.  No floating-point atomics are
@@ -174,7 +175,7 @@ struct HitDesc {
   int nt;     // t | N << 1 | chunk particle << 16
   int itip;   // node row | node column << 16
   int node;   // node index within the chunk (particle-major)
-  int rank;   // place among the node's hits (taken with the node's count)
+  int rank;   // place among the node's hits (taken with the node's count, before the pool slot)
   G lam[3];
 };
 
@@ -861,6 +862,9 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
                                  long idx) {
   const HitDesc<G> d = pool.desc[idx];
   const long at = (long)pool.cursor[d.node] + d.rank;
+  // after an overflow the node counts include hits the pool could not keep,
+  // so a place can fall outside the pool (the result is reported incomplete)
+  if (at < 0 || at >= (long)NPART * pool.cap_part) return;
   const int it = d.itip & 0xffff, ip = (int)((unsigned)d.itip >> 16);
   const int t = d.nt & 1, N = (d.nt >> 1) & 0x7fff, part = (int)((unsigned)d.nt >> 16);
   // the triangle's rays from its key: order slot, quad, corner ray
@@ -1057,6 +1061,15 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
     }
     const unsigned long long mask = __ballot(hit);
     if (mask == 0ull) continue;  // wave-uniform
+    // the hit's rank among its node's hits first, so that the round trip of
+    // that atomic overlaps the partition atomic's; a hit that then finds its
+    // partition full stays counted (the pool has overflowed: the status call
+    // reports it, and the consumers of the counts keep to the pool)
+    int node = 0, rank = 0;
+    if (hit) {
+      node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
+      rank = atomicAdd(&pool.count[node], 1);
+    }
     const int pt = (part + 97 * flushes) % NPART;
     ++flushes;
     const int leader = __ffsll((long long)mask) - 1;
@@ -1070,8 +1083,8 @@ __device__ void raster_drain(const Records<G>& rec, const NodeGrid& ng, const Hi
       d.key = T.key;
       d.nt = (T.vid[1] == T.vid[0] + 1 ? 0 : 1) | (T.N << 1) | (T.part << 16);
       d.itip = it | (ip << 16);
-      d.node = (T.part * ng.n_theta + it) * ng.n_phi + ip;
-      d.rank = atomicAdd(&pool.count[d.node], 1);
+      d.node = node;
+      d.rank = rank;
       d.lam[0] = lam[0]; d.lam[1] = lam[1]; d.lam[2] = lam[2];
       pool.desc[(long)pt * pool.cap_part + pos] = d;
     }
@@ -1443,9 +1456,16 @@ __global__ void __launch_bounds__(256) k_node_sum(const BatchDev B, const HitPoo
   const int pl = (int)(gn / n_nodes);
   const int node = (int)(gn - (long)pl * n_nodes);
   const long ob = (long)B.out_index[pl];
-  const int cnt = pool.count[gn];
+  int cnt = pool.count[gn];
   // the range start (the fused path's scatter leaves the cursor at its end)
   const long s0 = (long)pool.cursor[gn] - (cursor_at_end ? cnt : 0);
+  {
+    // after an overflow the counts include hits the pool could not keep (the
+    // result is reported incomplete): the range is kept inside the pool
+    const long cap = (long)NPART * pool.cap_part;
+    if (s0 < 0 || s0 >= cap) cnt = 0;
+    else if (s0 + cnt > cap) cnt = (int)(cap - s0);
+  }
   int keys[NODE_SORT_MAX], idxs[NODE_SORT_MAX];
   const int w = n_pol * 4;
   G acc[8], inc[2] = {0, 0};
