@@ -91,6 +91,20 @@ __device__ __forceinline__ void sincos_red(double x, double* s, double* c) { sin
 // tan(pi / 12), atan a = pi / 6 + atan t with t = (a sqrt 3 - 1) / (a + sqrt 3),
 // so |t| <= tan(pi / 12) and the Taylor series of atan to t^11 leaves below
 // 2e-9; then the octant and the quadrant.  atan2(0, 0) = 0.
+// q / d for 0 <= q, 1 <= d, q + d < 2^31 and a quotient below 2^15 (grid
+// indices: ray or quad -> row, key offset -> order slot).  q and d rounded to
+// FP32, the hardware reciprocal (1 ulp) and the product put the estimate
+// within a few 2^-24 relative of q / d, i.e. within 2^-7 for such quotients,
+// so the truncated estimate is off by at most one and one correction step
+// makes it exact (checked with the reciprocal 2 ulp off either way).  It
+// replaces an integer division sequence several times as long.
+__device__ __forceinline__ int div_quot15(int q, int d) {
+  int r = (int)((float)q * __builtin_amdgcn_rcpf((float)d));
+  if (r * d > q) --r;
+  else if ((r + 1) * d <= q) ++r;
+  return r;
+}
+
 __device__ __forceinline__ float atan2_f32(float y, float x) {
   const float ax = fabsf(x), ay = fabsf(y);
   const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);

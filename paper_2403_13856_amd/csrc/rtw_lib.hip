@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256, (sizeof(G) == 8 || GEN) ? 2 : 3)
       if (id < last) {
         for (int o = 0; o < B.n_ord; ++o) rec.flags[rbase + o * NN + id] = 0;
         RecordSink<G> sink{rec, rbase, NN, id, P.k, P.amplif_limit, false, P.k * P.robs};
-        const int iy = (int)(id / P.N), ix = (int)(id - (long)iy * P.N);
+        const int iy = div_quot15((int)id, P.N), ix = (int)id - iy * P.N;
         trace_ray<G, GEN>(P, ix, iy, sink);
         redo = sink.need64;
       }

@@ -446,7 +446,7 @@ template <typename G>
 __device__ inline void tri_load(const Records<G>& rec, long rb, int N, long quad, int t, int key, int part,
                                 Tri<G>& T) {
   const int Nq = N - 1;
-  const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
+  const int iy = div_quot15((int)quad, Nq), ix = (int)quad - iy * Nq;
   const long v00 = (long)iy * N + ix;
   T.vid[0] = v00;
   T.vid[1] = t == 0 ? v00 + 1 : v00 + N + 1;
@@ -870,8 +870,8 @@ __device__ inline void store_hit(const BatchDev& B, const Records<G>& rec, const
   // the triangle's rays from its key: order slot, quad, corner ray
   const unsigned within = (unsigned)((long)(d.key >> 1) - (long)B.n_ord * (B.quad_off[part] - B.quad_base));
   const unsigned nq = (unsigned)(N - 1) * (unsigned)(N - 1);
-  const unsigned slot = within / nq, quad = within - slot * nq;
-  const long v00 = (long)quad + quad / (unsigned)(N - 1);
+  const unsigned slot = (unsigned)div_quot15((int)within, (int)nq), quad = within - slot * nq;
+  const long v00 = (long)quad + div_quot15((int)quad, N - 1);
   const long rb = (long)B.n_ord * (B.ray_off[part] - B.ray_base) + (long)slot * N * N;
   const long vid[3] = {v00, t == 0 ? v00 + 1 : v00 + N + 1, t == 0 ? v00 + N + 1 : v00 + N};
   const bool with_phase = pool.phi != nullptr;
@@ -1167,7 +1167,7 @@ __global__ void __launch_bounds__(256) k_raster(const BatchDev B, const Records<
     const int Nq = N - 1;
     const long NN = (long)N * N;
     const long rb = B.n_ord * roff + (long)slot * NN;
-    const int iy = (int)(quad / Nq), ix = (int)(quad - (long)iy * Nq);
+    const int iy = div_quot15((int)quad, Nq), ix = (int)quad - iy * Nq;
     const long v00 = (long)iy * N + ix;
     // flags and vertex angles are loaded together: one memory round trip per
     // block instead of two (the angles of an invalid quad are not used)
