@@ -150,6 +150,11 @@ SHAPES = [
     # 256^2 rays); these two keep 73% and 59% of the nodes compared.
     ("needle_40_8_8", (40.0, 8.0, 8.0), (25.0, 50.0, 15.0), 1.333, 160, 0.6),
     ("disc_30_30_12", (30.0, 30.0, 12.0), (10.0, 35.0, 70.0), 1.5, 256, 0.45),
+    # extreme relative indices on a tilted ellipsoid: m = 1.05 (critical angle
+    # 72 deg: total internal reflection on most internal legs) and m = 1.9
+    # (84% and 91% of the nodes compared)
+    ("ellipsoid_m1.05", (20.0, 16.0, 12.0), (40.0, 30.0, 20.0), 1.05, 192, 0.67),
+    ("ellipsoid_m1.9", (20.0, 16.0, 12.0), (40.0, 30.0, 20.0), 1.9, 192, 0.72),
 ]
 
 
