@@ -547,23 +547,24 @@ __device__ void axis_segments(const double* deg, int n, AxisSeg* out) {
   }
 }
 
-// Once per call: node tables from the degree lists, workspace header,
-// counters and the first chunk's node counts (blocks 0 .. n_main - 1), and
-// the uniform runs of the two angle lists (blocks n_main and n_main + 1).
+// Once per call: the uniform runs of the two angle lists (blocks 0 and 1,
+// first so that their serial part overlaps the rest), then node tables from
+// the degree lists, workspace header, counters and the first chunk's node
+// counts (the blocks after those).
 // With one != 0 the call has one particle, whose metadata is written here
 // from the kernel arguments (no host upload).
 __global__ void __launch_bounds__(256) k_setup(int n_theta, const double* theta_deg, int n_phi, const double* phi_deg,
                                                double* th, double* ph, double* sth, double* cth, double* sph,
                                                double* cph, float* tf, unsigned* counter, WsHeader* hdr, WsHeader hv,
                                                ParticleConst* meta_P, long* meta_off, int* meta_out, ParticleConst P1,
-                                               long items1, int one, int* count0, long n_count0, int n_main,
-                                               AxisSeg* seg_t, AxisSeg* seg_p) {
-  if ((int)blockIdx.x >= n_main) {  // block-uniform
-    if ((int)blockIdx.x == n_main) axis_segments(theta_deg, n_theta, seg_t);
+                                               long items1, int one, int* count0, long n_count0, AxisSeg* seg_t,
+                                               AxisSeg* seg_p) {
+  if (blockIdx.x < 2) {  // block-uniform
+    if (blockIdx.x == 0) axis_segments(theta_deg, n_theta, seg_t);
     else axis_segments(phi_deg, n_phi, seg_p);
     return;
   }
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long i = (long)(blockIdx.x - 2) * blockDim.x + threadIdx.x;
   if (i < n_count0) count0[i] = 0;
   if (i < n_theta) {
     double t = theta_deg[i] * D2R;
@@ -1096,7 +1097,7 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
   hipLaunchKernelGGL(k_setup, dim3((unsigned)(n_main + 2)), dim3(256), 0, st, grid->n_theta, grid->theta_deg,
                      grid->n_phi, grid->phi_deg, (double*)ng.th, (double*)ng.ph, (double*)ng.sth, (double*)ng.cth,
                      (double*)ng.sph, (double*)ng.cph, tf, counter, (WsHeader*)(ws + L.hdr), hv, mP, moff, mout,
-                     pl.P[0], pl.tile_off[1], one_meta ? 1 : 0, pool.count, n_count0, n_main, (AxisSeg*)(ws + L.seg),
+                     pl.P[0], pl.tile_off[1], one_meta ? 1 : 0, pool.count, n_count0, (AxisSeg*)(ws + L.seg),
                      (AxisSeg*)(ws + L.seg) + 1); }
 
   const bool fp64 = S.precision == RTW_FP64;
@@ -1142,8 +1143,9 @@ int launch_plan(const Plan& pl, const Tuning& tu, const rtw_grid* grid, void* ou
                          counter + C_QUEUE_GEN); }
     if (!fp64) {
       ProfScope ps("k_retrace64", st);
-      hipLaunchKernelGGL(k_retrace64, dim3((unsigned)std::min<long>(2048, (rays + 255) / 256)), dim3(256), 0, st, B,
-                         *reinterpret_cast<Records<float>*>(&rec));
+      // two waves per SIMD (its registers): the grid that fits at once strides over the list
+      hipLaunchKernelGGL(k_retrace64, dim3((unsigned)std::min<long>(2L * cu, (rays + 255) / 256)), dim3(256), 0, st,
+                         B, *reinterpret_cast<Records<float>*>(&rec));
     }
     { ProfScope ps(fp64 ? "k_raster_fp64" : "k_raster_mixed", st);
     hipLaunchKernelGGL(k_raster<G>, dim3((unsigned)((quads + 255) / 256), S.n_ord), dim3(256), 0, st, B, rec, ng,
